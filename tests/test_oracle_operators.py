@@ -1,0 +1,321 @@
+"""Pins of the oracle's residuals and loss terms against closed forms.
+
+Each check ties the discrete operators to something other than their own
+formula: exactness on polynomials, exact discrete solutions (constant and
+free-stream states), the order of consistency with the continuous PDE,
+conservation, and the special values the paper states.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import operators as ops
+from oracle import reference as ref
+
+DT = torch.float64
+
+
+def _centres(n, x0=0.0, x1=1.0):
+    return x0 + (np.arange(n) + 0.5) * (x1 - x0) / n
+
+
+# --------------------------------------------------------------------- Poisson
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+def test_poisson_exact_on_quadratics(ndim):
+    """u = prod x_a(1 - x_a) vanishes on the walls; the 3-point Laplacian and the
+    quadratic-extrapolation ghost are exact for it, so R = 0 in every cell."""
+    n = 8
+    x = _centres(n)
+    grids = np.meshgrid(*([x] * ndim), indexing="ij")
+    q = [g * (1 - g) for g in grids]
+    u = np.prod(q, axis=0)
+    lap = np.zeros_like(u)
+    for a in range(ndim):
+        term = -2.0 * np.ones_like(u)
+        for b in range(ndim):
+            if b != a:
+                term = term * q[b]
+        lap += term
+    spec = ops.Spec("poisson", (n,) * ndim, (1.0,) * ndim, 1, forcing={0: lap})
+    R = ops.poisson_residual(spec, torch.tensor(u))[0].numpy()
+    assert np.max(np.abs(R)) < 1e-11
+
+
+def test_poisson_manufactured_is_exact_minimum():
+    """f := A_h(u_ref) (Section 3.1): u_ref gives zero loss and zero gradient, and
+    the least-squares minimiser of the linear residual is u_ref."""
+    n = 8
+    spec = ops.Spec("poisson", (n, n), (1.0, 1.0), 1, weights={"pde": 1.0})
+    u_ref = ref.poisson_reference((n, n))
+    spec.forcing = {0: ref.poisson_forcing(spec, u_ref)}
+    terms, grads = ops.loss_and_grad(spec, [[u_ref]])
+    assert terms["pde"] < 1e-26
+    assert np.max(np.abs(grads[0][0])) < 1e-10
+    # dense linear map u -> A_h u (columns are residuals of unit vectors, f = 0)
+    s0 = ops.Spec("poisson", (n, n), (1.0, 1.0), 1)
+    cols = []
+    for k in range(n * n):
+        e = np.zeros(n * n)
+        e[k] = 1.0
+        cols.append(ops.poisson_residual(s0, torch.tensor(e.reshape(n, n)))[0].numpy().ravel())
+    A = np.stack(cols, 1)
+    sol = np.linalg.lstsq(A, spec.forcing[0].ravel(), rcond=None)[0]
+    np.testing.assert_allclose(sol, u_ref.ravel(), rtol=0, atol=1e-12)
+    assert u_ref.max() > 0.5           # the reference is not trivial
+
+
+# --------------------------------------------------------------------- Burgers
+def test_upwind_flux_picks_upwind_state():
+    """The flux is f(left) for positive face speed and f(right) for negative."""
+    a = torch.tensor([0.5, 1.0, -0.2, -1.0], dtype=DT)
+    b = torch.tensor([0.7, 0.1, -0.6, 0.4], dtype=DT)
+    F = ops._upwind_flux(a, b).numpy()
+    mean = 0.5 * (a + b).numpy()
+    expect = np.where(mean > 0, 0.5 * a.numpy() ** 2, 0.5 * b.numpy() ** 2)
+    np.testing.assert_allclose(F, expect, rtol=1e-15)
+
+
+def _burgers_spec(nt, nx, **kw):
+    return ops.Spec("burgers", (nt, nx), (1.0, 2.0), 1, **kw)
+
+
+def test_burgers_constant_state():
+    spec = _burgers_spec(8, 8, weights={"pde": 1.0, "reg": 1e-4})
+    u = torch.full((8, 8), 0.37, dtype=DT)
+    assert float(ops.loss_terms(spec, [u])["pde"]) == 0.0
+    assert float(ops.loss_terms(spec, [u])["reg"]) == 0.0
+
+
+def _burgers_consistency_error(n):
+    spec = _burgers_spec(n, n)
+    dt, dx = spec.h
+    t = np.arange(n)[:, None] * dt
+    x = _centres(n, -1.0, 1.0)[None, :]
+    u = 1.0 + 0.3 * np.sin(np.pi * x) + 0.2 * t           # positive: one upwind side
+    exact = 0.2 + u * 0.3 * np.pi * np.cos(np.pi * x)        # u_t + u u_x
+    R = ops.burgers_residual(spec, torch.tensor(u))[0].numpy()
+    return np.max(np.abs(R - exact[1:, 1:-1]))
+
+
+def test_burgers_first_order_consistency():
+    """The implicit upwind residual approximates u_t + u u_x to first order."""
+    e1, e2 = _burgers_consistency_error(32), _burgers_consistency_error(64)
+    assert e2 < e1 and 1.7 < e1 / e2 < 2.3
+
+
+def test_burgers_forward_reference():
+    """The generated reference has zero inner residual and conserves sum_i u_i
+    (zero flux through the walls)."""
+    n = 16
+    spec = _burgers_spec(n, n, weights={"pde": 1.0})
+    x = _centres(n, -1.0, 1.0)
+    u0 = 0.3 * np.sin(np.pi * x) - 0.2 * np.sin(2 * np.pi * x)
+    U = ref.burgers_forward(u0, n, *spec.h)
+    R = ops.burgers_residual(spec, torch.tensor(U))[0].numpy()
+    assert np.max(np.abs(R)) < 1e-10
+    sums = U.sum(1)
+    assert np.max(np.abs(sums - sums[0])) < 1e-12
+
+
+# ------------------------------------------------------------------------ heat
+def _heat_spec(nt, nx, T=0.02, **kw):
+    return ops.Spec("heat", (nt, nx), (T, 1.0), 1, **kw)
+
+
+def test_heat_constant_state_any_conductivity():
+    spec = _heat_spec(6, 8)
+    q = torch.tensor(np.random.default_rng(0).standard_normal(8))
+    u = torch.full((6, 8), -0.8, dtype=DT)
+    R = ops.heat_residual(spec, u, q)[0]
+    assert float(R.abs().max()) == 0.0
+
+
+def test_heat_wall_extrapolation_exact_for_quadratics():
+    """(15 u0 - 10 u1 + 3 u2) / 8 is the face value of any quadratic."""
+    n = 8
+    x = _centres(n)
+    u = np.tile(2.0 + 3.0 * x - 5.0 * x ** 2, (3, 1))
+    left, right = ops.heat_boundary(_heat_spec(3, n), torch.tensor(u))
+    np.testing.assert_allclose(left.numpy(), 2.0, rtol=1e-14)
+    np.testing.assert_allclose(right.numpy(), 2.0 + 3.0 - 5.0, rtol=1e-13)
+
+
+def _heat_consistency_error(n):
+    T = 0.5
+    spec = _heat_spec(n, n, T=T)
+    dt, dx = spec.h
+    t = np.arange(n)[:, None] * dt
+    x = _centres(n)[None, :]
+    kx = 1.0 + 0.5 * np.sin(2 * x)
+    q = ref.inverse_softplus(kx[0])
+    u = np.exp(-t) * np.cos(3 * x)
+    u_t = -u
+    u_x = -3 * np.exp(-t) * np.sin(3 * x)
+    u_xx = -9 * u
+    k_x = np.cos(2 * x)
+    exact = u_t - (k_x * u_x + kx * u_xx)
+    R = ops.heat_residual(spec, torch.tensor(u), torch.tensor(q))[0].numpy()
+    return np.max(np.abs(R - exact[1:, 1:-1]))
+
+
+def test_heat_consistency():
+    """Residual approximates u_t - (k u_x)_x (first order in t, second in x)."""
+    e1, e2 = _heat_consistency_error(32), _heat_consistency_error(64)
+    assert e2 < e1 and e1 / e2 > 1.7
+
+
+def test_heat_forward_reference_loss_is_noise():
+    """With the true conductivity and the forward solution, only the data noise remains."""
+    n = 16
+    x = _centres(n)
+    k = 1.0 + 0.5 * np.exp(-((x - 0.5) ** 2) / (2 * 0.1 ** 2))
+    spec = _heat_spec(n, n, weights={"pde": 1.0, "data": 1.0, "ic": 1.0, "bc": 1.0})
+    dt, dx = spec.h
+    u0 = ref.heat_ic(x)
+    U = ref.heat_forward(u0, k, n, dt, dx)
+    idx = np.array([20, 77, 130, 201])
+    noise = np.array([0.01, -0.02, 0.005, 0.0])
+    spec.meas = [(0, "data", idx, U.ravel()[idx] + noise, 1.0 / 4),
+                 (0, "ic", np.arange(n), u0, dx)]
+    q = ref.inverse_softplus(k)
+    terms = ops.loss_value(spec, [[U, q]])
+    assert abs(terms["data"] - np.sum(noise ** 2) / 4) < 1e-15
+    assert terms["pde"] < 1e-20 and terms["bc"] < 1e-24 and terms["ic"] == 0.0
+
+
+def test_softplus_stable_and_exact():
+    q = torch.tensor([-800.0, -30.0, -1.0, 0.0, 1e-8, 2.0, 40.0, 900.0], dtype=DT)
+    k = ops.softplus(q).numpy()
+    expect = [math.log1p(math.exp(v)) if v < 30 else v + math.log1p(math.exp(-v)) for v in q.tolist()]
+    np.testing.assert_allclose(k, expect, rtol=1e-15)
+    qq = q.clone().requires_grad_(True)
+    (g,) = torch.autograd.grad(ops.softplus(qq).sum(), qq)
+    np.testing.assert_allclose(g.numpy(), torch.sigmoid(q).numpy(), rtol=1e-15)
+
+
+# ------------------------------------------------------------------------ ns3d
+def _ns_spec(n, chi=None, op="ns3d_fixed", **kw):
+    params = {"re": 60.0, "diam": 0.4, "lam": 1.0, "chi_shift": 5.0, "tau_coef": 0.5}
+    return ops.Spec(op, (n, n, n), (1.0, 1.0, 1.0), 1, params=params, chi=chi, **kw)
+
+
+def test_ns3d_free_stream_is_exact():
+    """Uniform flow (1, 0, 0), p = 0, no body satisfies every equation and ghost rule."""
+    n = 6
+    z = np.zeros((n, n, n))
+    spec = _ns_spec(n, chi=z)
+    R = ops.ns3d_residual(spec, [torch.tensor(z + 1), torch.tensor(z), torch.tensor(z), torch.tensor(z)])
+    assert max(float(r.abs().max()) for r in R) == 0.0
+
+
+def test_ns3d_brinkman_inside_body():
+    """Inside the body (chi = 1) the momentum residual is the penalty lambda * u."""
+    n = 5
+    rng = np.random.default_rng(1)
+    f = [torch.tensor(rng.standard_normal((n, n, n))) for _ in range(4)]
+    spec = _ns_spec(n, chi=np.ones((n, n, n)))
+    R = ops.ns3d_residual(spec, f)
+    for c in range(3):
+        np.testing.assert_allclose(R[1 + c].numpy(), f[c].numpy(), rtol=1e-15)
+
+
+def test_ns3d_chi_transform_initial_value():
+    """chihat = 0 gives chi = 1 / (1 + e^5), the initial body fraction of Section 3.5."""
+    spec = _ns_spec(4, op="ns3d")
+    chi = ops.ns3d_chi(spec, torch.zeros(1, dtype=DT))
+    assert abs(float(chi) - 1.0 / (1.0 + math.exp(5.0))) < 1e-17
+
+
+def _smooth_fields(n):
+    x = _centres(n)
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    Xt, Yt, Zt = (torch.tensor(a, requires_grad=True) for a in (X, Y, Z))
+    u = 1.0 + 0.3 * torch.sin(2 * Xt) * torch.cos(Yt) + 0.1 * Zt
+    v = 0.2 * torch.cos(Xt + Zt) * torch.sin(2 * Yt)
+    w = 0.1 * torch.sin(Xt * Yt + Zt)
+    p = 0.5 * torch.cos(Xt) * torch.sin(Zt) + 0.2 * Yt ** 2
+    return (Xt, Yt, Zt), (u, v, w, p)
+
+
+def _derivs(fn, coords):
+    g = torch.autograd.grad(fn.sum(), coords, create_graph=True)
+    h = []
+    for a in range(3):
+        if g[a].requires_grad:
+            ha = torch.autograd.grad(g[a].sum(), coords[a], retain_graph=True, allow_unused=True)[0]
+        else:
+            ha = None
+        h.append(torch.zeros_like(coords[a]) if ha is None else ha)
+    return [x.detach().numpy() for x in g], [x.detach().numpy() for x in h]
+
+
+def _ns_consistency_error(n, nu=0.4 / 60.0, tau=0.5):
+    coords, (u, v, w, p) = _smooth_fields(n)
+    du, hu = _derivs(u, coords)
+    dv, hv = _derivs(v, coords)
+    dw, hw = _derivs(w, coords)
+    dp, hp = _derivs(p, coords)
+    U = [x.detach().numpy() for x in (u, v, w)]
+    h = 1.0 / n
+    cont = du[0] + dv[1] + dw[2] - tau * h * sum(hp)
+    mom = []
+    for D, H, comp in ((du, hu, 0), (dv, hv, 1), (dw, hw, 2)):
+        conv = U[0] * D[0] + U[1] * D[1] + U[2] * D[2]
+        mom.append(conv + dp[comp] - nu * sum(H))
+    spec = _ns_spec(n, chi=np.zeros((n, n, n)))
+    R = ops.ns3d_residual(spec, [torch.tensor(x.detach().numpy()) for x in (u, v, w, p)])
+    inner = (slice(1, -1),) * 3
+    errs = [np.max(np.abs(R[0].numpy() - cont)[inner])]
+    errs += [np.max(np.abs(R[1 + c].numpy() - mom[c])[inner]) for c in range(3)]
+    return np.array(errs)
+
+
+def test_ns3d_second_order_consistency():
+    """Interior residuals approximate the PDE (with the h-scaled pressure
+    stabilisation) to second order: central differences."""
+    e1, e2 = _ns_consistency_error(12), _ns_consistency_error(24)
+    assert np.all(e1 / e2 > 3.3), e1 / e2
+
+
+def test_ns3d_inlet_ghost_linear_profile():
+    """u = 1 + a x has face value 1 at the inlet: the inlet cells see the exact
+    derivative a and a zero Laplacian."""
+    n, a = 6, 0.7
+    x = _centres(n)
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    z = np.zeros_like(X)
+    spec = _ns_spec(n, chi=z)
+    u = 1.0 + a * X
+    R = ops.ns3d_residual(spec, [torch.tensor(u), torch.tensor(z), torch.tensor(z), torch.tensor(z)])
+    np.testing.assert_allclose(R[0].numpy()[:, :, 0], a, rtol=1e-13)
+    np.testing.assert_allclose(R[1].numpy()[:, :, 0], u[:, :, 0] * a, rtol=1e-13)
+
+
+# ---------------------------------------------------------------------- cavity
+def test_cavity_lid_and_walls():
+    """u = y has value 0 on the bottom wall and 1 on the lid: every row sees the
+    exact derivative du/dy = 1 through the ghosts and a zero Laplacian."""
+    n = 8
+    y = _centres(n)
+    Y = np.tile(y[:, None], (1, n))
+    z = np.zeros((n, n))
+    spec = ops.Spec("cavity", (n, n), (1.0, 1.0), 1, params={"re": 100.0, "tau_coef": 0.5})
+    R = ops.cavity_residual(spec, [torch.tensor(Y), torch.tensor(z), torch.tensor(z)])
+    # momentum_u = u u_x + v u_y + p_x - lap u / Re = 0 everywhere except x walls
+    # (u = y does not vanish on the side walls; their ghosts add a Laplacian)
+    assert float(R[1][:, 1:-1].abs().max()) < 1e-12
+    np.testing.assert_allclose(R[0].numpy()[:, 1:-1], 0.0, atol=1e-12)
+
+
+def test_cavity_pressure_gauge_invariance():
+    """p enters only through differences: the loss is invariant under p -> p + c."""
+    n = 8
+    rng = np.random.default_rng(3)
+    f = [rng.standard_normal((n, n)) for _ in range(3)]
+    spec = ops.Spec("cavity", (n, n), (1.0, 1.0), 1, params={"re": 400.0, "tau_coef": 0.5},
+                    weights={"pde": 1.0})
+    a = ops.loss_value(spec, [f])["pde"]
+    b = ops.loss_value(spec, [[f[0], f[1], f[2] + 3.25]])["pde"]
+    assert abs(a - b) <= 1e-13 * a
