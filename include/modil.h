@@ -1,0 +1,249 @@
+/*
+ * modil.h -- C ABI of the multiresolution ODIL (mODIL) iteration on gfx950.
+ *
+ * The method (Karnakov, Litvinov & Koumoutsakos, arXiv 2303.04679) solves a
+ * PDE-constrained reconstruction problem by minimising a discrete loss
+ * (Section 2.1): squared residuals of the discretised equations on the inner
+ * points, squared misfits at measured points, and regularisation / initial /
+ * boundary terms.  The unknown fields are represented by the multigrid
+ * decomposition u = M_L(u_1..u_L) = u_1 + T_1(u_2 + T_2(... + T_{L-1} u_L))
+ * (Section 2.2, Horner form), with T the cell-based linear interpolation whose
+ * 1-D matrices the paper prints.  One optimiser iteration prolongs all
+ * levels, evaluates residuals and the loss, forms the exact adjoint (the
+ * transposed stencils, then M_L^T back to every level) and applies Adam to
+ * every level.
+ *
+ * Conventions
+ *   - Every pointer is a device pointer unless its name ends in _host.
+ *   - The caller owns all device memory (parameter packs, gradients, Adam
+ *     moments, the workspace).  The library keeps non-owning pointers and
+ *     performs no device allocation.  All work is enqueued on the stream
+ *     given at creation (or by modil_set_stream) and is asynchronous unless a
+ *     function says otherwise.  A context is not thread safe.
+ *   - No C++ exception crosses this interface.  Every function returns a
+ *     MODIL_* status; on failure modil_last_error(ctx) (or
+ *     modil_last_error(NULL) for failures without a context) describes it.
+ *   - Floating-point arrays have the problem's dtype (float or double);
+ *     loss terms are always double.
+ *
+ * Parameter pack layout (one flat array of the problem dtype)
+ *   [level][instance][field][slowest axis]...[fastest axis]
+ *   Levels run from the finest (l = 0) to the coarsest; level l has
+ *   dims[a] / 2^l cells along every axis the field spans.  modil_layout()
+ *   returns every offset.  Gradient packs and the Adam moments m, v use the
+ *   same layout, so Adam is one flat sweep.
+ *
+ * Fine-field layout (modil_prolong / modil_restrict_adjoint)
+ *   [instance][field][cells of that field on the finest grid].
+ */
+#ifndef MODIL_H
+#define MODIL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MODIL_ABI_VERSION 1
+
+/* ---- status codes ---------------------------------------------------- */
+#define MODIL_OK 0
+#define MODIL_ERR_INVALID_ARG (-1) /* null pointer, bad enum, bad value   */
+#define MODIL_ERR_SHAPE (-2)       /* grid / level / index out of range   */
+#define MODIL_ERR_DTYPE (-3)       /* unsupported dtype or centering      */
+#define MODIL_ERR_HIP (-4)         /* HIP runtime error (message has it)  */
+#define MODIL_ERR_NONFINITE (-5)   /* a loss term became NaN or Inf       */
+#define MODIL_ERR_STATE (-6)       /* call out of order / missing input   */
+
+/* ---- enumerations ---------------------------------------------------- */
+#define MODIL_F32 0
+#define MODIL_F64 1
+
+#define MODIL_CELL 0 /* values at cell centres (the only layout built)   */
+#define MODIL_NODE 1 /* values at grid nodes: reserved, rejected         */
+
+/* Residual operators (the discretised PDEs of Sections 3.1-3.5).
+ *   POISSON   d = 1,2,3; Laplacian u = f, Dirichlet u = 0 by quadratic
+ *             extrapolation (Section 3.1).  1 field, 1 equation.
+ *   BURGERS   space-time [t][x]; implicit first-order upwind
+ *             finite-volume residual on inner points (Section 3.2) plus
+ *             w_reg * (gradient-squared smoothing in x and t).  1 field.
+ *   HEAT_KX   space-time [t][x]; implicit heat residual with conductivity
+ *             k(x) = softplus(q(x)) (Section 3.4 scheme with k depending on
+ *             x), plus w_bc * wall terms.  Fields: u [t][x], q [x].
+ *   NS3D      steady Navier-Stokes with Brinkman penalisation in a channel
+ *             [z][y][x] (Section 3.5): fields u, v, w, p, chihat with
+ *             chi = sigmoid(chihat - chi_shift); with MODIL_FLAG_CHI_FIXED
+ *             the fields are u, v, w, p and chi is a given array.
+ *   CAVITY    steady 2-D Navier-Stokes, lid-driven cavity [y][x]
+ *             (Section 3.3): fields u, v, p.                              */
+#define MODIL_OP_POISSON 0
+#define MODIL_OP_BURGERS 1
+#define MODIL_OP_HEAT_KX 2
+#define MODIL_OP_NS3D 3
+#define MODIL_OP_CAVITY 4
+
+#define MODIL_FLAG_CHI_FIXED 1
+
+/* Loss terms, in the order of every terms array. */
+#define MODIL_TERM_PDE 0
+#define MODIL_TERM_DATA 1
+#define MODIL_TERM_REG 2
+#define MODIL_TERM_IC 3
+#define MODIL_TERM_BC 4
+#define MODIL_N_TERMS 5
+
+/* Device arrays attached with modil_set_field. */
+#define MODIL_FIELD_FORCING0 0 /* forcing of equation 0..3 (fine grid,  */
+#define MODIL_FIELD_FORCING1 1 /* [instance][cells]); subtracted from   */
+#define MODIL_FIELD_FORCING2 2 /* the residual of that equation         */
+#define MODIL_FIELD_FORCING3 3
+#define MODIL_FIELD_CHI 4      /* fixed body fraction, [instance][cells] */
+
+/* Per-instance scalars (modil_set_instance_scalar). */
+#define MODIL_SCALAR_RE 0
+
+#define MODIL_MAX_LEVELS 8
+#define MODIL_MAX_FIELDS 5
+
+/* ---- problem description ---------------------------------------------
+ * dims / lengths list the grid axes slowest first (ndim entries used):
+ *   POISSON [z][y][x] (last ndim), BURGERS/HEAT [t][x], NS3D [z][y][x],
+ *   CAVITY [y][x].  For space-time grids lengths[0] is the time horizon.
+ * Validation: ndim matches the operator, dims[a] divisible by
+ * 2^(n_levels-1) with at least 2 coarsest cells per axis (cell-based
+ * extrapolation needs two), lengths > 0, batch >= 1, 1 <= n_levels <= 8.  */
+typedef struct {
+  int32_t ndim;
+  int32_t dims[3];
+  double lengths[3];
+  int32_t n_levels;
+  int32_t centering; /* MODIL_CELL */
+  int32_t dtype;     /* MODIL_F32 / MODIL_F64 */
+  int32_t op;        /* MODIL_OP_* */
+  int32_t flags;     /* MODIL_FLAG_* */
+  int32_t batch;     /* independent instances of the same shape */
+  int32_t max_meas;  /* capacity: measurement entries over all lists */
+  double re;         /* Reynolds number (default for every instance) */
+  double diam;       /* characteristic length D (viscosity D / Re) */
+  double lambda_;    /* Brinkman penalisation coefficient */
+  double chi_shift;  /* chi = sigmoid(chihat - chi_shift) */
+  double tau_coef;   /* pressure stabilisation: tau_a = tau_coef * h_a */
+  double u_ref;      /* inlet / lid velocity */
+  double w_pde;      /* weight of the integrated squared residuals */
+  double w_reg;      /* weight of the smoothing terms (BURGERS) */
+  double w_bc;       /* weight of the wall terms (HEAT_KX) */
+} modil_problem;
+
+typedef struct {
+  int32_t n_fields;
+  int32_t n_levels;
+  int64_t total;                                  /* elements of one pack  */
+  int64_t level_offset[MODIL_MAX_LEVELS];         /* start of level l      */
+  int64_t level_stride[MODIL_MAX_LEVELS];         /* elements per instance */
+  int64_t field_offset[MODIL_MAX_LEVELS][MODIL_MAX_FIELDS]; /* in instance */
+  int32_t field_dims[MODIL_MAX_LEVELS][MODIL_MAX_FIELDS][3]; /* z,y,x, 1s  */
+  int64_t fine_total;      /* elements of one fine-field array (all inst.) */
+  int64_t fine_cells;      /* cells of the finest grid (one instance)      */
+  size_t workspace_bytes;  /* device workspace modil_create needs          */
+} modil_pack_layout;
+
+typedef struct {
+  double lr, beta1, beta2, eps;
+} modil_adam_hp;
+
+typedef struct modil_ctx modil_ctx;
+
+/* ---- version and errors ---------------------------------------------- */
+int modil_abi_version(void);
+const char *modil_status_str(int status);
+/* Message of the last failure on ctx (NULL: last failure of a call that
+ * had no context, e.g. modil_layout / modil_create). Never NULL. */
+const char *modil_last_error(const modil_ctx *ctx);
+
+/* ---- layout and lifetime ----------------------------------------------
+ * modil_layout validates the problem and fills the pack layout and the
+ * workspace size.  Host only; needs no GPU.
+ * modil_create validates again, binds the caller's workspace (device, at
+ * least layout.workspace_bytes, 256-byte aligned) and the stream
+ * (hipStream_t, NULL = default stream) and the current HIP device.
+ * modil_destroy releases host-side state only (the caller frees memory).  */
+int modil_layout(const modil_problem *problem, modil_pack_layout *out);
+int modil_create(const modil_problem *problem, void *workspace, size_t workspace_bytes,
+                 void *hip_stream, modil_ctx **out);
+int modil_destroy(modil_ctx *ctx);
+int modil_set_stream(modil_ctx *ctx, void *hip_stream);
+
+/* ---- problem data -------------------------------------------------------
+ * Measurements {(x_k, u_k)} (Sections 3.2, 3.4, 3.5): a list of n cells of
+ * one field of one instance, given as flat C-order indices into that
+ * field's finest grid, with values; the loss gains
+ *     weight * sum_k (u(cell_k) - value_k)^2
+ * in term `term` (MODIL_TERM_DATA, or MODIL_TERM_IC for an initial
+ * condition).  Host arrays are copied (synchronously) into the workspace;
+ * values are kept in double.  Indices must be in range and unique within
+ * the list (MODIL_ERR_SHAPE / MODIL_ERR_INVALID_ARG), the total over all
+ * lists must not exceed max_meas.  Lists accumulate until
+ * modil_clear_measurements.                                              */
+int modil_set_measurements(modil_ctx *ctx, int32_t instance, int32_t field, int32_t term,
+                           int32_t n, const int32_t *cell_idx_host,
+                           const double *values_host, double weight);
+int modil_clear_measurements(modil_ctx *ctx);
+
+/* Attach (or detach with NULL) a fine-grid device array of the problem dtype,
+ * layout [instance][cells]: forcing subtracted from residual equation e
+ * (manufactured solutions, Section 3.1), or the fixed body fraction chi of
+ * NS3D with MODIL_FLAG_CHI_FIXED.  The array must stay valid while used. */
+int modil_set_field(modil_ctx *ctx, int32_t which, const void *dev_ptr);
+
+/* Per-instance scalar (MODIL_SCALAR_RE): Reynolds number of one instance. */
+int modil_set_instance_scalar(modil_ctx *ctx, int32_t instance, int32_t which, double value);
+
+/* ---- the iteration -------------------------------------------------------
+ * modil_prolong: fine = M_L(theta) for every field (Section 2.2).
+ * modil_restrict_adjoint: grad = M_L^T fine, the exact transpose.
+ * modil_loss: terms[instance][MODIL_N_TERMS] (double, device) of the loss
+ *   at theta.
+ * modil_loss_grad: terms and grad = dL/dtheta on every level (exact
+ *   adjoint: transposed stencils, then M_L^T).  Nothing of the fine field
+ *   is kept between calls.
+ * modil_adam: elementwise Adam over the whole pack (Kingma & Ba, cited in
+ *   Section 2.1): m <- b1 m + (1-b1) g; v <- b2 v + (1-b2) g^2;
+ *   theta_out <- theta_in - lr/(1-b1^t) * m / (sqrt(v/(1-b2^t)) + eps).
+ *   step t >= 1.  theta_out may equal theta_in.
+ * modil_step: one full iteration -- loss terms at theta_in (written to terms
+ *   if not NULL), gradient, and Adam into theta_out.  theta_out must differ
+ *   from theta_in (tiles read neighbours of theta_in while theta_out is
+ *   written) -> MODIL_ERR_INVALID_ARG.
+ * modil_residual_metric: r[instance] = RMS over cells and PDE equations of
+ *   the cell-integrated residual, sqrt(sum (V R)^2 / (n_eq * n_cells)),
+ *   evaluated in double from the PDE term.                               */
+int modil_prolong(modil_ctx *ctx, const void *theta_pack, void *fine_out);
+int modil_restrict_adjoint(modil_ctx *ctx, const void *fine_in, void *grad_pack_out);
+int modil_loss(modil_ctx *ctx, const void *theta_pack, double *terms);
+int modil_loss_grad(modil_ctx *ctx, const void *theta_pack, void *grad_pack, double *terms);
+int modil_adam(modil_ctx *ctx, const void *theta_in, void *theta_out, void *m, void *v,
+               const void *grad, const modil_adam_hp *hp, int64_t step);
+int modil_step(modil_ctx *ctx, const void *theta_in, void *theta_out, void *m, void *v,
+               const modil_adam_hp *hp, int64_t step, double *terms);
+int modil_residual_metric(modil_ctx *ctx, const void *theta_pack, double *r);
+
+/* ---- health and timing ---------------------------------------------------
+ * modil_check: synchronises the stream; returns MODIL_ERR_NONFINITE if a
+ * loss term computed since the last check was NaN or Inf (and clears the
+ * flag), MODIL_ERR_HIP on an asynchronous runtime error, else MODIL_OK.
+ * modil_profile: enable (1) / disable (0) HIP-event timing of every kernel
+ * launch class; modil_profile_read returns the accumulated milliseconds and
+ * launch count of one class (synchronises), then resets it.
+ * Classes: 0 fine-level kernel, 1 Horner (coarse prolongation),
+ * 2 restriction, 3 Adam, 4 reductions / data terms.                      */
+int modil_check(modil_ctx *ctx);
+int modil_profile(modil_ctx *ctx, int32_t enable);
+int modil_profile_read(modil_ctx *ctx, int32_t kernel_class, double *total_ms, int64_t *count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MODIL_H */

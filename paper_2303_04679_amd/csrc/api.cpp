@@ -1,0 +1,646 @@
+// C ABI of libmodil: validation, pack layout, workspace carve-up and the
+// launch sequence of one mODIL iteration.  No exception crosses the ABI and
+// no device memory is allocated here: the caller provides the workspace.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace modil;
+
+namespace {
+
+thread_local std::string g_last_error = "no error";
+
+int fail_global(int status, const std::string &msg) {
+  g_last_error = msg;
+  return status;
+}
+
+int fail(modil_ctx *c, int status, const std::string &msg) {
+  if (c) c->err = msg;
+  g_last_error = msg;
+  return status;
+}
+
+int hip_fail(modil_ctx *c, hipError_t e, const char *where) {
+  return fail(c, MODIL_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_OR_RETURN(ctx, expr, where)              \
+  do {                                              \
+    hipError_t e_ = (expr);                         \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, where); \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+size_t dtype_size(const modil_problem &p) { return p.dtype == MODIL_F64 ? 8 : 4; }
+
+int expected_ndim(int op) {
+  switch (op) {
+    case MODIL_OP_BURGERS:
+    case MODIL_OP_HEAT_KX:
+    case MODIL_OP_CAVITY:
+      return 2;
+    case MODIL_OP_NS3D:
+      return 3;
+    default:
+      return 0;
+  }
+}
+
+int validate(const modil_problem *p, std::string &msg) {
+  if (!p) { msg = "problem is NULL"; return MODIL_ERR_INVALID_ARG; }
+  if (p->op < MODIL_OP_POISSON || p->op > MODIL_OP_CAVITY) {
+    msg = "unknown operator " + std::to_string(p->op);
+    return MODIL_ERR_INVALID_ARG;
+  }
+  if (p->dtype != MODIL_F32 && p->dtype != MODIL_F64) {
+    msg = "dtype must be MODIL_F32 or MODIL_F64";
+    return MODIL_ERR_DTYPE;
+  }
+  if (p->centering != MODIL_CELL) {
+    msg = "only cell-based centering is implemented";
+    return MODIL_ERR_DTYPE;
+  }
+  const int want = expected_ndim(p->op);
+  if (p->op == MODIL_OP_POISSON ? (p->ndim < 1 || p->ndim > 3) : p->ndim != want) {
+    msg = "ndim " + std::to_string(p->ndim) + " does not match the operator";
+    return MODIL_ERR_SHAPE;
+  }
+  if (p->n_levels < 1 || p->n_levels > MODIL_MAX_LEVELS) {
+    msg = "n_levels must be in 1..8";
+    return MODIL_ERR_SHAPE;
+  }
+  for (int a = 0; a < p->ndim; ++a) {
+    const int n = p->dims[a];
+    const int q = 1 << (p->n_levels - 1);
+    if (n < 4 || n % q != 0 || n / q < 2) {
+      msg = "dims[" + std::to_string(a) + "] = " + std::to_string(n) +
+            " must be >= 4 and a multiple of 2^(n_levels-1) with >= 2 coarsest cells";
+      return MODIL_ERR_SHAPE;
+    }
+    if (!(p->lengths[a] > 0.0) || !std::isfinite(p->lengths[a])) {
+      msg = "lengths must be positive";
+      return MODIL_ERR_INVALID_ARG;
+    }
+  }
+  long cells = 1;
+  for (int a = 0; a < p->ndim; ++a) cells *= p->dims[a];
+  if (cells > (1L << 31) - 1) {
+    msg = "grid too large for 32-bit measurement indices";
+    return MODIL_ERR_SHAPE;
+  }
+  if (p->batch < 1 || p->batch > 65535) {
+    msg = "batch must be in 1..65535";
+    return MODIL_ERR_INVALID_ARG;
+  }
+  if (p->max_meas < 0) {
+    msg = "max_meas must be >= 0";
+    return MODIL_ERR_INVALID_ARG;
+  }
+  if ((p->op == MODIL_OP_NS3D || p->op == MODIL_OP_CAVITY) && !(p->re > 0.0)) {
+    msg = "re must be positive";
+    return MODIL_ERR_INVALID_ARG;
+  }
+  if ((p->flags & MODIL_FLAG_CHI_FIXED) && p->op != MODIL_OP_NS3D) {
+    msg = "MODIL_FLAG_CHI_FIXED applies to MODIL_OP_NS3D only";
+    return MODIL_ERR_INVALID_ARG;
+  }
+  if (p->flags & ~MODIL_FLAG_CHI_FIXED) {
+    msg = "unknown flags";
+    return MODIL_ERR_INVALID_ARG;
+  }
+  return MODIL_OK;
+}
+
+struct Carve {
+  size_t w, g, gq, partials, terms, flag, m_idx, m_field, m_term, m_ptr, m_val, m_w, inst_re, end;
+  long n_fine_blocks, n_data_blocks;
+};
+
+Carve carve(const modil_problem &p, const modil_pack_layout &L) {
+  Carve c{};
+  const size_t ts = dtype_size(p);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align256(off + bytes);
+    return at;
+  };
+  c.n_fine_blocks = (long)((L.fine_cells + kBlock - 1) / kBlock);
+  c.n_data_blocks = std::max<long>(1, (p.max_meas + kBlock - 1) / kBlock);
+  const long nl = p.n_levels;
+  c.w = take(nl >= 2 ? (size_t)L.level_offset[nl - 1] * ts : 0);
+  c.g = take((size_t)L.total * ts);
+  bool xonly = false;
+  for (int f = 0; f < L.n_fields; ++f) xonly |= field_is_x_only(p, f);
+  c.gq = take(xonly ? (size_t)p.batch * L.fine_cells * ts : 0);
+  c.partials = take((size_t)p.batch * (c.n_fine_blocks + c.n_data_blocks) * kTerms * 8);
+  c.terms = take((size_t)p.batch * kTerms * 8);
+  c.flag = take(4);
+  const size_t mm = (size_t)std::max(p.max_meas, 1);
+  c.m_idx = take(mm * 4);
+  c.m_field = take(mm * 4);
+  c.m_term = take(mm * 4);
+  c.m_ptr = take(((size_t)p.batch + 1) * 4);
+  c.m_val = take(mm * 8);
+  c.m_w = take(mm * 8);
+  c.inst_re = take((size_t)p.batch * 8);
+  c.end = off;
+  return c;
+}
+
+void fill_layout(const modil_problem &p, modil_pack_layout &L) {
+  std::memset(&L, 0, sizeof(L));
+  L.n_fields = op_fields(p);
+  L.n_levels = p.n_levels;
+  long off = 0;
+  for (int l = 0; l < p.n_levels; ++l) {
+    long stride = 0;
+    for (int f = 0; f < L.n_fields; ++f) {
+      const FieldGeom g = field_geom(p, l, f);
+      L.field_offset[l][f] = stride;
+      for (int a = 0; a < 3; ++a) L.field_dims[l][f][a] = g.n[a];
+      stride += g.size;
+    }
+    L.level_stride[l] = stride;
+    L.level_offset[l] = off;
+    off += stride * p.batch;
+  }
+  L.total = off;
+  L.fine_cells = 1;
+  for (int a = 0; a < p.ndim; ++a) L.fine_cells *= p.dims[a];
+  L.fine_total = L.level_stride[0] * p.batch;
+  L.workspace_bytes = carve(p, L).end;
+}
+
+// RAII timing of one launch class with HIP events (only when profiling).
+struct Timed {
+  modil_ctx *c;
+  EventPair ev{};
+  bool on;
+  Timed(modil_ctx *ctx, int cls) : c(ctx), on(ctx->profiling), cls_(cls) {
+    if (!on) return;
+    ProfileClass &pc = c->prof[cls_];
+    if (!pc.pool.empty()) {
+      ev = pc.pool.back();
+      pc.pool.pop_back();
+    } else {
+      (void)hipEventCreate(&ev.a);
+      (void)hipEventCreate(&ev.b);
+    }
+    (void)hipEventRecord(ev.a, c->stream);
+  }
+  ~Timed() {
+    if (!on) return;
+    (void)hipEventRecord(ev.b, c->stream);
+    c->prof[cls_].pending.push_back(ev);
+  }
+  int cls_;
+};
+
+int upload_measurements(modil_ctx *c) {
+  std::vector<Meas> m = c->meas;
+  std::stable_sort(m.begin(), m.end(), [](const Meas &a, const Meas &b) {
+    if (a.inst != b.inst) return a.inst < b.inst;
+    if (a.field != b.field) return a.field < b.field;
+    if (a.idx != b.idx) return a.idx < b.idx;
+    return a.term < b.term;
+  });
+  const size_t n = m.size();
+  std::vector<int32_t> idx(n), fld(n), trm(n), ptr(c->prob.batch + 1, 0);
+  std::vector<double> val(n), w(n);
+  for (size_t k = 0; k < n; ++k) {
+    idx[k] = m[k].idx;
+    fld[k] = m[k].field;
+    trm[k] = m[k].term;
+    val[k] = m[k].val;
+    w[k] = m[k].w;
+    ptr[m[k].inst + 1]++;
+  }
+  for (int b = 0; b < c->prob.batch; ++b) ptr[b + 1] += ptr[b];
+  hipStream_t s = c->stream;
+  if (n) {
+    HIP_OR_RETURN(c, hipMemcpyAsync(c->m_idx, idx.data(), n * 4, hipMemcpyHostToDevice, s), "upload");
+    HIP_OR_RETURN(c, hipMemcpyAsync(c->m_field, fld.data(), n * 4, hipMemcpyHostToDevice, s), "upload");
+    HIP_OR_RETURN(c, hipMemcpyAsync(c->m_term, trm.data(), n * 4, hipMemcpyHostToDevice, s), "upload");
+    HIP_OR_RETURN(c, hipMemcpyAsync(c->m_val, val.data(), n * 8, hipMemcpyHostToDevice, s), "upload");
+    HIP_OR_RETURN(c, hipMemcpyAsync(c->m_w, w.data(), n * 8, hipMemcpyHostToDevice, s), "upload");
+  }
+  HIP_OR_RETURN(c, hipMemcpyAsync(c->m_inst_ptr, ptr.data(), ptr.size() * 4, hipMemcpyHostToDevice, s),
+                "upload");
+  HIP_OR_RETURN(c, hipStreamSynchronize(s), "upload");
+  c->n_meas_dev = (int)n;
+  return MODIL_OK;
+}
+
+// Horner prolongation of every level; returns the fine field (level 0).
+int horner(modil_ctx *c, const void *theta, const void **fine, void *last_dst = nullptr) {
+  const int L = c->prob.n_levels;
+  if (L == 1) {
+    *fine = theta;
+    return MODIL_OK;
+  }
+  Timed t(c, 1);
+  for (int l = L - 2; l >= 0; --l) {
+    const void *src = (l == L - 2) ? theta : c->w_buf;
+    void *dst = (l == 0 && last_dst) ? last_dst : c->w_buf;
+    const long doff = (l == 0 && last_dst) ? 0 : c->lay.level_offset[l];
+    HIP_OR_RETURN(c, launch_prolong_level(c, theta, src, c->lay.level_offset[l + 1], dst, doff, l),
+                  "prolong");
+  }
+  *fine = last_dst ? last_dst : c->w_buf;
+  return MODIL_OK;
+}
+
+int restrict_chain(modil_ctx *c, void *grad) {
+  Timed t(c, 2);
+  for (int l = 0; l + 1 < c->prob.n_levels; ++l)
+    HIP_OR_RETURN(c, launch_restrict_level(c, grad, c->lay.level_offset[l], grad,
+                                           c->lay.level_offset[l + 1], l),
+                  "restrict");
+  return MODIL_OK;
+}
+
+int evaluate(modil_ctx *c, const void *theta, void *grad, double *terms) {
+  const void *u = nullptr;
+  int st = horner(c, theta, &u);
+  if (st) return st;
+  const bool want = grad != nullptr;
+  {
+    Timed t(c, 0);
+    HIP_OR_RETURN(c, launch_fine(c, u, grad, want), "fine kernel");
+  }
+  {
+    Timed t(c, 4);
+    if (want) HIP_OR_RETURN(c, launch_colsum(c, grad), "column sum");
+    HIP_OR_RETURN(c, launch_data(c, u, grad, want), "data kernel");
+  }
+  if (want) {
+    st = restrict_chain(c, grad);
+    if (st) return st;
+  }
+  Timed t(c, 4);
+  HIP_OR_RETURN(c, launch_reduce(c, terms), "reduce");
+  return MODIL_OK;
+}
+
+bool check_ctx(modil_ctx *c) { return c != nullptr; }
+
+}  // namespace
+
+// ------------------------------------------------------------- op metadata
+namespace modil {
+
+int op_fields(const modil_problem &p) {
+  switch (p.op) {
+    case MODIL_OP_POISSON:
+    case MODIL_OP_BURGERS:
+      return 1;
+    case MODIL_OP_HEAT_KX:
+      return 2;
+    case MODIL_OP_NS3D:
+      return (p.flags & MODIL_FLAG_CHI_FIXED) ? 4 : 5;
+    case MODIL_OP_CAVITY:
+      return 3;
+  }
+  return 0;
+}
+
+int op_pde_equations(const modil_problem &p) {
+  switch (p.op) {
+    case MODIL_OP_NS3D:
+      return 4;
+    case MODIL_OP_CAVITY:
+      return 3;
+    default:
+      return 1;
+  }
+}
+
+bool field_is_x_only(const modil_problem &p, int f) { return p.op == MODIL_OP_HEAT_KX && f == 1; }
+
+FieldGeom field_geom(const modil_problem &p, int level, int f) {
+  FieldGeom g{};
+  for (int a = 0; a < 3; ++a) g.n[a] = 1;
+  for (int k = 0; k < p.ndim; ++k) g.n[3 - p.ndim + k] = p.dims[k] >> level;
+  if (field_is_x_only(p, f)) g.n[0] = g.n[1] = 1;
+  g.stride[2] = 1;
+  g.stride[1] = g.n[2];
+  g.stride[0] = (long)g.n[1] * g.n[2];
+  g.size = (long)g.n[0] * g.n[1] * g.n[2];
+  return g;
+}
+
+}  // namespace modil
+
+// --------------------------------------------------------------------- ABI
+extern "C" {
+
+int modil_abi_version(void) { return MODIL_ABI_VERSION; }
+
+const char *modil_status_str(int s) {
+  switch (s) {
+    case MODIL_OK: return "ok";
+    case MODIL_ERR_INVALID_ARG: return "invalid argument";
+    case MODIL_ERR_SHAPE: return "shape error";
+    case MODIL_ERR_DTYPE: return "dtype error";
+    case MODIL_ERR_HIP: return "HIP runtime error";
+    case MODIL_ERR_NONFINITE: return "non-finite loss";
+    case MODIL_ERR_STATE: return "invalid state";
+  }
+  return "unknown status";
+}
+
+const char *modil_last_error(const modil_ctx *c) {
+  return c ? c->err.c_str() : g_last_error.c_str();
+}
+
+int modil_layout(const modil_problem *p, modil_pack_layout *out) {
+  std::string msg;
+  const int st = validate(p, msg);
+  if (st) return fail_global(st, msg);
+  if (!out) return fail_global(MODIL_ERR_INVALID_ARG, "layout output is NULL");
+  fill_layout(*p, *out);
+  return MODIL_OK;
+}
+
+int modil_create(const modil_problem *p, void *ws, size_t ws_bytes, void *stream, modil_ctx **out) {
+  std::string msg;
+  int st = validate(p, msg);
+  if (st) return fail_global(st, msg);
+  if (!out) return fail_global(MODIL_ERR_INVALID_ARG, "output handle is NULL");
+  *out = nullptr;
+  modil_pack_layout L;
+  fill_layout(*p, L);
+  if (!ws || ws_bytes < L.workspace_bytes)
+    return fail_global(MODIL_ERR_INVALID_ARG, "workspace is NULL or smaller than layout.workspace_bytes (" +
+                                                  std::to_string(L.workspace_bytes) + ")");
+  if (reinterpret_cast<uintptr_t>(ws) % 256)
+    return fail_global(MODIL_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  modil_ctx *c = new (std::nothrow) modil_ctx();
+  if (!c) return fail_global(MODIL_ERR_STATE, "out of host memory");
+  c->prob = *p;
+  c->lay = L;
+  c->stream = (hipStream_t)stream;
+  c->ws = (char *)ws;
+  c->ws_bytes = ws_bytes;
+  (void)hipGetDevice(&c->device);
+  const Carve cv = carve(*p, L);
+  c->w_buf = c->ws + cv.w;
+  c->g_buf = c->ws + cv.g;
+  c->gq_buf = c->ws + cv.gq;
+  c->partials = (double *)(c->ws + cv.partials);
+  c->terms_tmp = (double *)(c->ws + cv.terms);
+  c->flag = (int32_t *)(c->ws + cv.flag);
+  c->m_idx = (int32_t *)(c->ws + cv.m_idx);
+  c->m_field = (int32_t *)(c->ws + cv.m_field);
+  c->m_term = (int32_t *)(c->ws + cv.m_term);
+  c->m_inst_ptr = (int32_t *)(c->ws + cv.m_ptr);
+  c->m_val = (double *)(c->ws + cv.m_val);
+  c->m_w = (double *)(c->ws + cv.m_w);
+  c->inst_re = (double *)(c->ws + cv.inst_re);
+  c->n_fine_blocks = cv.n_fine_blocks;
+  c->n_data_blocks = cv.n_data_blocks;
+  c->n_part_blocks = cv.n_fine_blocks + cv.n_data_blocks;
+  c->inst_re_host.assign(p->batch, p->re);
+  // zero flag, empty measurement lists, default Reynolds numbers
+  const int32_t zero = 0;
+  hipError_t e = hipMemcpyAsync(c->flag, &zero, 4, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->inst_re, c->inst_re_host.data(), p->batch * 8, hipMemcpyHostToDevice,
+                       c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    const std::string m = std::string("create: ") + hipGetErrorString(e);
+    delete c;
+    return fail_global(MODIL_ERR_HIP, m);
+  }
+  st = upload_measurements(c);
+  if (st) {
+    const std::string m = c->err;
+    delete c;
+    return fail_global(st, m);
+  }
+  *out = c;
+  return MODIL_OK;
+}
+
+int modil_destroy(modil_ctx *c) {
+  if (!c) return MODIL_OK;
+  for (auto &pc : c->prof) {
+    for (auto &ev : pc.pending) { (void)hipEventDestroy(ev.a); (void)hipEventDestroy(ev.b); }
+    for (auto &ev : pc.pool) { (void)hipEventDestroy(ev.a); (void)hipEventDestroy(ev.b); }
+  }
+  delete c;
+  return MODIL_OK;
+}
+
+int modil_set_stream(modil_ctx *c, void *stream) {
+  if (!c) return fail_global(MODIL_ERR_INVALID_ARG, "ctx is NULL");
+  c->stream = (hipStream_t)stream;
+  return MODIL_OK;
+}
+
+int modil_set_measurements(modil_ctx *c, int32_t inst, int32_t field, int32_t term, int32_t n,
+                           const int32_t *idx, const double *val, double weight) {
+  if (!c) return fail_global(MODIL_ERR_INVALID_ARG, "ctx is NULL");
+  if (inst < 0 || inst >= c->prob.batch) return fail(c, MODIL_ERR_INVALID_ARG, "instance out of range");
+  if (field < 0 || field >= c->lay.n_fields) return fail(c, MODIL_ERR_INVALID_ARG, "field out of range");
+  if (term != MODIL_TERM_DATA && term != MODIL_TERM_IC)
+    return fail(c, MODIL_ERR_INVALID_ARG, "term must be MODIL_TERM_DATA or MODIL_TERM_IC");
+  if (n < 0 || (n > 0 && (!idx || !val))) return fail(c, MODIL_ERR_INVALID_ARG, "bad list");
+  if (!std::isfinite(weight) || weight < 0.0) return fail(c, MODIL_ERR_INVALID_ARG, "bad weight");
+  if ((long)c->meas.size() + n > c->prob.max_meas)
+    return fail(c, MODIL_ERR_INVALID_ARG, "measurement capacity max_meas exceeded");
+  const FieldGeom g = field_geom(c->prob, 0, field);
+  std::vector<int32_t> sorted(idx, idx + n);
+  std::sort(sorted.begin(), sorted.end());
+  for (int k = 0; k < n; ++k) {
+    if (sorted[k] < 0 || sorted[k] >= g.size) return fail(c, MODIL_ERR_SHAPE, "cell index out of range");
+    if (k && sorted[k] == sorted[k - 1]) return fail(c, MODIL_ERR_INVALID_ARG, "duplicate cell index in list");
+  }
+  for (int k = 0; k < n; ++k) c->meas.push_back(Meas{inst, field, term, idx[k], val[k], weight});
+  return upload_measurements(c);
+}
+
+int modil_clear_measurements(modil_ctx *c) {
+  if (!c) return fail_global(MODIL_ERR_INVALID_ARG, "ctx is NULL");
+  c->meas.clear();
+  return upload_measurements(c);
+}
+
+int modil_set_field(modil_ctx *c, int32_t which, const void *ptr) {
+  if (!c) return fail_global(MODIL_ERR_INVALID_ARG, "ctx is NULL");
+  if (which >= MODIL_FIELD_FORCING0 && which <= MODIL_FIELD_FORCING3) {
+    c->forcing[which] = ptr;
+    return MODIL_OK;
+  }
+  if (which == MODIL_FIELD_CHI) {
+    if (!(c->prob.flags & MODIL_FLAG_CHI_FIXED))
+      return fail(c, MODIL_ERR_INVALID_ARG, "chi array needs MODIL_FLAG_CHI_FIXED");
+    c->chi = ptr;
+    return MODIL_OK;
+  }
+  return fail(c, MODIL_ERR_INVALID_ARG, "unknown field slot");
+}
+
+int modil_set_instance_scalar(modil_ctx *c, int32_t inst, int32_t which, double value) {
+  if (!c) return fail_global(MODIL_ERR_INVALID_ARG, "ctx is NULL");
+  if (inst < 0 || inst >= c->prob.batch) return fail(c, MODIL_ERR_INVALID_ARG, "instance out of range");
+  if (which != MODIL_SCALAR_RE || !(value > 0.0)) return fail(c, MODIL_ERR_INVALID_ARG, "bad scalar");
+  c->inst_re_host[inst] = value;
+  HIP_OR_RETURN(c, hipMemcpyAsync(c->inst_re, c->inst_re_host.data(), c->prob.batch * 8,
+                                  hipMemcpyHostToDevice, c->stream),
+                "set scalar");
+  HIP_OR_RETURN(c, hipStreamSynchronize(c->stream), "set scalar");
+  return MODIL_OK;
+}
+
+static int ready(modil_ctx *c) {
+  if (!c) return fail_global(MODIL_ERR_INVALID_ARG, "ctx is NULL");
+  if ((c->prob.flags & MODIL_FLAG_CHI_FIXED) && !c->chi)
+    return fail(c, MODIL_ERR_STATE, "fixed-chi problem needs modil_set_field(MODIL_FIELD_CHI)");
+  return MODIL_OK;
+}
+
+int modil_prolong(modil_ctx *c, const void *theta, void *fine_out) {
+  int st = ready(c);
+  if (st) return st;
+  if (!theta || !fine_out) return fail(c, MODIL_ERR_INVALID_ARG, "NULL pointer");
+  if (c->prob.n_levels == 1) {
+    HIP_OR_RETURN(c, hipMemcpyAsync(fine_out, theta, c->lay.fine_total * dtype_size(c->prob),
+                                    hipMemcpyDeviceToDevice, c->stream),
+                  "prolong copy");
+    return MODIL_OK;
+  }
+  const void *u = nullptr;
+  return horner(c, theta, &u, fine_out);
+}
+
+int modil_restrict_adjoint(modil_ctx *c, const void *fine_in, void *grad) {
+  int st = ready(c);
+  if (st) return st;
+  if (!fine_in || !grad) return fail(c, MODIL_ERR_INVALID_ARG, "NULL pointer");
+  HIP_OR_RETURN(c, hipMemcpyAsync(grad, fine_in, c->lay.fine_total * dtype_size(c->prob),
+                                  hipMemcpyDeviceToDevice, c->stream),
+                "restrict copy");
+  return restrict_chain(c, grad);
+}
+
+int modil_loss(modil_ctx *c, const void *theta, double *terms) {
+  int st = ready(c);
+  if (st) return st;
+  if (!theta || !terms) return fail(c, MODIL_ERR_INVALID_ARG, "NULL pointer");
+  return evaluate(c, theta, nullptr, terms);
+}
+
+int modil_loss_grad(modil_ctx *c, const void *theta, void *grad, double *terms) {
+  int st = ready(c);
+  if (st) return st;
+  if (!theta || !grad || !terms) return fail(c, MODIL_ERR_INVALID_ARG, "NULL pointer");
+  return evaluate(c, theta, grad, terms);
+}
+
+static int check_hp(modil_ctx *c, const modil_adam_hp *hp, int64_t step) {
+  if (!hp) return fail(c, MODIL_ERR_INVALID_ARG, "hyper-parameters are NULL");
+  if (step < 1) return fail(c, MODIL_ERR_INVALID_ARG, "step must be >= 1");
+  if (!(hp->beta1 >= 0.0 && hp->beta1 < 1.0 && hp->beta2 >= 0.0 && hp->beta2 < 1.0 &&
+        hp->eps > 0.0 && std::isfinite(hp->lr)))
+    return fail(c, MODIL_ERR_INVALID_ARG, "bad Adam hyper-parameters");
+  return MODIL_OK;
+}
+
+static int adam_all(modil_ctx *c, const void *th_in, void *th_out, void *m, void *v, const void *g,
+                    const modil_adam_hp *hp, int64_t step) {
+  const double bc1 = 1.0 - std::pow(hp->beta1, (double)step);
+  const double bc2 = 1.0 - std::pow(hp->beta2, (double)step);
+  Timed t(c, 3);
+  HIP_OR_RETURN(c, launch_adam(c, th_in, th_out, m, v, g, c->lay.total, hp->lr, hp->beta1,
+                               hp->beta2, hp->eps, bc1, bc2),
+                "adam");
+  return MODIL_OK;
+}
+
+int modil_adam(modil_ctx *c, const void *th_in, void *th_out, void *m, void *v, const void *g,
+               const modil_adam_hp *hp, int64_t step) {
+  if (!c) return fail_global(MODIL_ERR_INVALID_ARG, "ctx is NULL");
+  int st = check_hp(c, hp, step);
+  if (st) return st;
+  if (!th_in || !th_out || !m || !v || !g) return fail(c, MODIL_ERR_INVALID_ARG, "NULL pointer");
+  return adam_all(c, th_in, th_out, m, v, g, hp, step);
+}
+
+int modil_step(modil_ctx *c, const void *th_in, void *th_out, void *m, void *v,
+               const modil_adam_hp *hp, int64_t step, double *terms) {
+  int st = ready(c);
+  if (st) return st;
+  st = check_hp(c, hp, step);
+  if (st) return st;
+  if (!th_in || !th_out || !m || !v) return fail(c, MODIL_ERR_INVALID_ARG, "NULL pointer");
+  if (th_in == th_out) return fail(c, MODIL_ERR_INVALID_ARG, "theta_out must differ from theta_in");
+  st = evaluate(c, th_in, c->g_buf, terms ? terms : c->terms_tmp);
+  if (st) return st;
+  return adam_all(c, th_in, th_out, m, v, c->g_buf, hp, step);
+}
+
+int modil_residual_metric(modil_ctx *c, const void *theta, double *r) {
+  int st = ready(c);
+  if (st) return st;
+  if (!theta || !r) return fail(c, MODIL_ERR_INVALID_ARG, "NULL pointer");
+  st = evaluate(c, theta, nullptr, c->terms_tmp);
+  if (st) return st;
+  HIP_OR_RETURN(c, launch_metric(c, c->terms_tmp, r), "metric");
+  return MODIL_OK;
+}
+
+int modil_check(modil_ctx *c) {
+  if (!c) return fail_global(MODIL_ERR_INVALID_ARG, "ctx is NULL");
+  HIP_OR_RETURN(c, hipStreamSynchronize(c->stream), "check");
+  HIP_OR_RETURN(c, hipGetLastError(), "check");
+  int32_t flag = 0;
+  HIP_OR_RETURN(c, hipMemcpy(&flag, c->flag, 4, hipMemcpyDeviceToHost), "check");
+  if (flag) {
+    const int32_t zero = 0;
+    HIP_OR_RETURN(c, hipMemcpy(c->flag, &zero, 4, hipMemcpyHostToDevice), "check");
+    return fail(c, MODIL_ERR_NONFINITE, "a loss term was NaN or Inf");
+  }
+  return MODIL_OK;
+}
+
+int modil_profile(modil_ctx *c, int32_t enable) {
+  if (!c) return fail_global(MODIL_ERR_INVALID_ARG, "ctx is NULL");
+  c->profiling = enable != 0;
+  return MODIL_OK;
+}
+
+int modil_profile_read(modil_ctx *c, int32_t cls, double *total_ms, int64_t *count) {
+  if (!c) return fail_global(MODIL_ERR_INVALID_ARG, "ctx is NULL");
+  if (cls < 0 || cls > 4 || !total_ms || !count) return fail(c, MODIL_ERR_INVALID_ARG, "bad class");
+  HIP_OR_RETURN(c, hipStreamSynchronize(c->stream), "profile");
+  ProfileClass &pc = c->prof[cls];
+  for (auto &ev : pc.pending) {
+    float ms = 0.f;
+    HIP_OR_RETURN(c, hipEventElapsedTime(&ms, ev.a, ev.b), "profile");
+    pc.ms += ms;
+    pc.count += 1;
+    pc.pool.push_back(ev);
+  }
+  pc.pending.clear();
+  *total_ms = pc.ms;
+  *count = pc.count;
+  pc.ms = 0.0;
+  pc.count = 0;
+  return MODIL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,124 @@
+// Internal declarations shared by the host side of libmodil and its kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "modil.h"
+
+namespace modil {
+
+constexpr int kBlock = 256;       // threads per block of the flat kernels
+constexpr int kMaxF = MODIL_MAX_FIELDS;
+constexpr int kMaxL = MODIL_MAX_LEVELS;
+constexpr int kTerms = MODIL_N_TERMS;
+
+// Geometry of one field on one level: cells per axis (z, y, x; 1 for axes the
+// field or the grid does not span) and C-order strides.
+struct FieldGeom {
+  int n[3];
+  long stride[3];
+  long size;
+};
+
+// Constants of the residual operator, passed by value to the kernels.
+struct OpParams {
+  int ndim;          // active axes are the last ndim of (z, y, x)
+  int n[3];          // fine cells per axis (1 on inactive axes)
+  double h[3];       // cell size per axis
+  double V;          // cell measure (product of active h)
+  double w_pde, w_reg, w_bc;
+  double re, diam, lam, chi_shift, tau_coef, u_ref;
+  const double *inst_re;  // per-instance Reynolds number (device) or null
+};
+
+// Per-field description of the finest grid for the stencil engine.
+struct FineFields {
+  int nf;
+  long off[kMaxF];      // element offset of field f inside one instance
+  long stride[kMaxF][3];  // strides of field f (0 on axes it does not span)
+  long inst_stride;     // elements of all fields of one instance
+};
+
+struct Meas {
+  int32_t inst, field, term, idx;
+  double val, w;
+};
+
+struct EventPair {
+  hipEvent_t a, b;
+};
+
+struct ProfileClass {
+  std::vector<EventPair> pending;
+  std::vector<EventPair> pool;
+  double ms = 0.0;
+  int64_t count = 0;
+};
+
+}  // namespace modil
+
+struct modil_ctx {
+  modil_problem prob;
+  modil_pack_layout lay;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  char *ws = nullptr;
+  size_t ws_bytes = 0;
+
+  // workspace carve-up
+  void *w_buf = nullptr;     // Horner intermediates, levels 0..L-2 (level 0 = fine u)
+  void *g_buf = nullptr;     // gradient pack used by modil_step
+  void *gq_buf = nullptr;    // per-cell contributions of 1-D fields (heat q)
+  void *fine_tmp = nullptr;  // one fine-field array (scratch)
+  double *partials = nullptr;  // [batch][n_part_blocks][kTerms]
+  double *terms_tmp = nullptr; // [batch][kTerms]
+  int32_t *flag = nullptr;     // non-finite flag
+  int32_t *m_idx = nullptr, *m_field = nullptr, *m_term = nullptr, *m_inst_ptr = nullptr;
+  double *m_val = nullptr, *m_w = nullptr;
+  double *inst_re = nullptr;
+
+  long n_fine_blocks = 0;   // partial blocks of the fine kernel per instance
+  long n_data_blocks = 0;   // partial blocks of the data kernel per instance
+  long n_part_blocks = 0;   // n_fine_blocks + n_data_blocks
+
+  std::vector<modil::Meas> meas;
+  int n_meas_dev = 0;
+  int max_list_len = 0;
+  std::vector<double> inst_re_host;
+  const void *forcing[4] = {nullptr, nullptr, nullptr, nullptr};
+  const void *chi = nullptr;
+
+  bool profiling = false;
+  modil::ProfileClass prof[5];
+  std::string err;
+};
+
+namespace modil {
+
+// layout helpers (api.cpp)
+int op_fields(const modil_problem &p);
+int op_equations(const modil_problem &p);
+int op_pde_equations(const modil_problem &p);
+bool field_is_x_only(const modil_problem &p, int f);
+FieldGeom field_geom(const modil_problem &p, int level, int f);
+
+// kernel launchers (kernels_*.hip); all enqueue on ctx->stream and return
+// hipSuccess or the launch error.
+hipError_t launch_prolong_level(modil_ctx *c, const void *theta, const void *coarse_src,
+                                long coarse_off, void *dst, long dst_off, int level);
+hipError_t launch_restrict_level(modil_ctx *c, const void *fine_src, long fine_off, void *dst,
+                                 long dst_off, int level);
+hipError_t launch_adam(modil_ctx *c, const void *theta_in, void *theta_out, void *m, void *v,
+                       const void *g, long n, double lr, double b1, double b2, double eps,
+                       double bc1, double bc2);
+hipError_t launch_fine(modil_ctx *c, const void *u, void *g, bool want_grad);
+hipError_t launch_colsum(modil_ctx *c, void *g_fine);
+hipError_t launch_data(modil_ctx *c, const void *u, void *g, bool want_grad);
+hipError_t launch_reduce(modil_ctx *c, double *terms);
+hipError_t launch_metric(modil_ctx *c, const double *terms, double *r);
+
+}  // namespace modil

@@ -1,0 +1,88 @@
+"""Helpers for the GPU parity tests: build a libmodil context from an oracle
+Spec, move level fields in and out of parameter packs, compare."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2303_04679_amd.modil import Context, ProblemSpec
+
+TOL = {"f64": 1e-12, "f32": 1e-5}
+TERMS = ("pde", "data", "reg", "ic", "bc")
+
+
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def problem_of(spec, dtype, batch=1):
+    P = spec.params
+    return ProblemSpec(
+        "ns3d" if spec.op.startswith("ns3d") else spec.op, spec.dims, spec.lengths, spec.n_levels,
+        dtype=dtype, batch=batch,
+        max_meas=batch * sum(len(m[2]) for m in spec.meas) + 1,
+        chi_fixed=spec.op == "ns3d_fixed", re=P.get("re", 100.0), diam=P.get("diam", 0.4),
+        lam=P.get("lam", 1.0), chi_shift=P.get("chi_shift", 5.0), tau_coef=P.get("tau_coef", 0.5),
+        u_ref=1.0, w_pde=spec.weights["pde"], w_reg=spec.weights["reg"], w_bc=spec.weights["bc"])
+
+
+def context_of(spec, dtype, batch=1, specs=None):
+    """Context for `batch` instances; instance b uses specs[b] (default: spec)."""
+    specs = specs or [spec] * batch
+    ctx = Context(problem_of(spec, dtype, batch))
+    for b, s in enumerate(specs):
+        for field, term, idx, vals, w in s.meas:
+            ctx.set_measurements(field, idx, vals, w, term=term, instance=b)
+        if "re" in s.params and batch > 1:
+            ctx.set_reynolds(b, s.params["re"])
+    for e in range(4):
+        if e in spec.forcing:
+            arr = np.stack([np.asarray(s.forcing[e]).ravel() for s in specs])
+            ctx.set_field(f"forcing{e}", torch.tensor(arr, dtype=ctx.dtype, device="cuda").reshape(-1))
+    if spec.op == "ns3d_fixed":
+        arr = np.stack([np.asarray(s.chi).ravel() for s in specs])
+        ctx.set_field("chi", torch.tensor(arr, dtype=ctx.dtype, device="cuda").reshape(-1))
+    return ctx
+
+
+def pack_of(ctx, levels_per_instance):
+    pack = ctx.new_pack()
+    for b, levels in enumerate(levels_per_instance):
+        views = ctx.level_views(pack, b)
+        for lv, row in zip(views, levels):
+            for v, x in zip(lv, row):
+                v.copy_(torch.as_tensor(np.asarray(x), dtype=ctx.dtype))
+    return pack
+
+
+def levels_of(ctx, pack, instance=0):
+    return [[v.detach().cpu().double().numpy() for v in row]
+            for row in ctx.level_views(pack, instance)]
+
+
+def rounded(levels, dtype):
+    """The level values as the GPU sees them (FP32 inputs promoted back to FP64)."""
+    if dtype == "f64":
+        return [[np.asarray(x, dtype=np.float64) for x in row] for row in levels]
+    return [[np.asarray(x, dtype=np.float32).astype(np.float64) for x in row] for row in levels]
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a)
+
+
+def assert_terms(gpu_terms, ref_terms, tol, ctx_msg=""):
+    for k, t in enumerate(TERMS):
+        g, r = float(gpu_terms[k]), float(ref_terms[t])
+        assert abs(g - r) <= tol * max(abs(r), 1e-300) or (r == 0.0 and abs(g) < 1e-300), \
+            (ctx_msg, t, g, r)
+
+
+def assert_levels(gpu_levels, ref_levels, tol, ctx_msg=""):
+    for li, (grow, rrow) in enumerate(zip(gpu_levels, ref_levels)):
+        for fi, (g, r) in enumerate(zip(grow, rrow)):
+            e = rel(g, r)
+            assert e <= tol, (ctx_msg, "level", li, "field", fi, e)

@@ -1,0 +1,84 @@
+"""Host-side checks of libmodil: it loads, exports what the header declares,
+validates problems and computes pack layouts (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import operators as ops
+from paper_2303_04679_amd import _lib as L
+from paper_2303_04679_amd.modil import ProblemSpec, field_shape, layout
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "modil.h")
+
+
+def test_library_exports_every_declared_function():
+    text = open(HEADER).read()
+    names = set(re.findall(r"\b(modil_[a-z_]+)\s*\(", text))
+    lib = L.lib()
+    missing = [n for n in sorted(names) if not hasattr(lib, n)]
+    assert not missing, missing
+    assert len(names) >= 20
+    assert lib.modil_abi_version() == 1
+
+
+def test_status_strings():
+    lib = L.lib()
+    for s in (0, -1, -2, -3, -4, -5, -6):
+        assert lib.modil_status_str(s)
+
+
+@pytest.mark.parametrize("op,dims,L_,fields", [
+    ("poisson", (16, 16), 3, None), ("burgers", (64, 64), 5, None), ("heat", (256, 256), 6, None),
+    ("ns3d", (16, 16, 16), 3, None), ("cavity", (128, 128), 5, None)])
+def test_layout_matches_level_shapes(op, dims, L_, fields):
+    spec = ProblemSpec(op, dims, (1.0,) * len(dims), L_, batch=3)
+    lay = layout(spec)
+    shapes = ops.level_shapes(op, dims, L_)
+    total = 0
+    for lvl in range(L_):
+        assert lay.level_offset[lvl] == total
+        per_inst = 0
+        for f, shp in enumerate(shapes[lvl]):
+            assert field_shape(spec, lay, lvl, f) == tuple(shp)
+            assert lay.field_offset[lvl][f] == per_inst
+            per_inst += int(np.prod(shp))
+        assert lay.level_stride[lvl] == per_inst
+        total += 3 * per_inst
+    assert lay.total == total
+    assert lay.fine_cells == int(np.prod(dims))
+    assert lay.workspace_bytes > 0
+
+
+def test_config_sizes():
+    """Parameter counts of the five workloads (levels x fields)."""
+    cases = {("burgers", (64, 64), 5): 5456, ("heat", (256, 256), 6): 87360 + 504,
+             ("ns3d", (64,) * 3, 5): 5 * 299584, ("ns3d", (128,) * 3, 6): 5 * 2396736,
+             ("cavity", (128, 128), 5): 3 * 21824}
+    for (op, dims, nl), want in cases.items():
+        assert layout(ProblemSpec(op, dims, (1.0,) * len(dims), nl)).total == want
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(op="ns3d", dims=(16, 16), lengths=(1, 1), n_levels=2), L.ERR_SHAPE),
+    (dict(op="poisson", dims=(24, 24), lengths=(1, 1), n_levels=5), L.ERR_SHAPE),
+    (dict(op="poisson", dims=(16,), lengths=(1,), n_levels=5), L.ERR_SHAPE),
+    (dict(op="poisson", dims=(16,), lengths=(-1,), n_levels=2), L.ERR_INVALID_ARG),
+    (dict(op="cavity", dims=(16, 16), lengths=(1, 1), n_levels=2, batch=0), L.ERR_INVALID_ARG),
+    (dict(op="cavity", dims=(16, 16), lengths=(1, 1), n_levels=2, re=0.0), L.ERR_INVALID_ARG),
+    (dict(op="cavity", dims=(16, 16), lengths=(1, 1), n_levels=2, chi_fixed=True), L.ERR_INVALID_ARG),
+])
+def test_validation_errors(kw, status):
+    with pytest.raises(L.ModilError) as ei:
+        layout(ProblemSpec(**kw))
+    assert ei.value.status == status
+    assert L.lib().modil_last_error(None)
+
+
+def test_node_centering_rejected():
+    p = ProblemSpec("poisson", (16,), (1.0,), 2).to_c()
+    p.centering = L.NODE
+    out = L.PackLayout()
+    assert L.lib().modil_layout(ctypes.byref(p), ctypes.byref(out)) == L.ERR_DTYPE

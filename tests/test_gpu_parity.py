@@ -1,0 +1,217 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances: norm-wise relative error per (level, field) and relative error
+per loss term, 1e-12 in FP64 and 1e-5 in FP32 (FP32 inputs are promoted to
+FP64 for the oracle).  Sizes span many 256-thread blocks with ragged tails
+and non-square grids.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import adam as oadam
+from oracle import multigrid as mg
+from oracle import operators as ops
+from tests.gpu_helpers import (TOL, assert_levels, assert_terms, context_of, levels_of, need_gpu,
+                               pack_of, rel, rounded)
+from tests.oracle_cases import case, random_levels
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    ("poisson", (200,), 4),
+    ("poisson", (32, 48), 4),
+    ("poisson", (16, 8, 24), 3),
+    ("burgers", (64, 64), 5),
+    ("burgers", (24, 40), 3),
+    ("heat", (64, 32), 4),
+    ("heat", (40, 72), 3),
+    ("ns3d", (16, 16, 24), 3),
+    ("ns3d_fixed", (8, 16, 24), 3),
+    ("cavity", (32, 48), 4),
+]
+
+
+def _levels(spec, seed):
+    if spec.op == "burgers":
+        return random_levels(spec, seed, lo=0.05, hi=0.6)
+    return random_levels(spec, seed)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("op,dims,L", CASES)
+def test_loss_grad(op, dims, L, dtype):
+    need_gpu()
+    print(f"\n[parity] loss_grad {op} {dims} L={L} {dtype}", flush=True)
+    spec = case(op, dims, L, seed=7, with_forcing=op != "poisson")
+    lv = rounded(_levels(spec, 8), dtype)
+    ref_terms, ref_grad = ops.loss_and_grad(spec, lv)
+    ctx = context_of(spec, dtype)
+    theta = pack_of(ctx, [lv])
+    terms, grad = ctx.loss_grad(theta)
+    terms2 = ctx.loss(theta)
+    torch.cuda.synchronize()
+    tol = TOL[dtype]
+    assert_terms(terms[0].cpu().numpy(), ref_terms, tol, op)
+    assert_terms(terms2[0].cpu().numpy(), ref_terms, tol, op)
+    assert_levels(levels_of(ctx, grad), ref_grad, tol, op)
+
+
+@pytest.mark.parametrize("op,dims,L", [("poisson", (48, 32), 4), ("heat", (32, 64), 4),
+                                       ("ns3d", (8, 16, 8), 3)])
+def test_prolong_and_restrict(op, dims, L):
+    need_gpu()
+    spec = case(op, dims, L, seed=1)
+    lv = _levels(spec, 2)
+    ctx = context_of(spec, "f64")
+    theta = pack_of(ctx, [lv])
+    fine = ctx.prolong(theta)
+    torch.cuda.synchronize()
+    for f, name in enumerate(spec.fields):
+        axes = ops.field_axes(spec.op, name, spec.ndim)
+        ref = mg.decompose_horner([torch.tensor(r[f]) for r in lv], axes).numpy()
+        got = ctx.fine_views(fine)[f].cpu().numpy()
+        assert rel(got, ref) <= 1e-14
+    g = torch.randn(fine.numel(), dtype=torch.float64, device="cuda")
+    pk = ctx.restrict_adjoint(g)
+    torch.cuda.synchronize()
+    gl = levels_of(ctx, pk)
+    for f, name in enumerate(spec.fields):
+        axes = ops.field_axes(spec.op, name, spec.ndim)
+        ref = mg.decompose_transpose(torch.tensor(ctx.fine_views(g)[f].cpu().numpy()), L, axes)
+        for li in range(L):
+            assert rel(gl[li][f], ref[li].numpy()) <= 1e-14
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_adam(dtype):
+    need_gpu()
+    spec = case("cavity", (32, 32), 3, seed=2)
+    ctx = context_of(spec, dtype)
+    rng = np.random.default_rng(5)
+    n = int(ctx.lay.total)
+    th = rng.standard_normal(n)
+    m = 0.1 * rng.standard_normal(n)
+    v = np.abs(rng.standard_normal(n))
+    g = rng.standard_normal(n)
+    T = lambda a: torch.tensor(a, dtype=ctx.dtype, device="cuda")
+    cast = (lambda a: a) if dtype == "f64" else (lambda a: a.astype(np.float32).astype(np.float64))
+    th_t, th_o, m_t, v_t, g_t = T(th), T(th) * 0, T(m), T(v), T(g)
+    ctx.adam(th_t, th_o, m_t, v_t, g_t, step=7, lr=1e-2)
+    torch.cuda.synchronize()
+    rt, rm, rv = oadam.adam_step(cast(th), cast(m), cast(v), cast(g), 1e-2, 0.9, 0.999, 1e-8, 7)
+    tol = 1e-14 if dtype == "f64" else 1e-6
+    assert rel(th_o.cpu().numpy(), rt) <= tol
+    assert rel(m_t.cpu().numpy(), rm) <= tol
+    assert rel(v_t.cpu().numpy(), rv) <= tol
+
+
+@pytest.mark.parametrize("op,dims,L", [("burgers", (32, 32), 4), ("heat", (32, 32), 4),
+                                       ("ns3d", (8, 8, 16), 3), ("cavity", (32, 32), 4)])
+def test_step_sequence_f64(op, dims, L):
+    """Three modil_step calls (ping-pong theta) follow the oracle's loss, gradient and Adam."""
+    need_gpu()
+    spec = case(op, dims, L, seed=3)
+    lv = _levels(spec, 4)
+    ctx = context_of(spec, "f64")
+    a, b = pack_of(ctx, [lv]), ctx.new_pack()
+    m, v = ctx.new_pack(), ctx.new_pack()
+    ref = [[(x.copy(), np.zeros_like(x), np.zeros_like(x)) for x in row] for row in lv]
+    terms = torch.empty((1, 5), dtype=torch.float64, device="cuda")
+    for t in range(1, 4):
+        ctx.step(a, b, m, v, t, lr=1e-2, terms=terms)
+        torch.cuda.synchronize()
+        cur = [[s[0] for s in row] for row in ref]
+        rterms, rgrad = ops.loss_and_grad(spec, cur)
+        assert_terms(terms[0].cpu().numpy(), rterms, 1e-11, (op, t))
+        ref = [[oadam.adam_step(s[0], s[1], s[2], g, 1e-2, 0.9, 0.999, 1e-8, t)
+                for s, g in zip(row, grow)] for row, grow in zip(ref, rgrad)]
+        a, b = b, a
+    assert_levels(levels_of(ctx, a), [[s[0] for s in row] for row in ref], 1e-11, op)
+    assert_levels(levels_of(ctx, m), [[s[1] for s in row] for row in ref], 1e-11, op)
+
+
+@pytest.mark.parametrize("op,dims,L", [("heat", (32, 32), 4), ("ns3d", (8, 8, 16), 3)])
+def test_step_is_loss_grad_then_adam_f32(op, dims, L):
+    """In FP32 the fused step equals loss_grad followed by adam, bit for bit, and
+    its loss terms match the oracle.  (Adam's first steps are sign-like, so an
+    elementwise FP32 trajectory comparison is not meaningful.)"""
+    need_gpu()
+    spec = case(op, dims, L, seed=3)
+    lv = rounded(_levels(spec, 4), "f32")
+    ctx = context_of(spec, "f32")
+    th = pack_of(ctx, [lv])
+    out1, m1, v1 = ctx.new_pack(), ctx.new_pack(), ctx.new_pack()
+    out2, m2, v2 = ctx.new_pack(), ctx.new_pack(), ctx.new_pack()
+    terms = torch.empty((1, 5), dtype=torch.float64, device="cuda")
+    ctx.step(th, out1, m1, v1, 1, lr=1e-2, terms=terms)
+    t2, g = ctx.loss_grad(th)
+    ctx.adam(th, out2, m2, v2, g, 1, lr=1e-2)
+    torch.cuda.synchronize()
+    assert torch.equal(out1, out2) and torch.equal(m1, m2) and torch.equal(v1, v2)
+    assert torch.equal(terms, t2)
+    rterms, _ = ops.loss_and_grad(spec, lv)
+    assert_terms(terms[0].cpu().numpy(), rterms, 1e-5, op)
+
+
+def test_deterministic():
+    need_gpu()
+    spec = case("ns3d", (16, 16, 16), 3, seed=9, with_forcing=True)
+    ctx = context_of(spec, "f32")
+    theta = pack_of(ctx, [_levels(spec, 10)])
+    t1, g1 = ctx.loss_grad(theta)
+    t2, g2 = ctx.loss_grad(theta)
+    torch.cuda.synchronize()
+    assert torch.equal(t1, t2) and torch.equal(g1, g2)
+
+
+def test_batch_instances():
+    """Independent instances with their own data and Reynolds number."""
+    need_gpu()
+    specs = []
+    for b in range(3):
+        s = case("cavity", (32, 32), 3, seed=20 + b)
+        s.params["re"] = 100.0 + 300.0 * b
+        specs.append(s)
+    ctx = context_of(specs[0], "f64", batch=3, specs=specs)
+    lvs = [_levels(s, 30 + b) for b, s in enumerate(specs)]
+    theta = pack_of(ctx, lvs)
+    terms, grad = ctx.loss_grad(theta)
+    r = ctx.residual_metric(theta)
+    torch.cuda.synchronize()
+    for b, s in enumerate(specs):
+        rt, rg = ops.loss_and_grad(s, lvs[b])
+        assert_terms(terms[b].cpu().numpy(), rt, 1e-12, b)
+        assert_levels(levels_of(ctx, grad, b), rg, 1e-12, b)
+        assert abs(float(r[b]) - ops.residual_metric(s, lvs[b])) <= 1e-12 * float(r[b])
+
+
+def test_nonfinite_is_reported():
+    """A NaN measurement (forced from the host) raises MODIL_ERR_NONFINITE at check()."""
+    need_gpu()
+    from paper_2303_04679_amd import _lib as L
+    spec = case("burgers", (16, 16), 2, seed=1)
+    f, term, idx, vals, w = spec.meas[0]
+    vals = vals.copy()
+    vals[0] = float("nan")
+    spec.meas = [(f, term, idx, vals, w)]
+    ctx = context_of(spec, "f64")
+    theta = pack_of(ctx, [_levels(spec, 2)])
+    ctx.loss(theta)
+    with pytest.raises(L.ModilError) as ei:
+        ctx.check()
+    assert ei.value.status == L.ERR_NONFINITE
+    ctx.check()   # the flag is cleared
+
+
+def test_theta_pingpong_required():
+    need_gpu()
+    from paper_2303_04679_amd import _lib as L
+    spec = case("poisson", (16, 16), 2, seed=1)
+    ctx = context_of(spec, "f64")
+    a, m, v = ctx.new_pack(), ctx.new_pack(), ctx.new_pack()
+    with pytest.raises(L.ModilError) as ei:
+        ctx.step(a, a, m, v, 1)
+    assert ei.value.status == L.ERR_INVALID_ARG
