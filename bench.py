@@ -1,0 +1,236 @@
+#!/usr/bin/env python
+"""Throughput of one mODIL iteration on one MI355X.
+
+A step is one full iteration of the method on one batch of synthetic input:
+multigrid prolongation of every level, residuals / data terms and the FP64
+loss, the exact adjoint, restriction to every level and Adam on every level.
+
+    python bench.py [--steps K] [--warmup W] [--workload ns3d128]
+
+Prints one JSON line: fine-grid cell-iterations per second (fine cells x
+steps / seconds, inputs resident in HBM), the per-kernel-class durations from
+HIP events recorded on the library's stream during the timed steps, the
+roofline of the dominant kernel (algorithmic bytes / its average launch
+duration against 8 TB/s), and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+HBM_PEAK_GBS = 8000.0
+CLASSES = ("fine", "horner", "restrict", "adam", "reduce")
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="ns3d128")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="budget of the oracle CPU-baseline sample (0 disables it)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (for counter scaling)")
+    return ap.parse_args()
+
+
+def alg_bytes(ctx, spec, fused):
+    """Algorithmic bytes of one launch of each kernel class and of one iteration.
+
+    Every array a kernel must read or write is counted once; halo re-reads
+    and caching are not.  One iteration touches every parameter of every level
+    six times (theta, m, v read and written): 6 * b * S.
+
+    Fused channel-flow path: the finest-level kernel reads theta, m, v of the
+    finest level and the prolonged level 1, and writes theta', m', v' and the
+    finest gradient; the restriction class reads each gradient level, writes
+    the next one and applies Adam to it.  Generic path: the fine kernel reads
+    the prolonged field and writes the finest gradient; Adam is one sweep.
+    """
+    b = 4 if spec.dtype == "f32" else 8
+    lay = ctx.lay
+    L = spec.n_levels
+    size = [int(lay.level_stride[l]) * spec.batch for l in range(L)]
+    S = int(lay.total)
+    chi = spec.batch * spec.fine_cells * b if spec.chi_fixed else 0
+    if fused:
+        fine = (7 * size[0] + (size[1] if L > 1 else 0)) * b + chi
+        horner = sum((2 * size[l] + size[l + 1]) * b for l in range(1, L - 1))
+        restrict = sum((size[l] + 7 * size[l + 1]) * b for l in range(L - 1))
+        adam = 0
+    else:
+        fine = 2 * size[0] * b + chi
+        horner = sum((2 * size[l] + size[l + 1]) * b for l in range(L - 1))
+        restrict = sum((size[l] + size[l + 1]) * b for l in range(L - 1))
+        adam = 7 * S * b
+    return {"fine": fine, "horner": horner, "restrict": restrict, "adam": adam,
+            "reduce": 0, "iteration": 6 * S * b}
+
+
+def measured_traffic(workload, kernel_class):
+    """HBM bytes per launch from the committed counter summary, or None.
+
+    profiles/traffic_<workload>.json holds FETCH_SIZE and WRITE_SIZE of the
+    dominant kernel, scaled by what the same counters read for a plain device
+    copy of known size, together with the SHA-256 of the kernel sources at the
+    time; a changed source makes the figure stale (None).
+    """
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_class") != kernel_class:
+        return None
+    h = hashlib.sha256()
+    csrc = os.path.join(here, "paper_2303_04679_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        h.update(open(os.path.join(csrc, name), "rb").read())
+    if h.hexdigest() != rec.get("source_sha256"):
+        return None
+    return rec["fetch_bytes"] + rec["write_bytes"]
+
+
+def oracle_baseline(workload, theta_levels, seconds):
+    """The FP64 oracle (loss, autodiff gradient, Adam) on the same workload."""
+    import torch
+    from oracle import adam as oadam
+    from oracle import operators as ops
+    spec = workload.spec
+    op = "ns3d_fixed" if spec.chi_fixed else spec.op
+    ospec = ops.Spec(op, spec.dims, spec.lengths, spec.n_levels,
+                     params={"re": spec.re, "diam": spec.diam, "lam": spec.lam,
+                             "chi_shift": spec.chi_shift, "tau_coef": spec.tau_coef},
+                     weights={"pde": spec.w_pde, "reg": spec.w_reg, "bc": spec.w_bc},
+                     meas=[(f, t, idx, vals, w) for inst, f, t, idx, vals, w in workload.meas if inst == 0],
+                     chi=workload.chi if spec.chi_fixed else None)
+    state = [[(x, x * 0.0, x * 0.0) for x in row] for row in theta_levels]
+    t0 = time.perf_counter()
+    it = 0
+    while True:
+        cur = [[s[0] for s in row] for row in state]
+        _, grads = ops.loss_and_grad(ospec, cur)
+        it += 1
+        state = [[oadam.adam_step(s[0], s[1], s[2], g, workload.lr, 0.9, 0.999, 1e-8, it)
+                  for s, g in zip(row, grow)] for row, grow in zip(state, grads)]
+        el = time.perf_counter() - t0
+        if el >= seconds or it >= 50:
+            break
+    return {"value": spec.fine_cells * it / el, "unit": "cell-iter/s",
+            "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": f"{it} full iterations (loss, autodiff gradient, Adam) of {workload.name} "
+                      f"in FP64 on the host CPU, {el:.1f} s"}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs the mODIL iteration on one GPU only; "
+              "multi-GPU domain decomposition is not implemented.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2303_04679_amd import configs
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    wl = configs.WORKLOADS[args.workload]()
+    spec = wl.spec
+    print(f"[bench] workload {wl.name} dims {tuple(spec.dims)} L={spec.n_levels} {spec.dtype}",
+          file=sys.stderr, flush=True)
+    ctx, theta = configs.build(wl)
+    a, b = theta, ctx.new_pack()
+    m, v = ctx.new_pack(), ctx.new_pack()
+    terms = torch.empty((spec.batch, 5), dtype=torch.float64, device=ctx.device)
+    step = 0
+
+    def run(n):
+        nonlocal a, b, step
+        for _ in range(n):
+            step += 1
+            ctx.step(a, b, m, v, step, lr=wl.lr, terms=terms)
+            a, b = b, a
+
+    run(args.warmup)
+    torch.cuda.synchronize()
+    ctx.check()
+    # plain timed region
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(ctx.stream)
+    run(args.steps)
+    e1.record(ctx.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    ctx.check()
+    print(f"[bench] {args.steps} steps in {ms:.3f} ms", file=sys.stderr, flush=True)
+    # per-kernel-class durations (HIP events on the library stream)
+    ctx.profile(True)
+    for k in range(len(CLASSES)):
+        ctx.profile_read(k)
+    e0.record(ctx.stream)
+    run(args.steps)
+    e1.record(ctx.stream)
+    torch.cuda.synchronize()
+    ms_prof = e0.elapsed_time(e1)
+    kern = {}
+    for k, name in enumerate(CLASSES):
+        tot, cnt = ctx.profile_read(k)
+        kern[name] = {"total_ms": tot, "launches": cnt, "avg_ms": tot / max(cnt, 1)}
+    ctx.profile(False)
+    fused = spec.op == "ns3d" and all(f < 4 for _, f, _, _, _, _ in wl.meas)
+    ab = alg_bytes(ctx, spec, fused)
+    dom = max(CLASSES, key=lambda n: kern[n]["total_ms"])
+    avg_s = kern[dom]["avg_ms"] * 1e-3
+    achieved = ab[dom] / avg_s / 1e9 if avg_s > 0 else 0.0
+    ms_step = ms / args.steps
+    value = spec.fine_cells * spec.batch * args.steps / (ms * 1e-3)
+    it_gbs = ab["iteration"] / (ms_step * 1e-3) / 1e9
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=ctx.device)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+    cpu = None
+    if args.cpu_seconds > 0:
+        print("[bench] oracle CPU baseline ...", file=sys.stderr, flush=True)
+        lv = [[x.detach().cpu().double().numpy() for x in row] for row in ctx.level_views(theta, 0)]
+        cpu = oracle_baseline(wl, lv, args.cpu_seconds)
+    out = {
+        "metric": "fine-grid cell-iters/s",
+        "value": value,
+        "unit": "cell-iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": spec.dtype,
+        "data": "synthetic",
+        "config": {"workload": wl.name, "grid": "x".join(str(d) for d in spec.dims),
+                   "levels": spec.n_levels, "fields": len(spec.fields), "params": int(ctx.lay.total),
+                   "batch": spec.batch, "optimizer": "adam", "loss_reduction": "f64"},
+        "hbm_gbs_algorithmic": it_gbs,
+        "iteration_roofline_frac": it_gbs / HBM_PEAK_GBS,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "bytes_per_launch": ab[dom], "avg_launch_ms": kern[dom]["avg_ms"],
+                     "traffic": measured_traffic(wl.name, dom)},
+        "kernels": kern,
+        "fused_fine_kernel": fused,
+        "ms_per_step_profiled": ms_prof / args.steps,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -230,6 +230,13 @@ int modil_step(modil_ctx *ctx, const void *theta_in, void *theta_out, void *m, v
                const modil_adam_hp *hp, int64_t step, double *terms);
 int modil_residual_metric(modil_ctx *ctx, const void *theta_pack, double *r);
 
+/* ---- options --------------------------------------------------------------
+ * MODIL_OPT_FUSED (default 1): use the fused finest-level kernel where one
+ * exists (NS3D with measurements on velocity / pressure only); 0 selects the
+ * generic stencil engine.  Both compute the same iteration.               */
+#define MODIL_OPT_FUSED 0
+int modil_set_option(modil_ctx *ctx, int32_t option, int64_t value);
+
 /* ---- health and timing ---------------------------------------------------
  * modil_check: synchronises the stream; returns MODIL_ERR_NONFINITE if a
  * loss term computed since the last check was NaN or Inf (and clears the

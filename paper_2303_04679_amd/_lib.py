@@ -19,6 +19,7 @@ TERM_PDE, TERM_DATA, TERM_REG, TERM_IC, TERM_BC = 0, 1, 2, 3, 4
 N_TERMS = 5
 FIELD_FORCING0, FIELD_CHI = 0, 4
 SCALAR_RE = 0
+OPT_FUSED = 0
 MAX_LEVELS, MAX_FIELDS = 8, 5
 TERM_NAMES = ("pde", "data", "reg", "ic", "bc")
 
@@ -90,6 +91,7 @@ _SIGS = {
     "modil_step": (_I, [_P, _P, _P, _P, _P, ctypes.POINTER(AdamHP), ctypes.c_int64, _P]),
     "modil_residual_metric": (_I, [_P, _P, _P]),
     "modil_check": (_I, [_P]),
+    "modil_set_option": (_I, [_P, ctypes.c_int32, ctypes.c_int64]),
     "modil_profile": (_I, [_P, ctypes.c_int32]),
     "modil_profile_read": (_I, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                 ctypes.POINTER(ctypes.c_int64)]),

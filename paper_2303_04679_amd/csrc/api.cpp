@@ -57,6 +57,8 @@ int expected_ndim(int op) {
   }
 }
 
+void fill_layout(const modil_problem &p, modil_pack_layout &L);
+
 int validate(const modil_problem *p, std::string &msg) {
   if (!p) { msg = "problem is NULL"; return MODIL_ERR_INVALID_ARG; }
   if (p->op < MODIL_OP_POISSON || p->op > MODIL_OP_CAVITY) {
@@ -99,6 +101,14 @@ int validate(const modil_problem *p, std::string &msg) {
     msg = "grid too large for 32-bit measurement indices";
     return MODIL_ERR_SHAPE;
   }
+  {
+    modil_pack_layout L;
+    fill_layout(*p, L);
+    if (L.total > (1L << 31) - 1 || (long)p->batch * L.fine_cells > (1L << 31) - 1) {
+      msg = "parameter pack too large for 32-bit indexing";
+      return MODIL_ERR_SHAPE;
+    }
+  }
   if (p->batch < 1 || p->batch > 65535) {
     msg = "batch must be in 1..65535";
     return MODIL_ERR_INVALID_ARG;
@@ -123,9 +133,21 @@ int validate(const modil_problem *p, std::string &msg) {
 }
 
 struct Carve {
-  size_t w, g, gq, partials, terms, flag, m_idx, m_field, m_term, m_ptr, m_val, m_w, inst_re, end;
-  long n_fine_blocks, n_data_blocks;
+  size_t w, g, gq, partials, terms, flag, m_idx, m_field, m_term, m_ptr, m_val, m_w, inst_re;
+  size_t fm_ptr, fm_field, fm_idx, fm_term, fm_val, fm_w, end;
+  long n_fine_blocks, n_data_blocks, n_keys;
 };
+
+// per-instance partial-sum slots of the fused channel-flow kernel and its
+// measurement buckets (0 for other operators)
+void fused_geometry(const modil_problem &p, long &blocks, long &keys) {
+  blocks = keys = 0;
+  if (p.op != MODIL_OP_NS3D) return;
+  int tz, nzt, ntx, nty, ox, oy;
+  ns3d_tiles(p, tz, nzt, ntx, nty, ox, oy);
+  blocks = (long)nzt * ntx * nty;
+  keys = (long)p.batch * blocks * tz;
+}
 
 Carve carve(const modil_problem &p, const modil_pack_layout &L) {
   Carve c{};
@@ -136,7 +158,10 @@ Carve carve(const modil_problem &p, const modil_pack_layout &L) {
     off = align256(off + bytes);
     return at;
   };
-  c.n_fine_blocks = (long)((L.fine_cells + kBlock - 1) / kBlock);
+  long fused_blocks, fused_keys;
+  fused_geometry(p, fused_blocks, fused_keys);
+  c.n_fine_blocks = std::max<long>((long)((L.fine_cells + kBlock - 1) / kBlock), fused_blocks);
+  c.n_keys = fused_keys;
   c.n_data_blocks = std::max<long>(1, (p.max_meas + kBlock - 1) / kBlock);
   const long nl = p.n_levels;
   c.w = take(nl >= 2 ? (size_t)L.level_offset[nl - 1] * ts : 0);
@@ -155,6 +180,13 @@ Carve carve(const modil_problem &p, const modil_pack_layout &L) {
   c.m_val = take(mm * 8);
   c.m_w = take(mm * 8);
   c.inst_re = take((size_t)p.batch * 8);
+  const size_t fm = fused_keys ? mm : 0;
+  c.fm_ptr = take(fused_keys ? ((size_t)fused_keys + 1) * 4 : 0);
+  c.fm_field = take(fm * 4);
+  c.fm_idx = take(fm * 4);
+  c.fm_term = take(fm * 4);
+  c.fm_val = take(fm * 8);
+  c.fm_w = take(fm * 8);
   c.end = off;
   return c;
 }
@@ -238,44 +270,89 @@ int upload_measurements(modil_ctx *c) {
   }
   HIP_OR_RETURN(c, hipMemcpyAsync(c->m_inst_ptr, ptr.data(), ptr.size() * 4, hipMemcpyHostToDevice, s),
                 "upload");
+  // buckets of the fused channel-flow kernel: key = (tile, plane within the z-chunk)
+  c->fused_ok = false;
+  std::vector<int32_t> fptr, fidx, ffld, ftrm;
+  std::vector<double> fval, fw;
+  if (c->prob.op == MODIL_OP_NS3D) {
+    int tz, nzt, ntx, nty, ox, oy;
+    ns3d_tiles(c->prob, tz, nzt, ntx, nty, ox, oy);
+    const int nz = c->prob.dims[0], ny = c->prob.dims[1], nx = c->prob.dims[2];
+    (void)nz;
+    std::vector<std::pair<long, size_t>> order(n);
+    bool ok = true;
+    for (size_t k = 0; k < n; ++k) {
+      const int cell = m[k].idx, x = cell % nx, y = (cell / nx) % ny, z = cell / (nx * ny);
+      const long tile = (((long)m[k].inst * nzt + z / tz) * nty + y / oy) * ntx + x / ox;
+      order[k] = {tile * tz + z % tz, k};
+      ok = ok && m[k].field < 4;
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [](const std::pair<long, size_t> &a, const std::pair<long, size_t> &b) {
+                       return a.first < b.first;
+                     });
+    const long keys = (long)c->prob.batch * nzt * ntx * nty * tz;
+    fptr.assign(keys + 1, 0);
+    for (size_t k = 0; k < n; ++k) {
+      const Meas &e = m[order[k].second];
+      fidx.push_back(e.idx);
+      ffld.push_back(e.field);
+      ftrm.push_back(e.term);
+      fval.push_back(e.val);
+      fw.push_back(e.w);
+      fptr[order[k].first + 1]++;
+    }
+    for (long k = 0; k < keys; ++k) fptr[k + 1] += fptr[k];
+    HIP_OR_RETURN(c, hipMemcpyAsync(c->fm_ptr, fptr.data(), fptr.size() * 4, hipMemcpyHostToDevice, s), "upload");
+    if (n) {
+      HIP_OR_RETURN(c, hipMemcpyAsync(c->fm_idx, fidx.data(), n * 4, hipMemcpyHostToDevice, s), "upload");
+      HIP_OR_RETURN(c, hipMemcpyAsync(c->fm_field, ffld.data(), n * 4, hipMemcpyHostToDevice, s), "upload");
+      HIP_OR_RETURN(c, hipMemcpyAsync(c->fm_term, ftrm.data(), n * 4, hipMemcpyHostToDevice, s), "upload");
+      HIP_OR_RETURN(c, hipMemcpyAsync(c->fm_val, fval.data(), n * 8, hipMemcpyHostToDevice, s), "upload");
+      HIP_OR_RETURN(c, hipMemcpyAsync(c->fm_w, fw.data(), n * 8, hipMemcpyHostToDevice, s), "upload");
+    }
+    for (double re : c->inst_re_host) ok = ok && re == c->prob.re;
+    c->fused_ok = ok;
+  }
   HIP_OR_RETURN(c, hipStreamSynchronize(s), "upload");
   c->n_meas_dev = (int)n;
   return MODIL_OK;
 }
 
-// Horner prolongation of every level; returns the fine field (level 0).
-int horner(modil_ctx *c, const void *theta, const void **fine, void *last_dst = nullptr) {
-  const int L = c->prob.n_levels;
-  if (L == 1) {
-    *fine = theta;
+bool use_fused(const modil_ctx *c) {
+  return c->fused_enabled && c->fused_ok && c->prob.op == MODIL_OP_NS3D;
+}
+
+// Loss terms at theta; with grad the gradient of every level; with adam
+// also one Adam step theta -> th_out on every level.
+int evaluate(modil_ctx *c, const void *theta, void *grad, double *terms, const AdamHost *adam = nullptr,
+             void *th_out = nullptr, void *m = nullptr, void *v = nullptr) {
+  const bool want = grad != nullptr;
+  if (use_fused(c) && want) {
+    {
+      Timed t(c, 1);
+      HIP_OR_RETURN(c, launch_horner(c, theta, nullptr, true), "prolong");
+    }
+    {
+      Timed t(c, 0);
+      HIP_OR_RETURN(c, launch_ns3d_fused(c, theta, grad, adam, th_out, m, v), "fused kernel");
+    }
+    {
+      Timed t(c, 2);
+      HIP_OR_RETURN(c, launch_restrict_chain(c, grad, 0, theta, th_out, m, v, adam), "restrict");
+    }
+    long blocks, keys;
+    fused_geometry(c->prob, blocks, keys);
+    Timed t(c, 4);
+    HIP_OR_RETURN(c, launch_reduce(c, terms, blocks, 0, 0), "reduce");
     return MODIL_OK;
   }
-  Timed t(c, 1);
-  for (int l = L - 2; l >= 0; --l) {
-    const void *src = (l == L - 2) ? theta : c->w_buf;
-    void *dst = (l == 0 && last_dst) ? last_dst : c->w_buf;
-    const long doff = (l == 0 && last_dst) ? 0 : c->lay.level_offset[l];
-    HIP_OR_RETURN(c, launch_prolong_level(c, theta, src, c->lay.level_offset[l + 1], dst, doff, l),
-                  "prolong");
+  const void *u = theta;
+  if (c->prob.n_levels > 1) {
+    Timed t(c, 1);
+    HIP_OR_RETURN(c, launch_horner(c, theta, nullptr, false), "prolong");
+    u = c->w_buf;
   }
-  *fine = last_dst ? last_dst : c->w_buf;
-  return MODIL_OK;
-}
-
-int restrict_chain(modil_ctx *c, void *grad) {
-  Timed t(c, 2);
-  for (int l = 0; l + 1 < c->prob.n_levels; ++l)
-    HIP_OR_RETURN(c, launch_restrict_level(c, grad, c->lay.level_offset[l], grad,
-                                           c->lay.level_offset[l + 1], l),
-                  "restrict");
-  return MODIL_OK;
-}
-
-int evaluate(modil_ctx *c, const void *theta, void *grad, double *terms) {
-  const void *u = nullptr;
-  int st = horner(c, theta, &u);
-  if (st) return st;
-  const bool want = grad != nullptr;
   {
     Timed t(c, 0);
     HIP_OR_RETURN(c, launch_fine(c, u, grad, want), "fine kernel");
@@ -286,11 +363,20 @@ int evaluate(modil_ctx *c, const void *theta, void *grad, double *terms) {
     HIP_OR_RETURN(c, launch_data(c, u, grad, want), "data kernel");
   }
   if (want) {
-    st = restrict_chain(c, grad);
-    if (st) return st;
+    Timed t(c, 2);
+    HIP_OR_RETURN(c, launch_restrict_chain(c, grad, 0, nullptr, nullptr, nullptr, nullptr, nullptr),
+                  "restrict");
   }
-  Timed t(c, 4);
-  HIP_OR_RETURN(c, launch_reduce(c, terms), "reduce");
+  {
+    Timed t(c, 4);
+    const long generic_blocks = (long)((c->lay.fine_cells + kBlock - 1) / kBlock);
+    HIP_OR_RETURN(c, launch_reduce(c, terms, generic_blocks, c->n_fine_blocks, c->n_data_blocks),
+                  "reduce");
+  }
+  if (adam) {
+    Timed t(c, 3);
+    HIP_OR_RETURN(c, launch_adam(c, theta, th_out, m, v, grad, c->lay.total, *adam), "adam");
+  }
   return MODIL_OK;
 }
 
@@ -409,6 +495,12 @@ int modil_create(const modil_problem *p, void *ws, size_t ws_bytes, void *stream
   c->m_val = (double *)(c->ws + cv.m_val);
   c->m_w = (double *)(c->ws + cv.m_w);
   c->inst_re = (double *)(c->ws + cv.inst_re);
+  c->fm_ptr = (int32_t *)(c->ws + cv.fm_ptr);
+  c->fm_field = (int32_t *)(c->ws + cv.fm_field);
+  c->fm_idx = (int32_t *)(c->ws + cv.fm_idx);
+  c->fm_term = (int32_t *)(c->ws + cv.fm_term);
+  c->fm_val = (double *)(c->ws + cv.fm_val);
+  c->fm_w = (double *)(c->ws + cv.fm_w);
   c->n_fine_blocks = cv.n_fine_blocks;
   c->n_data_blocks = cv.n_data_blocks;
   c->n_part_blocks = cv.n_fine_blocks + cv.n_data_blocks;
@@ -499,6 +591,10 @@ int modil_set_instance_scalar(modil_ctx *c, int32_t inst, int32_t which, double 
   if (inst < 0 || inst >= c->prob.batch) return fail(c, MODIL_ERR_INVALID_ARG, "instance out of range");
   if (which != MODIL_SCALAR_RE || !(value > 0.0)) return fail(c, MODIL_ERR_INVALID_ARG, "bad scalar");
   c->inst_re_host[inst] = value;
+  if (c->prob.op == MODIL_OP_NS3D) {
+    int st = upload_measurements(c);  // re-evaluates whether the fused kernel applies
+    if (st) return st;
+  }
   HIP_OR_RETURN(c, hipMemcpyAsync(c->inst_re, c->inst_re_host.data(), c->prob.batch * 8,
                                   hipMemcpyHostToDevice, c->stream),
                 "set scalar");
@@ -523,8 +619,8 @@ int modil_prolong(modil_ctx *c, const void *theta, void *fine_out) {
                   "prolong copy");
     return MODIL_OK;
   }
-  const void *u = nullptr;
-  return horner(c, theta, &u, fine_out);
+  HIP_OR_RETURN(c, launch_horner(c, theta, fine_out, false), "prolong");
+  return MODIL_OK;
 }
 
 int modil_restrict_adjoint(modil_ctx *c, const void *fine_in, void *grad) {
@@ -534,7 +630,9 @@ int modil_restrict_adjoint(modil_ctx *c, const void *fine_in, void *grad) {
   HIP_OR_RETURN(c, hipMemcpyAsync(grad, fine_in, c->lay.fine_total * dtype_size(c->prob),
                                   hipMemcpyDeviceToDevice, c->stream),
                 "restrict copy");
-  return restrict_chain(c, grad);
+  HIP_OR_RETURN(c, launch_restrict_chain(c, grad, 0, nullptr, nullptr, nullptr, nullptr, nullptr),
+                "restrict");
+  return MODIL_OK;
 }
 
 int modil_loss(modil_ctx *c, const void *theta, double *terms) {
@@ -560,15 +658,11 @@ static int check_hp(modil_ctx *c, const modil_adam_hp *hp, int64_t step) {
   return MODIL_OK;
 }
 
-static int adam_all(modil_ctx *c, const void *th_in, void *th_out, void *m, void *v, const void *g,
-                    const modil_adam_hp *hp, int64_t step) {
+// bias corrections of step t folded into the step size and the v scale (FP64 on the host)
+static AdamHost adam_host(const modil_adam_hp *hp, int64_t step) {
   const double bc1 = 1.0 - std::pow(hp->beta1, (double)step);
   const double bc2 = 1.0 - std::pow(hp->beta2, (double)step);
-  Timed t(c, 3);
-  HIP_OR_RETURN(c, launch_adam(c, th_in, th_out, m, v, g, c->lay.total, hp->lr, hp->beta1,
-                               hp->beta2, hp->eps, bc1, bc2),
-                "adam");
-  return MODIL_OK;
+  return AdamHost{hp->beta1, hp->beta2, hp->lr / bc1, 1.0 / std::sqrt(bc2), hp->eps};
 }
 
 int modil_adam(modil_ctx *c, const void *th_in, void *th_out, void *m, void *v, const void *g,
@@ -577,7 +671,9 @@ int modil_adam(modil_ctx *c, const void *th_in, void *th_out, void *m, void *v, 
   int st = check_hp(c, hp, step);
   if (st) return st;
   if (!th_in || !th_out || !m || !v || !g) return fail(c, MODIL_ERR_INVALID_ARG, "NULL pointer");
-  return adam_all(c, th_in, th_out, m, v, g, hp, step);
+  Timed t(c, 3);
+  HIP_OR_RETURN(c, launch_adam(c, th_in, th_out, m, v, g, c->lay.total, adam_host(hp, step)), "adam");
+  return MODIL_OK;
 }
 
 int modil_step(modil_ctx *c, const void *th_in, void *th_out, void *m, void *v,
@@ -588,9 +684,8 @@ int modil_step(modil_ctx *c, const void *th_in, void *th_out, void *m, void *v,
   if (st) return st;
   if (!th_in || !th_out || !m || !v) return fail(c, MODIL_ERR_INVALID_ARG, "NULL pointer");
   if (th_in == th_out) return fail(c, MODIL_ERR_INVALID_ARG, "theta_out must differ from theta_in");
-  st = evaluate(c, th_in, c->g_buf, terms ? terms : c->terms_tmp);
-  if (st) return st;
-  return adam_all(c, th_in, th_out, m, v, c->g_buf, hp, step);
+  const AdamHost ah = adam_host(hp, step);
+  return evaluate(c, th_in, c->g_buf, terms ? terms : c->terms_tmp, &ah, th_out, m, v);
 }
 
 int modil_residual_metric(modil_ctx *c, const void *theta, double *r) {
@@ -601,6 +696,15 @@ int modil_residual_metric(modil_ctx *c, const void *theta, double *r) {
   if (st) return st;
   HIP_OR_RETURN(c, launch_metric(c, c->terms_tmp, r), "metric");
   return MODIL_OK;
+}
+
+int modil_set_option(modil_ctx *c, int32_t option, int64_t value) {
+  if (!c) return fail_global(MODIL_ERR_INVALID_ARG, "ctx is NULL");
+  if (option == MODIL_OPT_FUSED) {
+    c->fused_enabled = value != 0;
+    return MODIL_OK;
+  }
+  return fail(c, MODIL_ERR_INVALID_ARG, "unknown option");
 }
 
 int modil_check(modil_ctx *c) {

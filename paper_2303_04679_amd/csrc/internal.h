@@ -43,6 +43,23 @@ struct FineFields {
   long inst_stride;     // elements of all fields of one instance
 };
 
+// Geometry of every level of a parameter pack, 32-bit (validated to fit).
+struct Levels {
+  int L, nf, batch;
+  int off[kMaxL];          // pack offset of level l
+  int stride[kMaxL];       // elements of one instance on level l
+  int foff[kMaxL][kMaxF];  // field offsets inside one instance
+  int n[kMaxL][kMaxF][3];  // cells per axis (z, y, x) of every field
+};
+
+// Adam on pack elements: theta_out[e] = theta_in[e] - step * m / (sqrt(v) * isb2 + eps)
+template <typename T>
+struct AdamArgs {
+  const T *th_in;
+  T *th_out, *m, *v;
+  T b1, b2, step, isb2, eps;
+};
+
 struct Meas {
   int32_t inst, field, term, idx;
   double val, w;
@@ -81,6 +98,12 @@ struct modil_ctx {
   double *m_val = nullptr, *m_w = nullptr;
   double *inst_re = nullptr;
 
+  // measurements bucketed per (tile, plane) for the fused channel-flow kernel
+  int32_t *fm_ptr = nullptr, *fm_field = nullptr, *fm_idx = nullptr, *fm_term = nullptr;
+  double *fm_val = nullptr, *fm_w = nullptr;
+  bool fused_enabled = true;  // MODIL_OPT_FUSED
+  bool fused_ok = false;      // measurements admit the fused kernel
+
   long n_fine_blocks = 0;   // partial blocks of the fine kernel per instance
   long n_data_blocks = 0;   // partial blocks of the data kernel per instance
   long n_part_blocks = 0;   // n_fine_blocks + n_data_blocks
@@ -106,19 +129,31 @@ int op_pde_equations(const modil_problem &p);
 bool field_is_x_only(const modil_problem &p, int f);
 FieldGeom field_geom(const modil_problem &p, int level, int f);
 
-// kernel launchers (kernels_*.hip); all enqueue on ctx->stream and return
-// hipSuccess or the launch error.
-hipError_t launch_prolong_level(modil_ctx *c, const void *theta, const void *coarse_src,
-                                long coarse_off, void *dst, long dst_off, int level);
-hipError_t launch_restrict_level(modil_ctx *c, const void *fine_src, long fine_off, void *dst,
-                                 long dst_off, int level);
+Levels levels_of(const modil_ctx *c);
+
+// Adam hyper-parameters as passed to the kernels (bias corrections folded in)
+struct AdamHost {
+  double b1, b2, step, isb2, eps;
+};
+
+// kernel launchers (kernels.hip, ns3d_fused.hip); all enqueue on ctx->stream
+// and return hipSuccess or the launch error.
+// Horner chain: w_l for every coarse level into w_buf and the finest field
+// into fine_dst (w_buf level 0 if null); stops at level 1 when skip_fine.
+hipError_t launch_horner(modil_ctx *c, const void *theta, void *fine_dst, bool skip_fine);
+// g_{l+1} = T^T g_l for l >= from_level (pack layout in g); with adam also
+// Adam on every level it produces.
+hipError_t launch_restrict_chain(modil_ctx *c, void *g, int from_level, const void *th_in,
+                                 void *th_out, void *m, void *v, const AdamHost *adam);
 hipError_t launch_adam(modil_ctx *c, const void *theta_in, void *theta_out, void *m, void *v,
-                       const void *g, long n, double lr, double b1, double b2, double eps,
-                       double bc1, double bc2);
+                       const void *g, long n, const AdamHost &h);
 hipError_t launch_fine(modil_ctx *c, const void *u, void *g, bool want_grad);
 hipError_t launch_colsum(modil_ctx *c, void *g_fine);
 hipError_t launch_data(modil_ctx *c, const void *u, void *g, bool want_grad);
-hipError_t launch_reduce(modil_ctx *c, double *terms);
+hipError_t launch_reduce(modil_ctx *c, double *terms, long n_a, long off_b, long n_b);
+hipError_t launch_ns3d_fused(modil_ctx *c, const void *theta, void *g, const AdamHost *adam,
+                             void *th_out, void *m, void *v);
+void ns3d_tiles(const modil_problem &P, int &tz, int &nzt, int &ntx, int &nty, int &ox, int &oy);
 hipError_t launch_metric(modil_ctx *c, const double *terms, double *r);
 
 }  // namespace modil

@@ -17,125 +17,204 @@
 #include <cmath>
 
 #include "internal.h"
+#include "multigrid.h"
 #include "ops.h"
 
 namespace modil {
 
 // ---------------------------------------------------------------- geometry
-struct LevelGeom {
-  int nf;
-  long inst_stride;     // elements of one instance on this level
-  long foff[kMaxF];     // field offsets inside one instance
-  int n[kMaxF][3];      // cells per axis of every field (1 where not spanned)
-};
-
-static LevelGeom level_geom(const modil_ctx *c, int level) {
-  LevelGeom g{};
-  g.nf = c->lay.n_fields;
-  g.inst_stride = c->lay.level_stride[level];
-  for (int f = 0; f < g.nf; ++f) {
-    g.foff[f] = c->lay.field_offset[level][f];
-    for (int a = 0; a < 3; ++a) g.n[f][a] = c->lay.field_dims[level][f][a];
-  }
-  return g;
-}
-
-__device__ inline void locate(const LevelGeom &g, long e, int &inst, int &f, int (&i)[3]) {
-  inst = (int)(e / g.inst_stride);
-  long rem = e - (long)inst * g.inst_stride;
+// 32-bit geometry of every level (pack sizes are validated to fit in int32).
+__device__ inline void locate(const Levels &G, int l, int e, int &inst, int &f, int (&i)[3]) {
+  inst = e / G.stride[l];
+  int rem = e - inst * G.stride[l];
   f = 0;
-  for (int k = 1; k < g.nf; ++k)
-    if (rem >= g.foff[k]) f = k;
-  long cell = rem - g.foff[f];
-  i[2] = (int)(cell % g.n[f][2]);
-  cell /= g.n[f][2];
-  i[1] = (int)(cell % g.n[f][1]);
-  i[0] = (int)(cell / g.n[f][1]);
+  for (int k = 1; k < G.nf; ++k)
+    if (rem >= G.foff[l][k]) f = k;
+  int cell = rem - G.foff[l][f];
+  const int nx = G.n[l][f][2], ny = G.n[l][f][1];
+  i[2] = cell % nx;
+  cell /= nx;
+  i[1] = cell % ny;
+  i[0] = cell / ny;
 }
 
-// 1-D taps of the cell-based T: fine cell i of 2n fine cells from n coarse.
-__device__ inline int prolong_taps(int i, int n, int (&idx)[2], double (&w)[2]) {
-  const int J = i >> 1;
-  const int nb = (i & 1) ? J + 1 : J - 1;
-  if (nb < 0) {
-    idx[0] = J; w[0] = 1.25; idx[1] = J + 1; w[1] = -0.25;
-  } else if (nb >= n) {
-    idx[0] = J; w[0] = 1.25; idx[1] = J - 1; w[1] = -0.25;
-  } else {
-    idx[0] = J; w[0] = 0.75; idx[1] = nb; w[1] = 0.25;
+// (T w)(i) of field f at fine level l from the level-(l+1) array base cb
+template <typename T>
+__device__ inline T prolong_value(const Levels &G, int l, int inst, int f, const int (&i)[3],
+                                  const T *__restrict__ cbase) {
+  const T *cb = cbase + inst * G.stride[l + 1] + G.foff[l + 1][f];
+  const int cnx = G.n[l + 1][f][2], cny = G.n[l + 1][f][1];
+  const int sy = cnx, sz = cny * cnx;
+  const bool span_z = G.n[l][f][0] != G.n[l + 1][f][0];
+  const bool span_y = G.n[l][f][1] != cny;
+  int ix[2], iy[2], iz[2];
+  T wx[2], wy[2], wz[2];
+  prolong_taps(i[2], cnx, ix, wx);
+  if (span_y) prolong_taps(i[1], cny, iy, wy);
+  if (span_z) prolong_taps(i[0], G.n[l + 1][f][0], iz, wz);
+  if (span_z && span_y) {  // 3-D: eight taps
+    T acc = T(0);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        acc += wz[a] * wy[b] * (wx[0] * cb[iz[a] * sz + iy[b] * sy + ix[0]] +
+                                wx[1] * cb[iz[a] * sz + iy[b] * sy + ix[1]]);
+    return acc;
   }
-  return 2;
+  const int zoff = i[0] * sz;  // unspanned z keeps the index
+  if (span_y) {
+    return wy[0] * (wx[0] * cb[zoff + iy[0] * sy + ix[0]] + wx[1] * cb[zoff + iy[0] * sy + ix[1]]) +
+           wy[1] * (wx[0] * cb[zoff + iy[1] * sy + ix[0]] + wx[1] * cb[zoff + iy[1] * sy + ix[1]]);
+  }
+  const int yoff = zoff + i[1] * sy;
+  return wx[0] * cb[yoff + ix[0]] + wx[1] * cb[yoff + ix[1]];
 }
 
-// 1-D taps of T^T: coarse cell J of n coarse cells gathers from 2n fine.
-__device__ inline int restrict_taps(int J, int n, int (&idx)[6], double (&w)[6]) {
-  int k = 0;
-  if (J >= 1) { idx[k] = 2 * J - 1; w[k++] = 0.25; }
-  idx[k] = 2 * J; w[k++] = (J == 0) ? 1.25 : 0.75;
-  idx[k] = 2 * J + 1; w[k++] = (J == n - 1) ? 1.25 : 0.75;
-  if (J <= n - 2) { idx[k] = 2 * J + 2; w[k++] = 0.25; }
-  if (J == 1) { idx[k] = 0; w[k++] = -0.25; }
-  if (J == n - 2) { idx[k] = 2 * n - 1; w[k++] = -0.25; }
-  return k;
+// (T^T g)(I) of field f at coarse level l+1 from the level-l array base fb.
+// Column J of T is a window of four contiguous fine cells plus, for coarse
+// cells next to a wall, the extrapolated end cells (restrict_taps6, six
+// slots with zero weights where unused).  Along x, which varies across a
+// wave, all six slots are loaded unconditionally; the 4 x 4 window rows in
+// y and z are summed unconditionally too, so a thread issues all its loads
+// before it waits.  The end-cell rows in y and z sit in one branch that is
+// uniform across a wave running along x.
+template <typename T>
+__device__ inline T restrict_value(const Levels &G, int l, int inst, int f, const int (&I)[3],
+                                   const T *__restrict__ fbase) {
+  const T *fb = fbase + inst * G.stride[l] + G.foff[l][f];
+  const int sy = G.n[l][f][2], sz = G.n[l][f][1] * sy;
+  const bool span_z = G.n[l][f][0] != G.n[l + 1][f][0];
+  const bool span_y = G.n[l][f][1] != G.n[l + 1][f][1];
+  int iz[6], iy[6], ix[6];
+  T wz[6], wy[6], wx[6];
+  if (span_z) {
+    restrict_taps6(I[0], G.n[l + 1][f][0], iz, wz);
+  } else {
+    for (int k = 0; k < 6; ++k) { iz[k] = I[0]; wz[k] = T(k == 0); }
+  }
+  if (span_y) {
+    restrict_taps6(I[1], G.n[l + 1][f][1], iy, wy);
+  } else {
+    for (int k = 0; k < 6; ++k) { iy[k] = I[1]; wy[k] = T(k == 0); }
+  }
+  restrict_taps6(I[2], G.n[l + 1][f][2], ix, wx);
+  auto row6 = [&](int zz, int yy) {
+    const T *r = fb + zz * sz + yy * sy;
+    return wx[0] * r[ix[0]] + wx[1] * r[ix[1]] + wx[2] * r[ix[2]] + wx[3] * r[ix[3]] +
+           wx[4] * r[ix[4]] + wx[5] * r[ix[5]];
+  };
+  T acc = T(0);
+  if (span_z) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      T pl = T(0);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) pl += wy[b] * row6(iz[a], iy[b]);
+      acc += wz[a] * pl;
+    }
+    if (wy[4] != T(0) || wy[5] != T(0) || wz[4] != T(0) || wz[5] != T(0)) {
+#pragma unroll
+      for (int a = 0; a < 6; ++a)
+#pragma unroll
+        for (int b = 0; b < 6; ++b)
+          if (a >= 4 || b >= 4) acc += wz[a] * wy[b] * row6(iz[a], iy[b]);
+    }
+  } else if (span_y) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc += wy[b] * row6(iz[0], iy[b]);
+    if (wy[4] != T(0) || wy[5] != T(0)) acc += wy[4] * row6(iz[0], iy[4]) + wy[5] * row6(iz[0], iy[5]);
+  } else {
+    acc = row6(iz[0], iy[0]);
+  }
+  return acc;
+}
+
+template <typename T>
+__device__ inline void adam_elem(const AdamArgs<T> &A, int e, T g) {
+  const T mm = A.b1 * A.m[e] + (T(1) - A.b1) * g;
+  const T vv = A.b2 * A.v[e] + (T(1) - A.b2) * g * g;
+  A.m[e] = mm;
+  A.v[e] = vv;
+  A.th_out[e] = A.th_in[e] - A.step * mm / (sqrt(vv) * A.isb2 + A.eps);
+}
+
+// Adam with the old state already loaded (lets the loads overlap the gather)
+template <typename T>
+__device__ inline void adam_elem_loaded(const AdamArgs<T> &A, int e, T g, T th, T m, T v) {
+  const T mm = A.b1 * m + (T(1) - A.b1) * g;
+  const T vv = A.b2 * v + (T(1) - A.b2) * g * g;
+  A.m[e] = mm;
+  A.v[e] = vv;
+  A.th_out[e] = th - A.step * mm / (sqrt(vv) * A.isb2 + A.eps);
 }
 
 // ------------------------------------------------------------- prolongation
+// w_l = theta_l + T w_{l+1}; csrc points at the level-(l+1) source array
 template <typename T>
-__global__ __launch_bounds__(kBlock) void prolong_level_kernel(
-    LevelGeom fine, LevelGeom coarse, const T *__restrict__ theta_l, const T *__restrict__ csrc,
-    T *__restrict__ dst, long total) {
-  const long e = (long)blockIdx.x * kBlock + threadIdx.x;
+__global__ __launch_bounds__(kBlock) void prolong_kernel(Levels G, int l, const T *__restrict__ theta,
+                                                         const T *__restrict__ csrc, T *__restrict__ dst) {
+  const int total = G.stride[l] * G.batch;
+  const int e = blockIdx.x * kBlock + threadIdx.x;
   if (e >= total) return;
+  const T th = theta[G.off[l] + e];
   int inst, f, i[3];
-  locate(fine, e, inst, f, i);
-  int ti[3][2];
-  double tw[3][2];
-  int nt[3];
-  for (int a = 0; a < 3; ++a) {
-    if (fine.n[f][a] == coarse.n[f][a]) {  // axis not spanned by this field
-      ti[a][0] = i[a]; tw[a][0] = 1.0; nt[a] = 1;
-    } else {
-      nt[a] = prolong_taps(i[a], coarse.n[f][a], ti[a], tw[a]);
+  locate(G, l, e, inst, f, i);
+  dst[e] = th + prolong_value(G, l, inst, f, i, csrc);
+}
+
+// all levels l_hi-1 .. l_lo by one block (the small coarse levels); the
+// coarsest source is theta itself; w has the pack layout
+template <typename T>
+__global__ __launch_bounds__(1024) void horner_tail_kernel(Levels G, int l_lo,
+                                                           const T *__restrict__ theta, T *w) {
+  for (int l = G.L - 2; l >= l_lo; --l) {
+    const T *src = (l == G.L - 2) ? theta + G.off[l + 1] : w + G.off[l + 1];
+    const int total = G.stride[l] * G.batch;
+    for (int e = threadIdx.x; e < total; e += blockDim.x) {
+      int inst, f, i[3];
+      locate(G, l, e, inst, f, i);
+      w[G.off[l] + e] = theta[G.off[l] + e] + prolong_value(G, l, inst, f, i, src);
     }
+    __syncthreads();
   }
-  const T *cb = csrc + (long)inst * coarse.inst_stride + coarse.foff[f];
-  const long sy = coarse.n[f][2], sz = (long)coarse.n[f][1] * coarse.n[f][2];
-  T acc = T(0);
-  for (int a = 0; a < nt[0]; ++a)
-    for (int b = 0; b < nt[1]; ++b)
-      for (int d = 0; d < nt[2]; ++d)
-        acc += T(tw[0][a] * tw[1][b] * tw[2][d]) * cb[ti[0][a] * sz + ti[1][b] * sy + ti[2][d]];
-  dst[e] = theta_l[e] + acc;
 }
 
 // --------------------------------------------------------------- restriction
-template <typename T>
-__global__ __launch_bounds__(kBlock) void restrict_level_kernel(
-    LevelGeom fine, LevelGeom coarse, const T *__restrict__ gsrc, T *__restrict__ dst, long total) {
-  const long e = (long)blockIdx.x * kBlock + threadIdx.x;
+// g_{l+1} = T^T g_l (pack layout in g); with ADAM also Adam on level l+1
+template <typename T, bool ADAM>
+__global__ __launch_bounds__(kBlock) void restrict_kernel(Levels G, int l, T *g, AdamArgs<T> A) {
+  const int total = G.stride[l + 1] * G.batch;
+  const int e = blockIdx.x * kBlock + threadIdx.x;
   if (e >= total) return;
-  int inst, f, I[3];
-  locate(coarse, e, inst, f, I);
-  int ti[3][6];
-  double tw[3][6];
-  int nt[3];
-  for (int a = 0; a < 3; ++a) {
-    if (fine.n[f][a] == coarse.n[f][a]) {
-      ti[a][0] = I[a]; tw[a][0] = 1.0; nt[a] = 1;
-    } else {
-      nt[a] = restrict_taps(I[a], coarse.n[f][a], ti[a], tw[a]);
-    }
+  const int k = G.off[l + 1] + e;
+  T th = T(0), m = T(0), v = T(0);
+  if (ADAM) {  // issued before the gather so both latencies overlap
+    th = A.th_in[k];
+    m = A.m[k];
+    v = A.v[k];
   }
-  const T *fb = gsrc + (long)inst * fine.inst_stride + fine.foff[f];
-  const long sy = fine.n[f][2], sz = (long)fine.n[f][1] * fine.n[f][2];
-  T acc = T(0);
-  for (int a = 0; a < nt[0]; ++a)
-    for (int b = 0; b < nt[1]; ++b) {
-      T row = T(0);
-      for (int d = 0; d < nt[2]; ++d) row += T(tw[2][d]) * fb[ti[0][a] * sz + ti[1][b] * sy + ti[2][d]];
-      acc += T(tw[0][a] * tw[1][b]) * row;
+  int inst, f, I[3];
+  locate(G, l + 1, e, inst, f, I);
+  const T val = restrict_value(G, l, inst, f, I, g + G.off[l]);
+  g[k] = val;
+  if (ADAM) adam_elem_loaded(A, k, val, th, m, v);
+}
+
+template <typename T, bool ADAM>
+__global__ __launch_bounds__(1024) void restrict_tail_kernel(Levels G, int l_lo, T *g, AdamArgs<T> A) {
+  for (int l = l_lo; l + 1 < G.L; ++l) {
+    const int total = G.stride[l + 1] * G.batch;
+    for (int e = threadIdx.x; e < total; e += blockDim.x) {
+      int inst, f, I[3];
+      locate(G, l + 1, e, inst, f, I);
+      const T val = restrict_value(G, l, inst, f, I, g + G.off[l]);
+      const int k = G.off[l + 1] + e;
+      g[k] = val;
+      if (ADAM) adam_elem(A, k, val);
     }
-  dst[e] = acc;
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------- Adam
@@ -348,15 +427,17 @@ __global__ __launch_bounds__(kBlock) void data_kernel(
   block_terms(part, partials + ((long)inst * n_part_blocks + first_block + blockIdx.x) * kTerms);
 }
 
-// fixed-order sum of all partial blocks of one instance
+// fixed-order sum of the partial blocks [0, n_a) and [off_b, off_b + n_b) of one instance
 __global__ __launch_bounds__(kBlock) void reduce_kernel(const double *__restrict__ partials,
-                                                        long n_part_blocks, double *terms,
-                                                        int32_t *flag) {
+                                                        long n_part_blocks, long n_a, long off_b,
+                                                        long n_b, double *terms, int32_t *flag) {
   const int inst = blockIdx.x;
   double t[kTerms] = {0.0, 0.0, 0.0, 0.0, 0.0};
   const double *src = partials + (long)inst * n_part_blocks * kTerms;
-  for (long b = threadIdx.x; b < n_part_blocks; b += kBlock)
-    for (int k = 0; k < kTerms; ++k) t[k] += src[b * kTerms + k];
+  for (long b = threadIdx.x; b < n_a + n_b; b += kBlock) {
+    const long slot = b < n_a ? b : off_b + (b - n_a);
+    for (int k = 0; k < kTerms; ++k) t[k] += src[slot * kTerms + k];
+  }
   __shared__ double out[kTerms];
   block_terms(t, out);
   __syncthreads();
@@ -375,49 +456,108 @@ __global__ void metric_kernel(const double *terms, double *r, int batch, double 
 // -------------------------------------------------------------- launchers
 static inline unsigned nblk(long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-hipError_t launch_prolong_level(modil_ctx *c, const void *theta, const void *coarse_src,
-                                long coarse_off, void *dst, long dst_off, int level) {
-  const LevelGeom fg = level_geom(c, level), cg = level_geom(c, level + 1);
-  const long total = fg.inst_stride * c->prob.batch;
-  const long toff = c->lay.level_offset[level];
-  if (c->prob.dtype == MODIL_F64) {
-    prolong_level_kernel<double><<<nblk(total), kBlock, 0, c->stream>>>(
-        fg, cg, (const double *)theta + toff, (const double *)coarse_src + coarse_off,
-        (double *)dst + dst_off, total);
-  } else {
-    prolong_level_kernel<float><<<nblk(total), kBlock, 0, c->stream>>>(
-        fg, cg, (const float *)theta + toff, (const float *)coarse_src + coarse_off,
-        (float *)dst + dst_off, total);
+constexpr long kTailMax = 0;  // coarse levels up to this many values go to one block (off)
+
+Levels levels_of(const modil_ctx *c) {
+  Levels G{};
+  G.L = c->prob.n_levels;
+  G.nf = c->lay.n_fields;
+  G.batch = c->prob.batch;
+  for (int l = 0; l < G.L; ++l) {
+    G.off[l] = (int)c->lay.level_offset[l];
+    G.stride[l] = (int)c->lay.level_stride[l];
+    for (int f = 0; f < G.nf; ++f) {
+      G.foff[l][f] = (int)c->lay.field_offset[l][f];
+      for (int a = 0; a < 3; ++a) G.n[l][f][a] = c->lay.field_dims[l][f][a];
+    }
+  }
+  return G;
+}
+
+// smallest level index l >= 1 such that levels l..L-1 hold at most kTailMax values
+static int tail_level(const Levels &G) {
+  long acc = 0;
+  int l = G.L;
+  while (l - 1 >= 1 && acc + (long)G.stride[l - 1] * G.batch <= kTailMax) {
+    --l;
+    acc += (long)G.stride[l] * G.batch;
+  }
+  return l;  // levels [l, L) are small; l == L means none
+}
+
+template <typename T>
+static hipError_t horner_t(modil_ctx *c, const void *theta_v, void *fine_dst_v, bool skip_fine) {
+  const Levels G = levels_of(c);
+  const T *theta = (const T *)theta_v;
+  T *w = (T *)c->w_buf;
+  T *fine_dst = fine_dst_v ? (T *)fine_dst_v : w;
+  if (G.L == 1) return hipSuccess;
+  const int lt = tail_level(G);  // w_l for l in [lt - 1 ... ] computed by one block down to lt
+  int l = G.L - 2;
+  if (lt <= G.L - 2 && lt >= 1) {
+    // one block computes w_{L-2} .. w_{lt}
+    horner_tail_kernel<T><<<1, 1024, 0, c->stream>>>(G, lt, theta, w);
+    l = lt - 1;
+  }
+  const int l_end = skip_fine ? 1 : 0;
+  for (; l >= l_end; --l) {
+    const T *src = (l == G.L - 2) ? theta + G.off[l + 1] : w + G.off[l + 1];
+    T *dst = (l == 0) ? fine_dst : w + G.off[l];
+    const long total = (long)G.stride[l] * G.batch;
+    prolong_kernel<T><<<nblk(total), kBlock, 0, c->stream>>>(G, l, theta, src, dst);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_restrict_level(modil_ctx *c, const void *fine_src, long fine_off, void *dst,
-                                 long dst_off, int level) {
-  const LevelGeom fg = level_geom(c, level), cg = level_geom(c, level + 1);
-  const long total = cg.inst_stride * c->prob.batch;
-  if (c->prob.dtype == MODIL_F64) {
-    restrict_level_kernel<double><<<nblk(total), kBlock, 0, c->stream>>>(
-        fg, cg, (const double *)fine_src + fine_off, (double *)dst + dst_off, total);
-  } else {
-    restrict_level_kernel<float><<<nblk(total), kBlock, 0, c->stream>>>(
-        fg, cg, (const float *)fine_src + fine_off, (float *)dst + dst_off, total);
+hipError_t launch_horner(modil_ctx *c, const void *theta, void *fine_dst, bool skip_fine) {
+  return c->prob.dtype == MODIL_F64 ? horner_t<double>(c, theta, fine_dst, skip_fine)
+                                    : horner_t<float>(c, theta, fine_dst, skip_fine);
+}
+
+template <typename T>
+static hipError_t restrict_t(modil_ctx *c, void *g_v, int from, const void *th_in, void *th_out,
+                             void *m, void *v, const AdamHost *ad) {
+  const Levels G = levels_of(c);
+  T *g = (T *)g_v;
+  AdamArgs<T> A{};
+  if (ad) {
+    A.th_in = (const T *)th_in; A.th_out = (T *)th_out; A.m = (T *)m; A.v = (T *)v;
+    A.b1 = T(ad->b1); A.b2 = T(ad->b2); A.step = T(ad->step); A.isb2 = T(ad->isb2); A.eps = T(ad->eps);
+  }
+  const int lt = tail_level(G);  // levels [lt, L) are produced by one block
+  int l = from;
+  for (; l + 1 < G.L && l + 1 < lt; ++l) {
+    const long total = (long)G.stride[l + 1] * G.batch;
+    if (ad)
+      restrict_kernel<T, true><<<nblk(total), kBlock, 0, c->stream>>>(G, l, g, A);
+    else
+      restrict_kernel<T, false><<<nblk(total), kBlock, 0, c->stream>>>(G, l, g, A);
+  }
+  if (l + 1 < G.L) {
+    if (ad)
+      restrict_tail_kernel<T, true><<<1, 1024, 0, c->stream>>>(G, l, g, A);
+    else
+      restrict_tail_kernel<T, false><<<1, 1024, 0, c->stream>>>(G, l, g, A);
   }
   return hipGetLastError();
+}
+
+hipError_t launch_restrict_chain(modil_ctx *c, void *g, int from, const void *th_in, void *th_out,
+                                 void *m, void *v, const AdamHost *adam) {
+  return c->prob.dtype == MODIL_F64 ? restrict_t<double>(c, g, from, th_in, th_out, m, v, adam)
+                                    : restrict_t<float>(c, g, from, th_in, th_out, m, v, adam);
 }
 
 hipError_t launch_adam(modil_ctx *c, const void *th_in, void *th_out, void *m, void *v,
-                       const void *g, long n, double lr, double b1, double b2, double eps,
-                       double bc1, double bc2) {
-  const double step = lr / bc1, isb = 1.0 / std::sqrt(bc2);
+                       const void *g, long n, const AdamHost &h) {
   if (c->prob.dtype == MODIL_F64) {
     adam_kernel<double><<<nblk(n), kBlock, 0, c->stream>>>(
         (const double *)th_in, (double *)th_out, (double *)m, (double *)v, (const double *)g, n,
-        b1, b2, step, isb, eps);
+        h.b1, h.b2, h.step, h.isb2, h.eps);
   } else {
     adam_kernel<float><<<nblk(n), kBlock, 0, c->stream>>>(
         (const float *)th_in, (float *)th_out, (float *)m, (float *)v, (const float *)g, n,
-        (float)b1, (float)b2, (float)step, (float)isb, (float)eps);
+        (float)h.b1, (float)h.b2, (float)h.step, (float)h.isb2, (float)h.eps);
   }
   return hipGetLastError();
 }
@@ -532,9 +672,9 @@ hipError_t launch_data(modil_ctx *c, const void *u, void *g, bool want_grad) {
   return hipGetLastError();
 }
 
-hipError_t launch_reduce(modil_ctx *c, double *terms) {
-  reduce_kernel<<<c->prob.batch, kBlock, 0, c->stream>>>(c->partials, c->n_part_blocks, terms,
-                                                         c->flag);
+hipError_t launch_reduce(modil_ctx *c, double *terms, long n_a, long off_b, long n_b) {
+  reduce_kernel<<<c->prob.batch, kBlock, 0, c->stream>>>(c->partials, c->n_part_blocks, n_a, off_b,
+                                                         n_b, terms, c->flag);
   return hipGetLastError();
 }
 

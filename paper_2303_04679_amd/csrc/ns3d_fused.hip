@@ -1,0 +1,430 @@
+// Fused finest-level pass of the 3-D channel-flow problem (Section 3.5).
+//
+// One pass over the finest grid does, per cell: the last Horner step
+// u = theta_1 + T w_2 (prolongation fused into the read), the residuals of
+// continuity and momentum and their FP64 loss partials, the measurement
+// misfits, the exact adjoint gathered over the 7-point star (transposed
+// stencils with the ghost maps folded back), and -- when Adam is fused --
+// the Adam update of the finest level.  It writes the finest gradient for
+// the restriction kernel that follows.
+//
+// Tiling: a block owns a 32 x 16 (x, y) tile of cells and marches along z
+// through a chunk of planes.  Its 768 threads hold the tile with a 2-cell
+// halo: 20 rows of 32 cache-line-aligned columns (the owned rows and the two
+// halo rows on each side) and two more waves for the four halo columns.  Each
+// thread keeps its column's last four prolonged planes and three planes of
+// residual seeds in registers; the current planes of fields and seeds are
+// staged in LDS for the xy neighbours.  Seeds are formed for the owned cells
+// plus a 1-cell halo, the gradient for the owned cells.  The coarse plane
+// interpolation is cached per column, so each coarse plane is read once per
+// two fine planes.  Blocks are mapped to tiles so that every XCD works on one
+// contiguous slab of z-chunks and neighbouring tiles share its L2.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+#include "multigrid.h"
+#include "ops.h"
+
+namespace modil {
+
+constexpr int NSO_X = 32, NSO_Y = 16;   // owned cells per block (x, y)
+constexpr int NST_X = NSO_X + 4, NST_Y = NSO_Y + 4;  // tile with a 2-cell halo
+constexpr int NS_MAIN = NSO_X * NST_Y;  // threads on the full-width rows
+constexpr int NS_HALO = 4 * NST_Y;       // threads for the four halo columns
+constexpr int NS_THREADS = NS_MAIN + (NS_HALO + 63) / 64 * 64;  // whole waves
+constexpr int NS_XCD = 8;
+static_assert(NS_THREADS - NS_MAIN >= NS_HALO, "every halo-column position needs a thread");
+#ifndef NS_WAVES_PER_EU
+#define NS_WAVES_PER_EU 3
+#endif
+
+template <typename T>
+struct NS3DArgs {
+  OpParams p;
+  NSCoef<T> K;        // stencil coefficients (uniform: read from the kernel arguments)
+  int nc[3];          // level-1 cells per axis (z, y, x); unused without coarse levels
+  int has_coarse;
+  int tz, nzt, ntx, nty;
+  int tiles_per_xcd;  // ceil(nzt * ntx * nty / NS_XCD)
+  int fsize, csize;   // cells of one field on level 0 / level 1
+  const T *theta;     // level 0 of the theta pack
+  int th_inst;        // instance stride on level 0
+  const T *w1;        // level 1 of the prolonged coarse levels
+  int w1_inst;
+  T *g;               // level 0 of the gradient pack
+  const T *forcing[4];
+  const T *chi;       // fixed chi, [instance][cells]
+  const int32_t *mptr, *mfld, *midx, *mterm;
+  const double *mval, *mw;
+  double *partials;
+  int n_part_blocks;
+  AdamArgs<T> adam;   // level-0 pointers of theta_in / theta_out / m / v
+};
+
+template <typename T, int NF>
+__device__ inline void coarse_xy(const NS3DArgs<T> &A, int inst, int K, const int (&jx)[2],
+                                 const T (&wx)[2], const int (&jy)[2], const T (&wy)[2], T (&W)[NF]) {
+  const T *b = A.w1 + inst * A.w1_inst + K * A.nc[1] * A.nc[2];
+  for (int f = 0; f < NF; ++f) {
+    const T *bf = b + f * A.csize;
+    const T r0 = wx[0] * bf[jy[0] * A.nc[2] + jx[0]] + wx[1] * bf[jy[0] * A.nc[2] + jx[1]];
+    const T r1 = wx[0] * bf[jy[1] * A.nc[2] + jx[0]] + wx[1] * bf[jy[1] * A.nc[2] + jx[1]];
+    W[f] = wy[0] * r0 + wy[1] * r1;
+  }
+}
+
+// CHI: 1 fixed chi array, 2 unknown chihat (field 4)
+template <typename T, int CHI, bool ADAM>
+__global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel(NS3DArgs<T> A) {
+  constexpr int NF = (CHI == 2) ? 5 : 4;  // unknown fields
+  constexpr int NS = 5;                   // stored per cell: u, v, w, p, chi
+  __shared__ T Ul[2][NS][NST_Y][NST_X];
+  __shared__ T Al[2][4][NST_Y][NST_X];
+  __shared__ T Dl[4][NST_Y][NST_X];
+  __shared__ double red[NS_THREADS / 64][kTerms];
+
+  const OpParams &p = A.p;
+  const int tid = threadIdx.x;
+  // block -> tile: consecutive blocks go to different XCDs, so the tiles of
+  // XCD k are the contiguous range [k * tiles_per_xcd, (k + 1) * tiles_per_xcd)
+  const int per_inst = NS_XCD * A.tiles_per_xcd;
+  const int inst = blockIdx.x / per_inst;
+  const int bl = blockIdx.x - inst * per_inst;
+  const int tile = (bl % NS_XCD) * A.tiles_per_xcd + bl / NS_XCD;
+  if (tile >= A.nzt * A.ntx * A.nty) return;  // whole block leaves together
+  const int bx = tile % A.ntx, by = (tile / A.ntx) % A.nty, bz = tile / (A.ntx * A.nty);
+  // position of this thread in the tile (X, Y), halo included
+  int X = 0, Y = 0;
+  bool active = true;
+  if (tid < NS_MAIN) {
+    X = 2 + (tid % NSO_X);
+    Y = tid / NSO_X;
+  } else if (tid < NS_MAIN + NS_HALO) {
+    const int h = tid - NS_MAIN, c = h / NST_Y;
+    X = c < 2 ? c : NSO_X + c;
+    Y = h % NST_Y;
+  } else {
+    active = false;
+  }
+  const int nx = p.n[2], ny = p.n[1], nz = p.n[0];
+  const int ox = bx * NSO_X - 2, oy = by * NSO_Y - 2;
+  const int x = ox + X, y = oy + Y;
+  const int z0 = bz * A.tz, z1 = min(z0 + A.tz, nz);
+  const bool in_xy = active && x >= 0 && x < nx && y >= 0 && y < ny;
+  const bool seed_xy = in_xy && X >= 1 && X <= NST_X - 2 && Y >= 1 && Y <= NST_Y - 2;
+  const bool own_xy = in_xy && X >= 2 && X <= NST_X - 3 && Y >= 2 && Y <= NST_Y - 3;
+  const int plane = nx * ny;
+  const int col = y * nx + x;
+  const NSCoef<T> &K = A.K;
+  const T wv = T(p.w_pde * p.V);
+  const T *th_base = A.theta + inst * A.th_inst;
+
+  // xy interpolation taps of this column from level 1
+  int jx[2] = {0, 0}, jy[2] = {0, 0};
+  T wx[2] = {T(0), T(0)}, wy[2] = {T(0), T(0)};
+  if (A.has_coarse && in_xy) {
+    prolong_taps(x, A.nc[2], jx, wx);
+    prolong_taps(y, A.nc[1], jy, wy);
+  }
+  T Wlo[NF], Whi[NF];
+  for (int f = 0; f < NF; ++f) Wlo[f] = Whi[f] = T(0);
+  int kmin_c = -1000;
+
+  T U0[NS], U1[NS], U2[NS], U3[NS];  // planes pz-3 .. pz
+  T A0[4], A1[4], A2[4];             // seeds at planes pz-3 .. pz-1
+  for (int f = 0; f < NS; ++f) U0[f] = U1[f] = U2[f] = U3[f] = T(0);
+  for (int e = 0; e < 4; ++e) A0[e] = A1[e] = A2[e] = T(0);
+  double part[kTerms] = {0.0, 0.0, 0.0, 0.0, 0.0};
+
+  // ghost value of field f across face (axis a, side s) of a cell with value c
+#define GV(f, a, s, c) (T(ns_ghost<3>(p, f, a, s).b2) + T(ns_ghost<3>(p, f, a, s).c0) * (c))
+#define GC0(f, a, s) T(ns_ghost<3>(p, f, a, s).c0)
+
+  const int key_base = (inst * A.nzt * A.ntx * A.nty + tile) * A.tz;
+
+  // theta (and chi) of the next plane are loaded one iteration ahead
+  T thn[NF], chin = T(0);
+  for (int f = 0; f < NF; ++f) thn[f] = T(0);
+  if (in_xy && z0 - 2 >= 0) {
+    const int cell = (z0 - 2) * plane + col;
+    for (int f = 0; f < NF; ++f) thn[f] = th_base[f * A.fsize + cell];
+    if (CHI == 1) chin = A.chi[inst * A.fsize + cell];
+  }
+
+  for (int pz = z0 - 2; pz <= z1 + 1; ++pz) {
+    // ---- 0. issue the loads needed later: theta of plane pz+1, m and v of plane pz-2
+    T th[NF], chi_pz = chin;
+    for (int f = 0; f < NF; ++f) th[f] = thn[f];
+    if (in_xy && pz + 1 >= 0 && pz + 1 < nz) {
+      const int cell = (pz + 1) * plane + col;
+      for (int f = 0; f < NF; ++f) thn[f] = th_base[f * A.fsize + cell];
+      if (CHI == 1) chin = A.chi[inst * A.fsize + cell];
+    }
+    T mq[NF], vq[NF], tq[NF];
+    const int q = pz - 2, qb = q & 1;
+    const bool gather = own_xy && q >= z0 && q < z1;
+    if (ADAM && gather) {
+      const int k0 = inst * A.th_inst + q * plane + col;
+      for (int f = 0; f < NF; ++f) {
+        mq[f] = A.adam.m[k0 + f * A.fsize];
+        vq[f] = A.adam.v[k0 + f * A.fsize];
+        tq[f] = th_base[f * A.fsize + q * plane + col];
+      }
+    }
+    // ---- 1. prolong plane pz of this column
+    T un[NS];
+    if (in_xy && pz >= 0 && pz < nz) {
+      if (A.has_coarse) {
+        int km;
+        T wlo, whi;
+        if (pz == 0) { km = 0; wlo = T(1.25); whi = T(-0.25); }
+        else if (pz == nz - 1) { km = A.nc[0] - 2; wlo = T(-0.25); whi = T(1.25); }
+        else if ((pz & 1) == 0) { km = pz / 2 - 1; wlo = T(0.25); whi = T(0.75); }
+        else { km = pz / 2; wlo = T(0.75); whi = T(0.25); }
+        if (km != kmin_c) {
+          if (km == kmin_c + 1) {
+            for (int f = 0; f < NF; ++f) Wlo[f] = Whi[f];
+            coarse_xy<T, NF>(A, inst, km + 1, jx, wx, jy, wy, Whi);
+          } else {
+            coarse_xy<T, NF>(A, inst, km, jx, wx, jy, wy, Wlo);
+            coarse_xy<T, NF>(A, inst, km + 1, jx, wx, jy, wy, Whi);
+          }
+          kmin_c = km;
+        }
+        for (int f = 0; f < NF; ++f) un[f] = th[f] + (wlo * Wlo[f] + whi * Whi[f]);
+      } else {
+        for (int f = 0; f < NF; ++f) un[f] = th[f];
+      }
+      if (CHI == 2) un[4] = sigmoid_stable(un[4] - T(p.chi_shift));
+      else un[4] = chi_pz;
+    } else {
+      for (int f = 0; f < NS; ++f) un[f] = T(0);
+    }
+    for (int f = 0; f < NS; ++f) { U0[f] = U1[f]; U1[f] = U2[f]; U2[f] = U3[f]; U3[f] = un[f]; }
+
+    // ---- 2. stage plane pz-1 for the xy neighbours; clear the data seeds
+    const int s = pz - 1, sb = s & 1;
+    for (int f = 0; f < NS; ++f) Ul[sb][f][Y][X] = U2[f];
+    for (int f = 0; f < 4; ++f) Dl[f][Y][X] = T(0);
+    __syncthreads();
+
+    // ---- 3. residual seeds at plane s; measurement seeds at plane q = pz-2
+    T an[4] = {T(0), T(0), T(0), T(0)};
+    if (seed_xy && s >= 0 && s < nz && s >= z0 - 1 && s <= z1) {
+      T Us[4][7];
+      for (int f = 0; f < 4; ++f) {
+        const T c = U2[f];
+        Us[f][S_C] = c;
+        Us[f][S_ZM] = s > 0 ? U1[f] : GV(f, 0, 0, c);
+        Us[f][S_ZP] = s < nz - 1 ? U3[f] : GV(f, 0, 1, c);
+        Us[f][S_YM] = y > 0 ? Ul[sb][f][Y - 1][X] : GV(f, 1, 0, c);
+        Us[f][S_YP] = y < ny - 1 ? Ul[sb][f][Y + 1][X] : GV(f, 1, 1, c);
+        Us[f][S_XM] = x > 0 ? Ul[sb][f][Y][X - 1] : GV(f, 2, 0, c);
+        Us[f][S_XP] = x < nx - 1 ? Ul[sb][f][Y][X + 1] : GV(f, 2, 1, c);
+      }
+      NSLocal<3, T> L;
+      ns_local<3>(K, Us, L);
+      const T uc[3] = {U2[0], U2[1], U2[2]};
+      T r[4];
+      ns_residual<3, true>(K, L, uc, U2[4], r);
+      const int cell = s * plane + col;
+      for (int e = 0; e < 4; ++e) {
+        if (A.forcing[e]) r[e] -= A.forcing[e][inst * A.fsize + cell];
+        an[e] = T(2) * wv * r[e];
+      }
+      if (own_xy && s >= z0 && s < z1)
+        for (int e = 0; e < 4; ++e) part[MODIL_TERM_PDE] += (double)wv * (double)r[e] * (double)r[e];
+    }
+    for (int e = 0; e < 4; ++e) { A0[e] = A1[e]; A1[e] = A2[e]; A2[e] = an[e]; Al[sb][e][Y][X] = an[e]; }
+    if (q >= z0 && q < z1) {
+      const int key = key_base + (q - z0);
+      const int e0 = A.mptr[key], e1 = A.mptr[key + 1];
+      for (int e = e0 + tid; e < e1; e += NS_THREADS) {
+        const int f = A.mfld[e], k = A.midx[e];
+        const int lx = k % nx - ox, ly = (k / nx) % ny - oy;  // tile coordinates
+        const T uv = Ul[qb][f][ly][lx];
+        const double r = (double)uv - A.mval[e];
+        part[A.mterm[e]] += A.mw[e] * r * r;
+        if (e == e0 || A.mfld[e - 1] != f || A.midx[e - 1] != k) {
+          double gs = 0.0;
+          for (int j = e; j < e1 && A.mfld[j] == f && A.midx[j] == k; ++j)
+            gs += 2.0 * A.mw[j] * ((double)uv - A.mval[j]);
+          Dl[f][ly][lx] = T(gs);
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---- 4. gradient, and Adam, at plane q
+    if (gather) {
+      T Uq[4][7];
+      for (int f = 0; f < 4; ++f) {
+        const T c = U1[f];
+        Uq[f][S_C] = c;
+        Uq[f][S_ZM] = q > 0 ? U0[f] : GV(f, 0, 0, c);
+        Uq[f][S_ZP] = q < nz - 1 ? U2[f] : GV(f, 0, 1, c);
+        Uq[f][S_YM] = y > 0 ? Ul[qb][f][Y - 1][X] : GV(f, 1, 0, c);
+        Uq[f][S_YP] = y < ny - 1 ? Ul[qb][f][Y + 1][X] : GV(f, 1, 1, c);
+        Uq[f][S_XM] = x > 0 ? Ul[qb][f][Y][X - 1] : GV(f, 2, 0, c);
+        Uq[f][S_XP] = x < nx - 1 ? Ul[qb][f][Y][X + 1] : GV(f, 2, 1, c);
+      }
+      NSLocal<3, T> L;
+      ns_local<3>(K, Uq, L);
+      const T uc[3] = {U1[0], U1[1], U1[2]};
+      const T chic = U1[4];
+      T g[5], cs[4], dchi, fs[4];
+      ns_centre_sens<3, true>(K, L, A1, uc, chic, cs, dchi);
+      for (int f = 0; f < 4; ++f) g[f] = cs[f];
+      g[4] = dchi * chic * (T(1) - chic);
+      // neighbours j whose star holds this cell: the face of j pointing here
+      if (q > 0) {
+        const T uj[3] = {U0[0], U0[1], U0[2]};
+        ns_face_sens<3, true>(K, 0, 1, A0, uj, U0[4], fs);
+        for (int f = 0; f < 4; ++f) g[f] += fs[f];
+      } else {
+        ns_face_sens<3, true>(K, 0, -1, A1, uc, chic, fs);
+        for (int f = 0; f < 4; ++f) g[f] += GC0(f, 0, 0) * fs[f];
+      }
+      if (q < nz - 1) {
+        const T uj[3] = {U2[0], U2[1], U2[2]};
+        ns_face_sens<3, true>(K, 0, -1, A2, uj, U2[4], fs);
+        for (int f = 0; f < 4; ++f) g[f] += fs[f];
+      } else {
+        ns_face_sens<3, true>(K, 0, 1, A1, uc, chic, fs);
+        for (int f = 0; f < 4; ++f) g[f] += GC0(f, 0, 1) * fs[f];
+      }
+#define NS_XY_NEIGHBOUR(cond, axis, side_lo, DY, DX, sideface)                          \
+      if (cond) {                                                                       \
+        const T aj[4] = {Al[qb][0][Y + DY][X + DX], Al[qb][1][Y + DY][X + DX],     \
+                         Al[qb][2][Y + DY][X + DX], Al[qb][3][Y + DY][X + DX]};    \
+        const T uj[3] = {Ul[qb][0][Y + DY][X + DX], Ul[qb][1][Y + DY][X + DX],     \
+                         Ul[qb][2][Y + DY][X + DX]};                                  \
+        ns_face_sens<3, true>(K, axis, sideface, aj, uj, Ul[qb][4][Y + DY][X + DX], fs); \
+        for (int f = 0; f < 4; ++f) g[f] += fs[f];                                      \
+      } else {                                                                          \
+        ns_face_sens<3, true>(K, axis, -(sideface), A1, uc, chic, fs);              \
+        for (int f = 0; f < 4; ++f) g[f] += GC0(f, axis, side_lo) * fs[f];        \
+      }
+      NS_XY_NEIGHBOUR(y > 0, 1, 0, -1, 0, 1)
+      NS_XY_NEIGHBOUR(y < ny - 1, 1, 1, 1, 0, -1)
+      NS_XY_NEIGHBOUR(x > 0, 2, 0, 0, -1, 1)
+      NS_XY_NEIGHBOUR(x < nx - 1, 2, 1, 0, 1, -1)
+#undef NS_XY_NEIGHBOUR
+      for (int f = 0; f < 4; ++f) g[f] += Dl[f][Y][X];
+      const int cell = q * plane + col;
+      const int base = inst * A.th_inst + cell;
+      for (int f = 0; f < NF; ++f) {
+        const int k = base + f * A.fsize;
+        A.g[k] = g[f];
+        if (ADAM) {
+          const T mm = A.adam.b1 * mq[f] + (T(1) - A.adam.b1) * g[f];
+          const T vv = A.adam.b2 * vq[f] + (T(1) - A.adam.b2) * g[f] * g[f];
+          A.adam.m[k] = mm;
+          A.adam.v[k] = vv;
+          A.adam.th_out[k] = tq[f] - A.adam.step * mm / (sqrt(vv) * A.adam.isb2 + A.adam.eps);
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+#undef GV
+#undef GC0
+  // ---- block sum of the loss partials (fixed order)
+  for (int k = 0; k < kTerms; ++k) {
+    double v = part[k];
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_down(v, off, 64);
+    part[k] = v;
+  }
+  if ((tid & 63) == 0)
+    for (int k = 0; k < kTerms; ++k) red[tid >> 6][k] = part[k];
+  __syncthreads();
+  if (tid < kTerms) {
+    double sum = 0.0;
+    for (int w = 0; w < NS_THREADS / 64; ++w) sum += red[w][tid];
+    A.partials[((long)inst * A.n_part_blocks + tile) * kTerms + tid] = sum;
+  }
+}
+
+// ------------------------------------------------------------------ host side
+void ns3d_tiles(const modil_problem &P, int &tz, int &nzt, int &ntx, int &nty, int &ox, int &oy) {
+  const int nz = P.dims[0], ny = P.dims[1], nx = P.dims[2];
+  tz = nz >= 64 ? 16 : 8;
+  nzt = (nz + tz - 1) / tz;
+  ntx = (nx + NSO_X - 1) / NSO_X;
+  nty = (ny + NSO_Y - 1) / NSO_Y;
+  ox = NSO_X;
+  oy = NSO_Y;
+}
+
+template <typename T>
+static hipError_t fused_t(modil_ctx *c, const void *theta, void *g, const AdamHost *ad,
+                          const void *th_out, void *m, void *v) {
+  const modil_problem &P = c->prob;
+  NS3DArgs<T> A{};
+  OpParams &p = A.p;
+  p.ndim = 3;
+  for (int a = 0; a < 3; ++a) {
+    p.n[a] = P.dims[a];
+    p.h[a] = P.lengths[a] / P.dims[a];
+  }
+  p.V = p.h[0] * p.h[1] * p.h[2];
+  p.w_pde = P.w_pde; p.w_reg = P.w_reg; p.w_bc = P.w_bc;
+  p.re = P.re; p.diam = P.diam; p.lam = P.lambda_; p.chi_shift = P.chi_shift;
+  p.tau_coef = P.tau_coef; p.u_ref = P.u_ref;
+  p.inst_re = c->inst_re;
+  int tox, toy;
+  ns3d_tiles(P, A.tz, A.nzt, A.ntx, A.nty, tox, toy);
+  A.tiles_per_xcd = (A.nzt * A.ntx * A.nty + NS_XCD - 1) / NS_XCD;
+  for (int a = 0; a < 3; ++a) {
+    A.K.i2h[a] = T(0.5 / p.h[a]);
+    A.K.ih2[a] = T(1.0 / (p.h[a] * p.h[a]));
+    A.K.tauh[a] = T(p.tau_coef / p.h[a]);
+  }
+  A.K.nu = T(P.diam / P.re);  // the fused path requires one Reynolds number for all instances
+  A.K.lam = T(P.lambda_);
+  A.K.ssum = A.K.ih2[0] + A.K.ih2[1] + A.K.ih2[2];
+  A.K.tsum = A.K.tauh[0] + A.K.tauh[1] + A.K.tauh[2];
+  A.has_coarse = P.n_levels > 1;
+  A.fsize = (int)c->lay.fine_cells;
+  A.th_inst = (int)c->lay.level_stride[0];
+  A.theta = (const T *)theta;
+  if (A.has_coarse) {
+    for (int a = 0; a < 3; ++a) A.nc[a] = P.dims[a] / 2;
+    A.csize = A.nc[0] * A.nc[1] * A.nc[2];
+    A.w1_inst = (int)c->lay.level_stride[1];
+    // level 1 of the prolonged coarse fields: theta itself when it is the coarsest
+    A.w1 = (P.n_levels == 2 ? (const T *)theta : (const T *)c->w_buf) + c->lay.level_offset[1];
+  }
+  A.g = (T *)g;
+  for (int e = 0; e < 4; ++e) A.forcing[e] = (const T *)c->forcing[e];
+  A.chi = (const T *)c->chi;
+  A.mptr = c->fm_ptr; A.mfld = c->fm_field; A.midx = c->fm_idx; A.mterm = c->fm_term;
+  A.mval = c->fm_val; A.mw = c->fm_w;
+  A.partials = c->partials;
+  A.n_part_blocks = (int)c->n_part_blocks;
+  if (ad) {
+    A.adam.th_in = (const T *)theta; A.adam.th_out = (T *)th_out;
+    A.adam.m = (T *)m; A.adam.v = (T *)v;
+    A.adam.b1 = T(ad->b1); A.adam.b2 = T(ad->b2); A.adam.step = T(ad->step);
+    A.adam.isb2 = T(ad->isb2); A.adam.eps = T(ad->eps);
+  }
+  const dim3 grid(NS_XCD * A.tiles_per_xcd * P.batch), block(NS_THREADS);
+  const bool fixed = (P.flags & MODIL_FLAG_CHI_FIXED) != 0;
+  if (fixed) {
+    if (ad) ns3d_fused_kernel<T, 1, true><<<grid, block, 0, c->stream>>>(A);
+    else ns3d_fused_kernel<T, 1, false><<<grid, block, 0, c->stream>>>(A);
+  } else {
+    if (ad) ns3d_fused_kernel<T, 2, true><<<grid, block, 0, c->stream>>>(A);
+    else ns3d_fused_kernel<T, 2, false><<<grid, block, 0, c->stream>>>(A);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_ns3d_fused(modil_ctx *c, const void *theta, void *g, const AdamHost *adam,
+                             void *th_out, void *m, void *v) {
+  return c->prob.dtype == MODIL_F64 ? fused_t<double>(c, theta, g, adam, th_out, m, v)
+                                    : fused_t<float>(c, theta, g, adam, th_out, m, v);
+}
+
+}  // namespace modil

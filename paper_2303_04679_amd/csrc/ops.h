@@ -208,6 +208,157 @@ struct OpHeat {
 // D = 3: channel [z][y][x], fields u (x), v (y), w (z), p, [chihat];
 // D = 2: cavity [y][x], fields u (x), v (y), p.
 // Velocity component c points along grid axis 2 - c.
+// Equations: 0 continuity, 1 + c momentum of component c.
+//
+// The formulas are split into point functions shared by the generic stencil
+// engine and the fused channel-flow kernel:
+//   ns_residual     residuals at a cell from its star of (u.., p) and chi
+//   ns_face_sens    sensitivity of sum_e a_e r_e(j) to the neighbour value of
+//                   every (velocity, p) field across one face of j; it
+//                   depends only on the seeds and centre values at j
+//   ns_centre_sens  sensitivity to the centre values of j (needs the star)
+
+template <int D>
+__host__ __device__ inline double ns_nu(const OpParams &p, int inst) {
+  const double re = p.inst_re ? p.inst_re[inst] : p.re;
+  return (D == 3 ? p.diam : 1.0) / re;
+}
+
+// stencil coefficients in the working precision, computed once per thread
+template <typename T>
+struct NSCoef {
+  T i2h[3];   // 1 / (2 h_a)
+  T ih2[3];   // 1 / h_a^2
+  T tauh[3];  // tau_coef / h_a (stabilisation tau_a / h_a^2 with tau_a = tau_coef h_a)
+  T nu, lam, ssum, tsum;
+};
+
+template <int D, typename T>
+__device__ inline NSCoef<T> ns_coef(const OpParams &p, int inst) {
+  NSCoef<T> k;
+  for (int a = 0; a < 3; ++a) {
+    k.i2h[a] = T(0.5 / p.h[a]);
+    k.ih2[a] = T(1.0 / (p.h[a] * p.h[a]));
+    k.tauh[a] = T(p.tau_coef / p.h[a]);
+  }
+  k.nu = T(ns_nu<D>(p, inst));
+  k.lam = T(p.lam);
+  k.ssum = T(0);
+  k.tsum = T(0);
+  for (int a = 3 - D; a < 3; ++a) {
+    k.ssum += k.ih2[a];
+    k.tsum += k.tauh[a];
+  }
+  return k;
+}
+
+template <int D, typename T>
+struct NSLocal {
+  T du[D][D];  // du[c][k]: derivative of component c along the axis of component k
+  T lap[D];
+  T dp[D];
+  T stab;
+  T body[D];  // convection + pressure gradient - viscous term
+};
+
+// U: star values of the velocity components and p (fields 0..D), ghosts applied
+template <int D, typename T, int NFU>
+__device__ inline void ns_local(const NSCoef<T> &K, const T (&U)[NFU][7], NSLocal<D, T> &L) {
+  for (int c = 0; c < D; ++c) {
+    L.lap[c] = T(0);
+    for (int k = 0; k < D; ++k) {
+      const int ax = 2 - k;
+      L.du[c][k] = (U[c][slot_p(ax)] - U[c][slot_m(ax)]) * K.i2h[ax];
+      L.lap[c] += (U[c][slot_p(ax)] - T(2) * U[c][S_C] + U[c][slot_m(ax)]) * K.ih2[ax];
+    }
+  }
+  L.stab = T(0);
+  for (int k = 0; k < D; ++k) {
+    const int ax = 2 - k;
+    L.dp[k] = (U[D][slot_p(ax)] - U[D][slot_m(ax)]) * K.i2h[ax];
+    L.stab += (U[D][slot_p(ax)] - T(2) * U[D][S_C] + U[D][slot_m(ax)]) * K.tauh[ax];
+  }
+  for (int c = 0; c < D; ++c) {
+    T b = L.dp[c] - K.nu * L.lap[c];
+    for (int k = 0; k < D; ++k) b += U[k][S_C] * L.du[c][k];
+    L.body[c] = b;
+  }
+}
+
+template <int D, bool HAS_CHI, typename T>
+__device__ inline void ns_residual(const NSCoef<T> &K, const NSLocal<D, T> &L, const T *uc, T chi,
+                                   T *r) {
+  T cont = T(0);
+  for (int c = 0; c < D; ++c) cont += L.du[c][c];
+  r[0] = cont - L.stab;
+  for (int c = 0; c < D; ++c)
+    r[1 + c] = HAS_CHI ? (T(1) - chi) * L.body[c] + K.lam * chi * uc[c] : L.body[c];
+}
+
+// s[f], f = 0..D (velocity components, p): d(sum_e a_e r_e(j)) / d U_f(j + side * e_axis)
+template <int D, bool HAS_CHI, typename T>
+__device__ inline void ns_face_sens(const NSCoef<T> &K, int axis, int side, const T *a,
+                                    const T *uc, T chi, T *s) {
+  const T i2h = K.i2h[axis], ih2 = K.ih2[axis];
+  const T sg = side > 0 ? T(1) : T(-1);
+  const int kc = 2 - axis;  // component along this axis
+  const T omc = HAS_CHI ? T(1) - chi : T(1);
+  for (int c = 0; c < D; ++c) {
+    const T A = a[1 + c] * omc;
+    T v = A * (sg * uc[kc] * i2h - K.nu * ih2);
+    if (c == kc) v += sg * a[0] * i2h;
+    s[c] = v;
+  }
+  s[D] = -a[0] * K.tauh[axis] + sg * a[1 + kc] * omc * i2h;
+}
+
+// s[f], f = 0..D: sensitivity to the centre values; dchi = d(sum a r)/d chi
+template <int D, bool HAS_CHI, typename T>
+__device__ inline void ns_centre_sens(const NSCoef<T> &K, const NSLocal<D, T> &L, const T *a,
+                                      const T *uc, T chi, T *s, T &dchi) {
+  const T omc = HAS_CHI ? T(1) - chi : T(1);
+  for (int f = 0; f < D; ++f) {
+    T v = T(0);
+    for (int c = 0; c < D; ++c) v += a[1 + c] * omc * L.du[c][f];
+    v += T(2) * a[1 + f] * omc * K.nu * K.ssum;
+    if (HAS_CHI) v += a[1 + f] * K.lam * chi;
+    s[f] = v;
+  }
+  s[D] = T(2) * a[0] * K.tsum;
+  dchi = T(0);
+  if (HAS_CHI)
+    for (int c = 0; c < D; ++c) dchi += a[1 + c] * (K.lam * uc[c] - L.body[c]);
+}
+
+template <typename T>
+__device__ inline T sigmoid_stable(T z) {
+  return z >= T(0) ? T(1) / (T(1) + exp(-z)) : exp(z) / (T(1) + exp(z));
+}
+
+// Ghost rules of the channel (D = 3) and of the cavity (D = 2) for (velocity, p).
+template <int D>
+__host__ __device__ inline GhostRule ns_ghost(const OpParams &p, int f, int axis, int side) {
+  const int P = D;
+  if (D == 3) {
+    if (axis == 2) {                      // inlet (side 0) / outlet (side 1)
+      if (side == 0) {
+        if (f == P) return GhostRule{0.0, 1.0, 0.0};              // dp/dn = 0
+        return GhostRule{f == 0 ? 2.0 * p.u_ref : 0.0, -1.0, 0.0};  // u = (U, 0, 0)
+      }
+      if (f == P) return GhostRule{0.0, -1.0, 0.0};               // p = 0
+      return GhostRule{0.0, 1.0, 0.0};                              // du/dn = 0
+    }
+    // free-slip walls: normal component zero, the rest Neumann
+    const int normal = 2 - axis;
+    if (f == normal) return GhostRule{0.0, -1.0, 0.0};
+    return GhostRule{0.0, 1.0, 0.0};
+  }
+  // cavity: no-slip walls, lid (axis 1, side 1) moves with u = u_ref
+  if (f == P) return GhostRule{0.0, 1.0, 0.0};
+  if (axis == 1 && side == 1 && f == 0) return GhostRule{2.0 * p.u_ref, -1.0, 0.0};
+  return GhostRule{0.0, -1.0, 0.0};
+}
+
 // CHI: 0 no body, 1 fixed chi array, 2 unknown chihat field.
 template <int D, int CHI>
 struct OpNS {
@@ -218,84 +369,25 @@ struct OpNS {
   __device__ static bool needs_nb(int f) { return f <= D; }
   __device__ static GhostRule ghost(const OpParams &p, int f, int axis, int side) {
     if (f > D) return GhostRule{0.0, 0.0, 0.0};
-    if (D == 3) {
-      if (axis == 2) {                      // inlet (side 0) / outlet (side 1)
-        if (side == 0) {
-          if (f == P) return GhostRule{0.0, 1.0, 0.0};              // dp/dn = 0
-          return GhostRule{f == 0 ? 2.0 * p.u_ref : 0.0, -1.0, 0.0};  // u = (U, 0, 0)
-        }
-        if (f == P) return GhostRule{0.0, -1.0, 0.0};               // p = 0
-        return GhostRule{0.0, 1.0, 0.0};                              // du/dn = 0
-      }
-      // free-slip walls: normal component zero, the rest Neumann
-      const int normal = 2 - axis;
-      if (f == normal) return GhostRule{0.0, -1.0, 0.0};
-      return GhostRule{0.0, 1.0, 0.0};
-    }
-    // cavity: no-slip walls, lid (axis 1, side 1) moves with u = u_ref
-    if (f == P) return GhostRule{0.0, 1.0, 0.0};
-    if (axis == 1 && side == 1 && f == 0) return GhostRule{2.0 * p.u_ref, -1.0, 0.0};
-    return GhostRule{0.0, -1.0, 0.0};
-  }
-
-  template <typename T>
-  struct Local {
-    T du[D][D];  // du[c][k]: derivative of component c along the axis of component k
-    T lap[D];
-    T dp[D];
-    T stab;
-  };
-
-  template <typename T>
-  __device__ static void locals(const OpParams &p, const T (&U)[NF][7], Local<T> &L) {
-    for (int c = 0; c < D; ++c) {
-      L.lap[c] = T(0);
-      for (int k = 0; k < D; ++k) {
-        const int ax = 2 - k;
-        const T i2h = T(0.5 / p.h[ax]), ih2 = T(1.0 / (p.h[ax] * p.h[ax]));
-        L.du[c][k] = (U[c][slot_p(ax)] - U[c][slot_m(ax)]) * i2h;
-        L.lap[c] += (U[c][slot_p(ax)] - T(2) * U[c][S_C] + U[c][slot_m(ax)]) * ih2;
-      }
-    }
-    L.stab = T(0);
-    for (int k = 0; k < D; ++k) {
-      const int ax = 2 - k;
-      L.dp[k] = (U[P][slot_p(ax)] - U[P][slot_m(ax)]) * T(0.5 / p.h[ax]);
-      L.stab += (U[P][slot_p(ax)] - T(2) * U[P][S_C] + U[P][slot_m(ax)]) * T(p.tau_coef / p.h[ax]);
-    }
-  }
-
-  template <typename T>
-  __device__ static T nu_of(const OpParams &p, int inst) {
-    const double re = p.inst_re ? p.inst_re[inst] : p.re;
-    return T((D == 3 ? p.diam : 1.0) / re);
+    return ns_ghost<D>(p, f, axis, side);
   }
 
   template <typename T>
   __device__ static T chi_of(const OpParams &p, const T (&U)[NF][7], T chi_fixed) {
     if (CHI == 1) return chi_fixed;
-    if (CHI == 2) {
-      const T z = U[NF - 1][S_C] - T(p.chi_shift);
-      return z >= T(0) ? T(1) / (T(1) + exp(-z)) : exp(z) / (T(1) + exp(z));
-    }
+    if (CHI == 2) return sigmoid_stable(U[NF - 1][S_C] - T(p.chi_shift));
     return T(0);
   }
 
   template <typename T>
   __device__ static void eval(const OpParams &p, const int *, int inst, const T (&U)[NF][7],
                               T chi_fixed, T *r, T *wv, int *term) {
-    Local<T> L;
-    locals(p, U, L);
-    const T nu = nu_of<T>(p, inst);
-    T cont = T(0);
-    for (int c = 0; c < D; ++c) cont += L.du[c][c];
-    r[0] = cont - L.stab;
-    const T chi = chi_of(p, U, chi_fixed);
-    for (int c = 0; c < D; ++c) {
-      T body = L.dp[c] - nu * L.lap[c];
-      for (int k = 0; k < D; ++k) body += U[k][S_C] * L.du[c][k];
-      r[1 + c] = CHI ? (T(1) - chi) * body + T(p.lam) * chi * U[c][S_C] : body;
-    }
+    const NSCoef<T> K = ns_coef<D, T>(p, inst);
+    NSLocal<D, T> L;
+    ns_local<D>(K, U, L);
+    T uc[D];
+    for (int c = 0; c < D; ++c) uc[c] = U[c][S_C];
+    ns_residual<D, CHI != 0>(K, L, uc, chi_of(p, U, chi_fixed), r);
     for (int e = 0; e < NE; ++e) {
       wv[e] = T(p.w_pde * p.V);
       term[e] = MODIL_TERM_PDE;
@@ -305,43 +397,24 @@ struct OpNS {
   template <typename T>
   __device__ static void vjp(const OpParams &p, const int *, int inst, const T (&U)[NF][7],
                              T chi_fixed, const T *a, T (&s)[NF][7]) {
-    Local<T> L;
-    locals(p, U, L);
-    const T nu = nu_of<T>(p, inst);
+    const NSCoef<T> K = ns_coef<D, T>(p, inst);
+    NSLocal<D, T> L;
+    ns_local<D>(K, U, L);
+    T uc[D];
+    for (int c = 0; c < D; ++c) uc[c] = U[c][S_C];
     const T chi = chi_of(p, U, chi_fixed);
-    // continuity
-    for (int c = 0; c < D; ++c) {
-      const int ax = 2 - c;
-      const T i2h = T(0.5 / p.h[ax]);
-      s[c][slot_p(ax)] += a[0] * i2h;
-      s[c][slot_m(ax)] -= a[0] * i2h;
-      const T t = a[0] * T(p.tau_coef / p.h[ax]);
-      s[P][slot_p(ax)] -= t;
-      s[P][slot_m(ax)] -= t;
-      s[P][S_C] += T(2) * t;
+    T fs[D + 1];
+    for (int k = 0; k < D; ++k) {
+      const int ax = 2 - k;
+      ns_face_sens<D, CHI != 0>(K, ax, 1, a, uc, chi, fs);
+      for (int f = 0; f <= D; ++f) s[f][slot_p(ax)] += fs[f];
+      ns_face_sens<D, CHI != 0>(K, ax, -1, a, uc, chi, fs);
+      for (int f = 0; f <= D; ++f) s[f][slot_m(ax)] += fs[f];
     }
-    // momentum
-    for (int c = 0; c < D; ++c) {
-      const T A = CHI ? a[1 + c] * (T(1) - chi) : a[1 + c];
-      T body = L.dp[c] - nu * L.lap[c];
-      for (int k = 0; k < D; ++k) {
-        const int ax = 2 - k;
-        const T i2h = T(0.5 / p.h[ax]), ih2 = T(1.0 / (p.h[ax] * p.h[ax]));
-        body += U[k][S_C] * L.du[c][k];
-        s[k][S_C] += A * L.du[c][k];
-        const T cv = A * U[k][S_C] * i2h;
-        const T vs = A * nu * ih2;
-        s[c][slot_p(ax)] += cv - vs;
-        s[c][slot_m(ax)] -= cv + vs;
-        s[c][S_C] += T(2) * vs;
-      }
-      const int axc = 2 - c;
-      s[P][slot_p(axc)] += A * T(0.5 / p.h[axc]);
-      s[P][slot_m(axc)] -= A * T(0.5 / p.h[axc]);
-      if (CHI) s[c][S_C] += a[1 + c] * T(p.lam) * chi;
-      if (CHI == 2)
-        s[NF - 1][S_C] += a[1 + c] * (T(p.lam) * U[c][S_C] - body) * chi * (T(1) - chi);
-    }
+    T dchi;
+    ns_centre_sens<D, CHI != 0>(K, L, a, uc, chi, fs, dchi);
+    for (int f = 0; f <= D; ++f) s[f][S_C] += fs[f];
+    if (CHI == 2) s[NF - 1][S_C] += dchi * chi * (T(1) - chi);
   }
 };
 

@@ -246,6 +246,10 @@ class Context:
         L.check(L.lib().modil_residual_metric(self.h, _ptr(theta), _ptr(out)), self.h)
         return out
 
+    def set_fused(self, enabled: bool):
+        """Use the fused finest-level kernel where one exists (default) or the generic engine."""
+        L.check(L.lib().modil_set_option(self.h, L.OPT_FUSED, 1 if enabled else 0), self.h)
+
     def check(self):
         """Synchronise; raise ModilError on a non-finite loss or a HIP error."""
         L.check(L.lib().modil_check(self.h), self.h)
