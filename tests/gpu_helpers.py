@@ -81,8 +81,45 @@ def assert_terms(gpu_terms, ref_terms, tol, ctx_msg=""):
             (ctx_msg, t, g, r)
 
 
-def assert_levels(gpu_levels, ref_levels, tol, ctx_msg=""):
+def cancellation(ref_levels, field_axes_list):
+    """Per (level, field): || |M^T| |g_fine| || / || g_level ||.
+
+    A coarse-level gradient is the restriction of the fine gradient, a sum of
+    many fine contributions of both signs.  Rounding errors of the fine
+    contributions add up in absolute value while the signal cancels, so the
+    attainable relative accuracy of level l is the working precision times
+    this factor (1 on the finest level).
+    """
+    from oracle import multigrid as mg
+    out = []
+    for li, row in enumerate(ref_levels):
+        frow = []
+        for fi, r in enumerate(row):
+            if li == 0:
+                frow.append(1.0)
+                continue
+            a = np.abs(np.asarray(ref_levels[0][fi], dtype=np.float64))
+            for _ in range(li):
+                for ax in field_axes_list[fi]:
+                    n_c = a.shape[ax] // 2
+                    Ta = np.abs(mg.cell_T_matrix(n_c))
+                    a = np.moveaxis(np.tensordot(Ta.T, np.moveaxis(a, ax, 0), axes=1), 0, ax)
+            nr = np.linalg.norm(r)
+            frow.append(max(1.0, np.linalg.norm(a) / nr) if nr > 0 else 1.0)
+        out.append(frow)
+    return out
+
+
+def assert_levels(gpu_levels, ref_levels, tol, ctx_msg="", spec=None):
+    """Norm-wise relative error per (level, field).  With spec (FP32 checks),
+    coarse levels are held to tol times their cancellation factor."""
+    factors = None
+    if spec is not None:
+        from oracle import operators as ops
+        axes = [ops.field_axes(spec.op, name, spec.ndim) for name in spec.fields]
+        factors = cancellation(ref_levels, axes)
     for li, (grow, rrow) in enumerate(zip(gpu_levels, ref_levels)):
         for fi, (g, r) in enumerate(zip(grow, rrow)):
             e = rel(g, r)
-            assert e <= tol, (ctx_msg, "level", li, "field", fi, e)
+            t = tol * (factors[li][fi] if factors else 1.0)
+            assert e <= t, (ctx_msg, "level", li, "field", fi, e, t)
