@@ -250,6 +250,66 @@ int modil_check(modil_ctx *ctx);
 int modil_profile(modil_ctx *ctx, int32_t enable);
 int modil_profile_read(modil_ctx *ctx, int32_t kernel_class, double *total_ms, int64_t *count);
 
+/* ---- learned warm start: a small convolutional network --------------------
+ * Not part of the paper: a network that maps measurements of a lid-driven
+ * cavity instance to the coarse multigrid levels of its solution, used as
+ * the starting point of the iteration (cold-start mODIL stays the fallback).
+ *
+ * Input image [batch][4][size][size] (float): channels u_obs, v_obs, mask of
+ * observed cells, (Re - re_center) / re_scale.  Fixed topology, parameters
+ * in bf16 (rounded to nearest even from float masters), float accumulation:
+ *   trunk 1: 4 -> width1, 4x4 kernel, stride 4          -> size/4
+ *   trunk 2: width1 -> width2, 3x3, stride 2, pad 1     -> size/8
+ *   trunk 3: width2 -> width3, 3x3, stride 2, pad 1     -> size/16
+ *   head k (k = 1, 2, 3): trunk k -> out_ch, 3x3, stride 1, pad 1
+ * ReLU after the trunk layers, none after the heads.  Output: the three head
+ * maps concatenated, [batch][out_ch][size/4]^2, then size/8, then size/16.
+ * Parameter pack (float / bf16, same layout): for the layers in the order
+ * trunk 1..3, head 1..3, the weights [co][ci][k][k] then the biases [co].
+ * Loss: mean squared error over all outputs, accumulated in double.       */
+typedef struct {
+  int32_t batch;   /* maximum images per call */
+  int32_t size;    /* image side, a multiple of 16 */
+  int32_t n_obs;   /* observed cells per image */
+  int32_t width1, width2, width3, out_ch;
+  double re_center, re_scale;
+} modil_cnn_desc;
+
+typedef struct {
+  int64_t n_params;        /* parameters (weights and biases)            */
+  int64_t w_offset[6];     /* offsets of the layers' weights in the pack */
+  int64_t b_offset[6];     /* offsets of the layers' biases              */
+  int64_t img_size;        /* floats of one input image                  */
+  int64_t act_size;        /* floats of the trunk activations, one image */
+  int64_t out_size;        /* floats of the three head maps, one image   */
+  size_t workspace_bytes;
+} modil_cnn_layout_t;
+
+typedef struct modil_cnn modil_cnn;
+
+int modil_cnn_layout(const modil_cnn_desc *desc, modil_cnn_layout_t *out);
+int modil_cnn_create(const modil_cnn_desc *desc, void *workspace, size_t workspace_bytes,
+                     void *hip_stream, modil_cnn **out);
+int modil_cnn_destroy(modil_cnn *net);
+/* img[b] from obs_idx[b][n_obs] (flat cell indices, unique per image),
+ * obs_u, obs_v [b][n_obs] and re[b] (all device arrays). */
+int modil_cnn_rasterize(modil_cnn *net, int32_t batch, const int32_t *obs_idx, const float *obs_u,
+                        const float *obs_v, const float *re, float *img);
+/* acts [batch][act_size] (trunk activations), out [batch][out_size]. */
+int modil_cnn_forward(modil_cnn *net, int32_t batch, const uint16_t *params_bf16, const float *img,
+                      float *acts, float *out);
+/* loss (device double) = mean over all outputs of (out - target)^2 and the
+ * gradient of the loss with respect to every parameter (float pack), for
+ * the acts / out of the preceding forward call on the same input. */
+int modil_cnn_loss_backward(modil_cnn *net, int32_t batch, const uint16_t *params_bf16,
+                            const float *img, const float *acts, const float *out,
+                            const float *target, double *loss, float *grad);
+/* Adam on the float masters, then params_bf16 = round-to-nearest-even(master). */
+int modil_cnn_adam(modil_cnn *net, float *master, uint16_t *params_bf16, float *m, float *v,
+                   const float *grad, const modil_adam_hp *hp, int64_t step);
+/* params_bf16 = round-to-nearest-even(master) */
+int modil_cnn_to_bf16(modil_cnn *net, const float *master, uint16_t *params_bf16);
+
 #ifdef __cplusplus
 }
 #endif

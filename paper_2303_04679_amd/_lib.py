@@ -68,6 +68,20 @@ class AdamHP(ctypes.Structure):
                 ("beta2", ctypes.c_double), ("eps", ctypes.c_double)]
 
 
+class CnnDesc(ctypes.Structure):
+    _fields_ = [("batch", ctypes.c_int32), ("size", ctypes.c_int32), ("n_obs", ctypes.c_int32),
+                ("width1", ctypes.c_int32), ("width2", ctypes.c_int32), ("width3", ctypes.c_int32),
+                ("out_ch", ctypes.c_int32), ("re_center", ctypes.c_double),
+                ("re_scale", ctypes.c_double)]
+
+
+class CnnLayout(ctypes.Structure):
+    _fields_ = [("n_params", ctypes.c_int64), ("w_offset", ctypes.c_int64 * 6),
+                ("b_offset", ctypes.c_int64 * 6), ("img_size", ctypes.c_int64),
+                ("act_size", ctypes.c_int64), ("out_size", ctypes.c_int64),
+                ("workspace_bytes", ctypes.c_size_t)]
+
+
 _P = ctypes.c_void_p
 _I = ctypes.c_int
 _SIGS = {
@@ -95,6 +109,14 @@ _SIGS = {
     "modil_profile": (_I, [_P, ctypes.c_int32]),
     "modil_profile_read": (_I, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                 ctypes.POINTER(ctypes.c_int64)]),
+    "modil_cnn_layout": (_I, [ctypes.POINTER(CnnDesc), ctypes.POINTER(CnnLayout)]),
+    "modil_cnn_create": (_I, [ctypes.POINTER(CnnDesc), _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)]),
+    "modil_cnn_destroy": (_I, [_P]),
+    "modil_cnn_rasterize": (_I, [_P, ctypes.c_int32, _P, _P, _P, _P, _P]),
+    "modil_cnn_forward": (_I, [_P, ctypes.c_int32, _P, _P, _P, _P]),
+    "modil_cnn_loss_backward": (_I, [_P, ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P]),
+    "modil_cnn_adam": (_I, [_P, _P, _P, _P, _P, _P, ctypes.POINTER(AdamHP), ctypes.c_int64]),
+    "modil_cnn_to_bf16": (_I, [_P, _P, _P]),
 }
 
 _lib = None

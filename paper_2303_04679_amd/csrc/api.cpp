@@ -387,6 +387,8 @@ bool check_ctx(modil_ctx *c) { return c != nullptr; }
 // ------------------------------------------------------------- op metadata
 namespace modil {
 
+int set_global_error(int status, const std::string &msg) { return fail_global(status, msg); }
+
 int op_fields(const modil_problem &p) {
   switch (p.op) {
     case MODIL_OP_POISSON:

@@ -131,6 +131,9 @@ FieldGeom field_geom(const modil_problem &p, int level, int f);
 
 Levels levels_of(const modil_ctx *c);
 
+// record the message returned by modil_last_error(NULL); returns status
+int set_global_error(int status, const std::string &msg);
+
 // Adam hyper-parameters as passed to the kernels (bias corrections folded in)
 struct AdamHost {
   double b1, b2, step, isb2, eps;

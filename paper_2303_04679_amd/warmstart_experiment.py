@@ -1,0 +1,241 @@
+"""Warm start versus cold start on the 128^2 lid-driven cavity.
+
+    python -m paper_2303_04679_amd.warmstart_experiment --out result.json
+
+1. Cold-start mODIL solves (Adam, cosine-decayed step) of the training and
+   held-out instances (Re ~ U(100, 1000) per instance, seeded), batched.
+2. Canonical coarse-level targets from the converged fields; observations
+   are the solution's velocity at 64 seeded cells.
+3. Training of the warm-start network with the library's kernels.
+4. One-off choice of the step schedule of each start (cold and warm) on a
+   subset of training instances; frozen for the evaluation.
+5. Held-out evaluation: iterations to r <= 1e-6 (and to 1e-5), per instance,
+   for the cold and the warm start (with the fallback rule); times from the
+   per-iteration time of a single-instance solve plus, for the warm start,
+   rasterisation and network inference; and direct single-instance
+   wall-clock solves for a few instances.
+"""
+import argparse
+import json
+import time
+
+import numpy as np
+import torch
+
+from . import warmstart as W
+from .solve import cosine_lr, solve
+
+
+def log(msg):
+    print(f"[warmstart] {msg}", flush=True)
+
+
+def cold_solve(res, iters, lr0, progress=True):
+    ctx = W.cavity_context(res)
+    th = ctx.new_pack()
+    out = solve(ctx, th, cosine_lr(lr0, 1e-6, iters), iters, r_target=0.0, check_every=500,
+                log=(lambda it, r: log(f"  it {it} median r {np.median(r):.2e}") if it % 5000 == 0 else None)
+                if progress else None)
+    return ctx, out
+
+
+def dataset(seeds, iters, lr0, batch):
+    ys = [[], [], []]
+    us, vs = [], []
+    res_all, idx_all = W.instances(seeds)
+    r_final = []
+    for k in range(0, len(seeds), batch):
+        res = res_all[k:k + batch]
+        t0 = time.time()
+        ctx, out = cold_solve(res, iters, lr0)
+        fine = W.fine_fields(ctx, out.theta)
+        y = W.canonical_targets(fine.double())
+        for i in range(3):
+            ys[i].append(y[i].float())
+        u, v = W.observe(fine, idx_all[k:k + batch])
+        us.append(u)
+        vs.append(v)
+        r_final.append(out.r_final)
+        log(f"solved instances {k}..{k + len(res) - 1} in {time.time() - t0:.1f} s, "
+            f"median r {np.median(out.r_final):.2e}")
+        ctx.close()
+    return (res_all, idx_all, torch.cat(us), torch.cat(vs), [torch.cat(t) for t in ys],
+            np.concatenate(r_final))
+
+
+def train(net, data, steps, lr, batch, seed=0):
+    res, idx, u, v, ys, _ = data
+    n = len(res)
+    tgt = torch.cat([y.reshape(n, -1) for y in ys], 1).contiguous()
+    g = np.random.default_rng(seed)
+    lrf = cosine_lr(lr, lr * 0.01, steps)
+    hist = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        pick = np.sort(g.choice(n, batch, replace=False))
+        pt = torch.as_tensor(pick, device=u.device)
+        W.predict(net, res[pick], idx[pick], u[pt].contiguous(), v[pt].contiguous())
+        loss = net.loss_backward(batch, tgt[pt].contiguous())
+        net.adam(lrf(s))
+        if s % 250 == 0 or s == steps - 1:
+            hist.append((s, float(loss), time.perf_counter() - t0))
+            log(f"train step {s} loss {float(loss):.3e} ({time.perf_counter() - t0:.1f} s)")
+    return hist
+
+
+def start_packs(ctx, net, res, idx, u, v):
+    cold = ctx.new_pack()
+    y32, y16, y8 = W.predict(net, res, idx, u, v)
+    warm = W.warm_levels(ctx, ctx.new_pack(), y32, y16, y8)
+    return cold, warm
+
+
+def iters_to(out, target):
+    """First checked iteration with r <= target per instance (-1: never)."""
+    it = np.full(len(out.r_final), -1)
+    for i, r in out.r_history:
+        hit = (it < 0) & (r <= target)
+        it[hit] = i
+    return it
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--n-train", type=int, default=2000)
+    ap.add_argument("--n-test", type=int, default=200)
+    ap.add_argument("--iters", type=int, default=30000)
+    ap.add_argument("--batch", type=int, default=250)
+    ap.add_argument("--train-steps", type=int, default=3000)
+    ap.add_argument("--direct", type=int, default=8, help="single-instance wall-clock solves")
+    args = ap.parse_args()
+    torch.manual_seed(0)
+    lr_cold = 3e-3
+    t_all = time.time()
+    log("generating training data")
+    train_seeds = list(range(args.n_train))
+    test_seeds = list(range(100000, 100000 + args.n_test))
+    data = dataset(train_seeds, args.iters, lr_cold, args.batch)
+    log("training the network")
+    net = W.WarmStartNet(W.NetConfig(batch=64), seed=0)
+    hist = train(net, data, args.train_steps, 1e-3, 64)
+    # held-out instances: reference solutions give their observations
+    log("solving the held-out instances (cold start)")
+    tres, tidx = W.instances(test_seeds)
+    ctx_ref, ref = cold_solve(tres, args.iters, lr_cold, progress=False)
+    fine = W.fine_fields(ctx_ref, ref.theta)
+    tu, tv = W.observe(fine, tidx)
+    ty = W.canonical_targets(fine.double())
+    ctx_ref.close()
+    # schedule choice on training instances (first 32), frozen afterwards
+    log("choosing step schedules on training instances")
+    sub = slice(0, 32)
+    sres, sidx = data[0][sub], data[1][sub]
+    su, sv = data[2][sub].contiguous(), data[3][sub].contiguous()
+    grid = [(lr0, n) for lr0 in (3e-3, 1e-3, 3e-4, 1e-4, 3e-5, 1e-5)
+            for n in (30000, 15000, 7500, 3000, 1500)]
+    best = {}
+    for which in ("cold", "warm"):
+        scores = []
+        for lr0, n in grid:
+            if which == "cold" and lr0 < 1e-3:
+                continue
+            ctx = W.cavity_context(sres)
+            cold, warm = start_packs(ctx, net, sres, sidx, su, sv)
+            th = cold if which == "cold" else W.choose_start(ctx, cold, warm)[0]
+            out = solve(ctx, th, cosine_lr(lr0, 1e-6, n), n, r_target=1e-6, check_every=50)
+            it = out.iterations.astype(float)
+            it[it < 0] = np.inf
+            scores.append((np.median(it), float(np.median(out.r_final)), lr0, n))
+            log(f"  {which} lr0 {lr0:g} n {n}: median iterations {np.median(it)}, median r {np.median(out.r_final):.2e}")
+            ctx.close()
+        scores.sort(key=lambda t: (t[0], t[1]))
+        best[which] = scores[0]
+    log(f"chosen: {best}")
+    # evaluation on held-out instances
+    results = {}
+    for which in ("cold", "warm"):
+        _, _, lr0, n = best[which]
+        ctx = W.cavity_context(tres)
+        cold, warm = start_packs(ctx, net, tres, tidx, tu, tv)
+        if which == "cold":
+            th, used = cold, np.zeros(len(tres), bool)
+        else:
+            th, used = W.choose_start(ctx, cold, warm)
+        r0 = ctx.residual_metric(th).cpu().numpy()
+        err0 = torch.sqrt(((W.fine_fields(ctx, th) - fine) ** 2)[:, :2].mean(dim=(1, 2, 3))).cpu().numpy()
+        out = solve(ctx, th, cosine_lr(lr0, 1e-6, n), max(n, args.iters), r_target=1e-6, check_every=50)
+        it6 = out.iterations
+        it5 = iters_to(out, 1e-5)
+        fine_s = W.fine_fields(ctx, out.theta)
+        err = torch.sqrt(((fine_s - fine) ** 2)[:, :2].mean(dim=(1, 2, 3))).cpu().numpy()
+        results[which] = {"lr0": lr0, "schedule_iters": n, "iters_1e-6": it6.tolist(),
+                          "iters_1e-5": it5.tolist(), "r0": r0.tolist(), "velocity_rms_start": err0.tolist(), "r_final": out.r_final.tolist(),
+                          "used_warm": used.tolist(), "velocity_rms_vs_reference": err.tolist()}
+        log(f"{which}: reached 1e-6 {np.mean(it6 >= 0):.2f}, median iters {np.median(it6[it6 >= 0]) if np.any(it6 >= 0) else -1}")
+        ctx.close()
+    # timing: per-iteration time of a single-instance solve and the inference cost
+    ctx1 = W.cavity_context(tres[:1])
+    th1 = ctx1.new_pack()
+    a, b, m, v = th1.clone(), ctx1.new_pack(), ctx1.new_pack(), ctx1.new_pack()
+    for i in range(200):
+        ctx1.step(a, b, m, v, i + 1, lr=1e-4)
+        a, b = b, a
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(2000):
+        ctx1.step(a, b, m, v, 201 + i, lr=1e-4)
+        a, b = b, a
+    torch.cuda.synchronize()
+    t_iter = (time.perf_counter() - t0) / 2000
+    for _ in range(5):
+        start_packs(ctx1, net, tres[:1], tidx[:1], tu[:1].contiguous(), tv[:1].contiguous())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(50):
+        start_packs(ctx1, net, tres[:1], tidx[:1], tu[:1].contiguous(), tv[:1].contiguous())
+    torch.cuda.synchronize()
+    t_inf = (time.perf_counter() - t0) / 50
+    # direct single-instance wall-clock solves
+    direct = []
+    for k in range(args.direct):
+        row = {"re": float(tres[k])}
+        for which in ("cold", "warm"):
+            _, _, lr0, n = best[which]
+            ctx = W.cavity_context(tres[k:k + 1])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            cold, warm = start_packs(ctx, net, tres[k:k + 1], tidx[k:k + 1], tu[k:k + 1].contiguous(),
+                                     tv[k:k + 1].contiguous())
+            th = cold if which == "cold" else W.choose_start(ctx, cold, warm)[0]
+            out = solve(ctx, th, cosine_lr(lr0, 1e-6, n), max(n, args.iters), r_target=1e-6, check_every=50)
+            row[which] = {"iters": int(out.iterations[0]), "seconds": time.perf_counter() - t0,
+                          "r_final": float(out.r_final[0])}
+            ctx.close()
+        direct.append(row)
+        log(f"direct {k}: {row}")
+    summ = {}
+    for which in ("cold", "warm"):
+        it = np.array(results[which]["iters_1e-6"])
+        ok = it >= 0
+        q = np.percentile(it[ok], [25, 50, 75]).tolist() if ok.any() else [None] * 3
+        extra = t_inf if which == "warm" else 0.0
+        summ[which] = {"reached_1e-6": float(ok.mean()), "iters_quartiles": q,
+                       "seconds_median": (q[1] * t_iter + extra) if q[1] is not None else None}
+    both = (np.array(results["cold"]["iters_1e-6"]) >= 0) & (np.array(results["warm"]["iters_1e-6"]) >= 0)
+    if both.any():
+        ratio = np.array(results["cold"]["iters_1e-6"])[both] / np.maximum(np.array(results["warm"]["iters_1e-6"])[both], 1)
+        summ["speedup_iters_median_on_common"] = float(np.median(ratio))
+    summary = {"n_train": args.n_train, "n_test": args.n_test, "train_loss": hist,
+               "schedules": {k: {"lr0": v[2], "iters": v[3]} for k, v in best.items()},
+               "seconds_per_iteration_single": t_iter, "seconds_inference_single": t_inf,
+               "summary": summ, "per_instance": results, "direct": direct,
+               "train_r_final_median": float(np.median(data[5])), "total_seconds": time.time() - t_all}
+    json.dump(summary, open(args.out, "w"))
+    torch.save({"master": net.master.cpu()}, args.out.replace(".json", "_net.pt"))
+    log(f"done: {json.dumps(summ)}")
+
+
+if __name__ == "__main__":
+    main()
