@@ -20,6 +20,8 @@ N_TERMS = 5
 FIELD_FORCING0, FIELD_CHI = 0, 4
 SCALAR_RE = 0
 OPT_FUSED = 0
+OPT_MARCH = 1
+OPT_MARCH_TILE = 2
 MAX_LEVELS, MAX_FIELDS = 8, 5
 TERM_NAMES = ("pde", "data", "reg", "ic", "bc")
 

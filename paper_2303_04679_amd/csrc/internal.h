@@ -103,6 +103,8 @@ struct modil_ctx {
   double *fm_val = nullptr, *fm_w = nullptr;
   bool fused_enabled = true;  // MODIL_OPT_FUSED
   bool fused_ok = false;      // measurements admit the fused kernel
+  bool march_enabled = true;  // MODIL_OPT_MARCH
+  int march_tile = 0;         // MODIL_OPT_MARCH_TILE
 
   long n_fine_blocks = 0;   // partial blocks of the fine kernel per instance
   long n_data_blocks = 0;   // partial blocks of the data kernel per instance
@@ -148,6 +150,12 @@ hipError_t launch_horner(modil_ctx *c, const void *theta, void *fine_dst, bool s
 // Adam on every level it produces.
 hipError_t launch_restrict_chain(modil_ctx *c, void *g, int from_level, const void *th_in,
                                  void *th_out, void *m, void *v, const AdamHost *adam);
+// Marching restriction of level l -> l+1 with optional Adam (restrict_march.hip);
+// returns false, launching nothing, when the level's shape does not admit it.
+// tile: 16 * rows + planes per wave, 0 = automatic.
+template <typename T>
+bool launch_restrict_march(const Levels &G, int l, T *g, const AdamArgs<T> &A, bool adam, int tile,
+                           hipStream_t s);
 hipError_t launch_adam(modil_ctx *c, const void *theta_in, void *theta_out, void *m, void *v,
                        const void *g, long n, const AdamHost &h);
 hipError_t launch_fine(modil_ctx *c, const void *u, void *g, bool want_grad);

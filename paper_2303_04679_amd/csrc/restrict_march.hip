@@ -1,0 +1,388 @@
+// Marching restriction with Adam: g_{l+1} = T^T g_l on one level, followed by
+// Adam on the level-(l+1) parameters, for fields that span every axis they
+// have (Section 2.2: T is the tensor product of the 1-D cell-based
+// interpolation, so T^T is applied one axis at a time).
+//
+// A wave owns a run of coarse cells along x (one lane per coarse cell, up to
+// 64 per row; narrower rows pack several row groups into a wave), YR coarse
+// rows and ZR coarse planes.  Each fine value is loaded once per wave:
+//   x  a lane loads its two fine cells 2J, 2J+1 as one vector load and takes
+//      the neighbours 2J-1, 2J+2 (and the extrapolated end cells) from the
+//      adjacent lanes by shuffles;
+//   y  the fine rows of a plane are scattered into the YR coarse rows with the
+//      weights of T (each fine row feeds two coarse rows);
+//   z  the wave marches through the fine planes two at a time; a fine plane
+//      feeds the previous, current and next coarse plane accumulators, and the
+//      previous one is complete once both planes of a step are in.
+// The loads of both planes of a step are issued before any of them is used.
+// Summation order is fixed, so results are deterministic.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace modil {
+
+template <typename T> struct Pair;
+template <> struct Pair<float> { using type = float2; };
+template <> struct Pair<double> { using type = double2; };
+
+constexpr int kMarchWaves = 4;  // waves per block
+
+struct MarchPlan {
+  int W;          // lanes per coarse row (min(64, coarse nx))
+  int wshift;     // log2(W)
+  int groups;     // row groups per wave (64 / W)
+  int nseg;       // 64-lane segments per coarse row (coarse nx / 64, or 1)
+  int nyc, nzc;   // y and z chunks
+  int n_tasks;    // waves with work
+};
+
+// One fine row of a plane: the lane's two cells and, with SEG, the cells
+// just outside the lane's 64-wide segment (edge lanes only; others reload
+// their own cells, which stay in the same cache line).
+template <typename T, bool SEG>
+struct RowLoad {
+  T a, b, lo, hi;
+};
+
+template <typename T, bool SEG>
+__device__ inline RowLoad<T, SEG> load_row(const T *__restrict__ r, int cx, int lo_off, int hi_off) {
+  using P2 = typename Pair<T>::type;
+  RowLoad<T, SEG> v;
+  const P2 ab = *reinterpret_cast<const P2 *>(r + 2 * cx);
+  v.a = ab.x;
+  v.b = ab.y;
+  if (SEG) {
+    v.lo = r[lo_off];
+    v.hi = r[hi_off];
+  } else {
+    v.lo = v.hi = T(0);
+  }
+  return v;
+}
+
+// Column value (T^T along x) of one row: every lane executes the shuffles.
+template <typename T, bool SEG>
+__device__ inline T x_restrict(const RowLoad<T, SEG> &v, int W, int gl, int cx, int cnx) {
+  T left = __shfl_up(v.b, 1, W);    // fine 2J-1
+  T right = __shfl_down(v.a, 1, W);  // fine 2J+2
+  const T e0 = __shfl_up(v.a, 1, W);    // fine 0, for J = 1
+  const T e1 = __shfl_down(v.b, 1, W);  // fine 2n-1, for J = n-2
+  if (SEG) {
+    if (gl == 0) left = v.lo;
+    if (gl == W - 1) right = v.hi;
+  }
+  T x = (cx == 0 ? T(1.25) : T(0.75)) * v.a + (cx == cnx - 1 ? T(1.25) : T(0.75)) * v.b;
+  if (cx > 0) x += T(0.25) * left;
+  if (cx < cnx - 1) x += T(0.25) * right;
+  if (cx == 1) x -= T(0.25) * e0;
+  if (cx == cnx - 2) x -= T(0.25) * e1;
+  return x;
+}
+
+// Rows of a plane, in order: k = 0 is fine row 2 Y0 - 1 (it feeds coarse row
+// Y0 with 1/4); k = 1 .. 2 YR are the rows 2 Y0 .. 2 (Y0 + YR) - 1 the wave
+// owns; k = 2 YR + 1 is row 2 (Y0 + YR) (1/4 to coarse row Y0 + YR - 1).  With
+// YR >= 2 the two extrapolated end rows (fine row 0 feeding coarse row 1, the
+// last fine row feeding coarse row ny/2 - 2) lie inside the owned rows.  A row
+// outside the grid is clamped onto an owned one (same cache lines) and skipped.
+template <int YR>
+__device__ inline int row_of(int k, int Y0, int ny) {
+  if (k == 0) return Y0 > 0 ? 2 * Y0 - 1 : 0;
+  if (k <= 2 * YR) return 2 * Y0 + k - 1;
+  return 2 * (Y0 + YR) < ny ? 2 * (Y0 + YR) : ny - 1;
+}
+
+// T^T along y of one plane from its loaded rows into P[0..YR-1]
+template <typename T, int YR, bool SEG>
+__device__ inline void y_restrict(const RowLoad<T, SEG> (&rows)[2 * YR + 2], int W, int gl, int cx,
+                                  int cnx, int Y0, int ny, T (&P)[YR]) {
+  static_assert(YR >= 2, "the end rows must fall inside the owned rows");
+  const int cny = ny >> 1;
+#pragma unroll
+  for (int j = 0; j < YR; ++j) P[j] = T(0);
+#pragma unroll
+  for (int k = 0; k < 2 * YR + 2; ++k) {
+    const T x = x_restrict<T, SEG>(rows[k], W, gl, cx, cnx);
+    if (k == 0) {
+      if (Y0 > 0) P[0] += T(0.25) * x;
+    } else if (k <= 2 * YR) {
+      const int j = (k - 1) >> 1;  // coarse row (relative) of fine row 2 Y0 + k - 1
+      if (k & 1) {                 // even fine row 2 (Y0 + j)
+        const bool end = Y0 + j == 0;
+        P[j] += (end ? T(1.25) : T(0.75)) * x;
+        if (end) {
+          if (j + 1 < YR) P[j + 1] -= T(0.25) * x;
+        } else if (j >= 1) {
+          P[j - 1] += T(0.25) * x;
+        }
+      } else {  // odd fine row 2 (Y0 + j) + 1
+        const bool end = Y0 + j == cny - 1;
+        P[j] += (end ? T(1.25) : T(0.75)) * x;
+        if (end) {
+          if (j >= 1) P[j - 1] -= T(0.25) * x;
+        } else if (j + 1 < YR) {
+          P[j + 1] += T(0.25) * x;
+        }
+      }
+    } else {
+      if (Y0 + YR < cny) P[YR - 1] += T(0.25) * x;
+    }
+  }
+}
+
+template <typename T, int YR, bool SEG>
+__device__ inline void load_plane(const T *__restrict__ pb, int nx, int Y0, int ny, int cx,
+                                  int lo_off, int hi_off, RowLoad<T, SEG> (&rows)[2 * YR + 2]) {
+#pragma unroll
+  for (int k = 0; k < 2 * YR + 2; ++k)
+    rows[k] = load_row<T, SEG>(pb + (long)row_of<YR>(k, Y0, ny) * nx, cx, lo_off, hi_off);
+}
+
+template <typename T, int YR, bool ADAM>
+__device__ inline void emit_rows(T *__restrict__ g, const AdamArgs<T> &A, long e0, int cnx,
+                                 const T (&val)[YR], const T (&th)[YR], const T (&m)[YR],
+                                 const T (&v)[YR]) {
+#pragma unroll
+  for (int j = 0; j < YR; ++j) {
+    const long e = e0 + (long)j * cnx;
+    g[e] = val[j];
+    if (ADAM) {
+      const T mm = A.b1 * m[j] + (T(1) - A.b1) * val[j];
+      const T vv = A.b2 * v[j] + (T(1) - A.b2) * val[j] * val[j];
+      A.m[e] = mm;
+      A.v[e] = vv;
+      A.th_out[e] = th[j] - A.step * mm / (sqrt(vv) * A.isb2 + A.eps);
+    }
+  }
+}
+
+template <typename T, int YR, bool ADAM>
+__device__ inline void load_adam(const AdamArgs<T> &A, long e0, int cnx, T (&th)[YR], T (&m)[YR],
+                                 T (&v)[YR]) {
+#pragma unroll
+  for (int j = 0; j < YR; ++j) {
+    if (ADAM) {
+      const long e = e0 + (long)j * cnx;
+      th[j] = A.th_in[e];
+      m[j] = A.m[e];
+      v[j] = A.v[e];
+    } else {
+      th[j] = m[j] = v[j] = T(0);
+    }
+  }
+}
+
+template <typename T, int YR, int ZR, bool SPANZ, bool SEG, bool ADAM>
+__global__ __launch_bounds__(64 * kMarchWaves) void restrict_march_kernel(Levels G, int l, T *g,
+                                                                          AdamArgs<T> A, MarchPlan P) {
+  // blocks with consecutive logical indices land on the same XCD (blocks are
+  // dealt round-robin over the 8 XCDs), so neighbouring tiles share an L2
+  const int B = gridDim.x, b = blockIdx.x, xcd = b & 7;
+  const int q = B >> 3, r = B & 7;
+  const int lb = xcd * q + (xcd < r ? xcd : r) + (b >> 3);
+  const int task = lb * kMarchWaves + (threadIdx.x >> 6);
+  if (task >= P.n_tasks) return;  // whole waves
+  const int lane = threadIdx.x & 63;
+  int t = task;
+  const int yc = t % P.nyc;
+  t /= P.nyc;
+  const int zc = t % P.nzc;
+  t /= P.nzc;
+  const int seg = t % P.nseg;
+  t /= P.nseg;
+  const int f = t % G.nf;
+  const int inst = t / G.nf;
+
+  const int W = P.W;
+  const int grp = lane >> P.wshift, gl = lane & (W - 1);
+  const int nz = G.n[l][f][0], ny = G.n[l][f][1], nx = G.n[l][f][2];
+  const int cnx = nx >> 1, cny = ny >> 1;
+  const int cx = seg * 64 + gl;
+  const int Y0 = (yc * P.groups + grp) * YR;
+  const int lo_off = (SEG && gl == 0 && cx > 0) ? 2 * cx - 1 : 2 * cx;
+  const int hi_off = (SEG && gl == W - 1 && cx < cnx - 1) ? 2 * cx + 2 : 2 * cx + 1;
+
+  const T *fb = g + G.off[l] + (long)inst * G.stride[l] + G.foff[l][f];
+  const long cbase = G.off[l + 1] + (long)inst * G.stride[l + 1] + G.foff[l + 1][f];
+  const long plane_f = (long)ny * nx;
+  const long plane_c = (long)cny * cnx;
+  const long row0 = (long)Y0 * cnx + cx;
+
+  T th[YR], m[YR], v[YR];
+  if (!SPANZ) {
+    RowLoad<T, SEG> rows[2 * YR + 2];
+    load_adam<T, YR, ADAM>(A, cbase + row0, cnx, th, m, v);
+    load_plane<T, YR, SEG>(fb, nx, Y0, ny, cx, lo_off, hi_off, rows);
+    T Pl[YR];
+    y_restrict<T, YR, SEG>(rows, W, gl, cx, cnx, Y0, ny, Pl);
+    emit_rows<T, YR, ADAM>(g, A, cbase + row0, cnx, Pl, th, m, v);
+    return;
+  }
+
+  const int cnz = nz >> 1;
+  const int Z0 = zc * ZR;
+  T Ap[YR], Ac[YR], An[YR];
+#pragma unroll
+  for (int j = 0; j < YR; ++j) Ap[j] = Ac[j] = An[j] = T(0);
+  const int Jbeg = Z0 - 1 > 0 ? Z0 - 1 : 0;
+  const int Jend = Z0 + ZR < cnz - 1 ? Z0 + ZR : cnz - 1;
+  for (int J = Jbeg; J <= Jend; ++J) {
+    // step J takes fine planes 2J and 2J+1; they feed coarse planes J-1, J, J+1
+    const int za = 2 * J, zb = 2 * J + 1;
+    const bool emit = J - 1 >= Z0 && J - 1 < Z0 + ZR;
+    const bool needA = !(J == Z0 - 1 && za != 0);       // plane 2J feeds only J-1, J-2 there
+    const bool needB = !(J == Z0 + ZR && zb != nz - 1);  // plane 2J+1 feeds only J, J+1 there
+    if (emit) load_adam<T, YR, ADAM>(A, cbase + (long)(J - 1) * plane_c + row0, cnx, th, m, v);
+    RowLoad<T, SEG> ra[2 * YR + 2], rb[2 * YR + 2];
+    if (needA) load_plane<T, YR, SEG>(fb + za * plane_f, nx, Y0, ny, cx, lo_off, hi_off, ra);
+    if (needB) load_plane<T, YR, SEG>(fb + zb * plane_f, nx, Y0, ny, cx, lo_off, hi_off, rb);
+    if (needA) {
+      T Pa[YR];
+      y_restrict<T, YR, SEG>(ra, W, gl, cx, cnx, Y0, ny, Pa);
+      const T wa = za == 0 ? T(1.25) : T(0.75);
+#pragma unroll
+      for (int j = 0; j < YR; ++j) {
+        Ac[j] += wa * Pa[j];
+        if (za == 0)
+          An[j] -= T(0.25) * Pa[j];
+        else
+          Ap[j] += T(0.25) * Pa[j];
+      }
+    }
+    if (needB) {
+      T Pb[YR];
+      y_restrict<T, YR, SEG>(rb, W, gl, cx, cnx, Y0, ny, Pb);
+      const bool last = zb == nz - 1;
+      const T wb = last ? T(1.25) : T(0.75);
+#pragma unroll
+      for (int j = 0; j < YR; ++j) {
+        Ac[j] += wb * Pb[j];
+        if (last)
+          Ap[j] -= T(0.25) * Pb[j];
+        else
+          An[j] += T(0.25) * Pb[j];
+      }
+    }
+    if (emit) emit_rows<T, YR, ADAM>(g, A, cbase + (long)(J - 1) * plane_c + row0, cnx, Ap, th, m, v);
+#pragma unroll
+    for (int j = 0; j < YR; ++j) {
+      Ap[j] = Ac[j];
+      Ac[j] = An[j];
+      An[j] = T(0);
+    }
+  }
+  // the last coarse plane is complete after the last step
+  if (Jend == cnz - 1 && cnz - 1 >= Z0 && cnz - 1 < Z0 + ZR) {
+    const long e0 = cbase + (long)(cnz - 1) * plane_c + row0;
+    load_adam<T, YR, ADAM>(A, e0, cnx, th, m, v);
+    emit_rows<T, YR, ADAM>(g, A, e0, cnx, Ap, th, m, v);
+  }
+}
+
+// ------------------------------------------------------------------ host side
+// Tile choice: rows per wave YR and planes per wave ZR, 0 = automatic.
+static void choose_tile(int cnx, int cny, int cnz, bool spanz, int req, int &YR, int &ZR) {
+  YR = req ? (req >> 4) : 4;
+  ZR = req ? (req & 15) : 4;
+  if (!req && spanz) {
+    // keep enough waves in flight on small levels
+    const long cells = (long)cnx * cny * cnz;
+    if (cells <= 32L * 32 * 32) { YR = 2; ZR = 1; }
+    else if (cells <= 64L * 64 * 64) { YR = 4; ZR = 2; }
+  }
+  if (!spanz) ZR = 1;
+}
+
+// The marching kernel applies to level l -> l+1 when every field has the
+// same shape, spans x and y (and z, or no z at all), the coarse rows are
+// whole 64-lane segments or a power of two of at least 16 cells, the tiles
+// divide the coarse grid, and g admits paired loads.
+bool restrict_march_ok(const Levels &G, int l, const void *g, size_t elem, int req, int &YR, int &ZR,
+                       bool &spanz, MarchPlan &P) {
+  if (l + 1 >= G.L) return false;
+  if (reinterpret_cast<uintptr_t>(g) % (2 * elem)) return false;
+  for (int f = 1; f < G.nf; ++f)
+    for (int a = 0; a < 3; ++a)
+      if (G.n[l][f][a] != G.n[l][0][a] || G.n[l + 1][f][a] != G.n[l + 1][0][a]) return false;
+  const int nz = G.n[l][0][0], ny = G.n[l][0][1], nx = G.n[l][0][2];
+  const int cnz = G.n[l + 1][0][0], cny = G.n[l + 1][0][1], cnx = G.n[l + 1][0][2];
+  if (nx != 2 * cnx || ny != 2 * cny) return false;
+  spanz = nz > 1;
+  if (spanz ? nz != 2 * cnz : cnz != 1) return false;
+  if (cnx % 64 == 0) {
+    P.W = 64;
+    P.nseg = cnx / 64;
+  } else if (cnx >= 16 && cnx < 64 && (cnx & (cnx - 1)) == 0) {
+    P.W = cnx;
+    P.nseg = 1;
+  } else {
+    return false;
+  }
+  P.wshift = 0;
+  while ((1 << P.wshift) < P.W) ++P.wshift;
+  P.groups = 64 / P.W;
+  choose_tile(cnx, cny, spanz ? cnz : 1, spanz, req, YR, ZR);
+  if (cny % (P.groups * YR)) return false;
+  if (spanz && cnz % ZR) return false;
+  P.nyc = cny / (P.groups * YR);
+  P.nzc = spanz ? cnz / ZR : 1;
+  const long tasks = (long)G.batch * G.nf * P.nseg * P.nyc * P.nzc;
+  if (tasks > (1L << 30)) return false;
+  P.n_tasks = (int)tasks;
+  return true;
+}
+
+template <typename T, int YR, int ZR, bool ADAM>
+static void launch_march_yz(const Levels &G, int l, T *g, const AdamArgs<T> &A, const MarchPlan &P,
+                            bool spanz, hipStream_t s) {
+  const unsigned blocks = (unsigned)((P.n_tasks + kMarchWaves - 1) / kMarchWaves);
+  const dim3 grid(blocks), block(64 * kMarchWaves);
+  const bool seg = P.nseg > 1;
+  if (spanz) {
+    if (seg)
+      restrict_march_kernel<T, YR, ZR, true, true, ADAM><<<grid, block, 0, s>>>(G, l, g, A, P);
+    else
+      restrict_march_kernel<T, YR, ZR, true, false, ADAM><<<grid, block, 0, s>>>(G, l, g, A, P);
+  } else {
+    if (seg)
+      restrict_march_kernel<T, YR, 1, false, true, ADAM><<<grid, block, 0, s>>>(G, l, g, A, P);
+    else
+      restrict_march_kernel<T, YR, 1, false, false, ADAM><<<grid, block, 0, s>>>(G, l, g, A, P);
+  }
+}
+
+template <typename T, bool ADAM>
+static bool launch_march_t(const Levels &G, int l, T *g, const AdamArgs<T> &A, const MarchPlan &P,
+                           int YR, int ZR, bool spanz, hipStream_t s) {
+  switch (YR * 16 + (spanz ? ZR : 1)) {
+    case 2 * 16 + 1: launch_march_yz<T, 2, 1, ADAM>(G, l, g, A, P, spanz, s); return true;
+    case 2 * 16 + 2: launch_march_yz<T, 2, 2, ADAM>(G, l, g, A, P, spanz, s); return true;
+    case 2 * 16 + 4: launch_march_yz<T, 2, 4, ADAM>(G, l, g, A, P, spanz, s); return true;
+    case 4 * 16 + 1: launch_march_yz<T, 4, 1, ADAM>(G, l, g, A, P, spanz, s); return true;
+    case 4 * 16 + 2: launch_march_yz<T, 4, 2, ADAM>(G, l, g, A, P, spanz, s); return true;
+    case 4 * 16 + 4: launch_march_yz<T, 4, 4, ADAM>(G, l, g, A, P, spanz, s); return true;
+    case 4 * 16 + 8: launch_march_yz<T, 4, 8, ADAM>(G, l, g, A, P, spanz, s); return true;
+    default: return false;
+  }
+}
+
+// Launch the marching restriction (and Adam) of level l -> l+1 if it
+// applies; returns false (nothing launched) otherwise.
+template <typename T>
+bool launch_restrict_march(const Levels &G, int l, T *g, const AdamArgs<T> &A, bool adam, int req,
+                           hipStream_t s) {
+  int YR, ZR;
+  bool spanz;
+  MarchPlan P{};
+  if (!restrict_march_ok(G, l, g, sizeof(T), req, YR, ZR, spanz, P)) return false;
+  return adam ? launch_march_t<T, true>(G, l, g, A, P, YR, ZR, spanz, s)
+              : launch_march_t<T, false>(G, l, g, A, P, YR, ZR, spanz, s);
+}
+
+template bool launch_restrict_march<float>(const Levels &, int, float *, const AdamArgs<float> &,
+                                           bool, int, hipStream_t);
+template bool launch_restrict_march<double>(const Levels &, int, double *,
+                                            const AdamArgs<double> &, bool, int, hipStream_t);
+
+}  // namespace modil

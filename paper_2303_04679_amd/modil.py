@@ -250,6 +250,15 @@ class Context:
         """Use the fused finest-level kernel where one exists (default) or the generic engine."""
         L.check(L.lib().modil_set_option(self.h, L.OPT_FUSED, 1 if enabled else 0), self.h)
 
+    def set_march(self, enabled: bool):
+        """Restrict with the marching kernel where a level admits it (default) or
+        with the per-cell gather kernel."""
+        L.check(L.lib().modil_set_option(self.h, L.OPT_MARCH, 1 if enabled else 0), self.h)
+
+    def set_march_tile(self, rows: int = 0, planes: int = 0):
+        """Coarse rows and planes per wave of the marching kernel (0, 0: automatic)."""
+        L.check(L.lib().modil_set_option(self.h, L.OPT_MARCH_TILE, 16 * rows + planes), self.h)
+
     def check(self):
         """Synchronise; raise ModilError on a non-finite loss or a HIP error."""
         L.check(L.lib().modil_check(self.h), self.h)

@@ -226,8 +226,19 @@ def observe(fine, idx):
 
 
 def predict(net, re, idx, u_obs, v_obs):
-    """Head maps (y32, y16, y8) for a batch of instances."""
+    """Head maps (y32, y16, y8) for a batch of instances.  Up to the network's
+    batch capacity the maps are views of its output buffer (and its
+    activations stay in place for loss_backward); larger batches are run in
+    chunks and returned as new tensors."""
     B = len(re)
+    cap = net.cfg.batch
+    if B > cap:
+        parts = []
+        for s in range(0, B, cap):
+            e = min(B, s + cap)
+            y = predict(net, re[s:e], idx[s:e], u_obs[s:e].contiguous(), v_obs[s:e].contiguous())
+            parts.append([t.clone() for t in y])
+        return [torch.cat([p[k] for p in parts]) for k in range(3)]
     dev = net.device
     net.rasterize(torch.as_tensor(idx, device=dev), u_obs, v_obs,
                   torch.as_tensor(np.asarray(re, dtype=np.float32), device=dev), batch=B)
