@@ -245,6 +245,11 @@ int modil_residual_metric(modil_ctx *ctx, const void *theta_pack, double *r);
  * that level to the gather kernel.                                        */
 #define MODIL_OPT_MARCH 1
 #define MODIL_OPT_MARCH_TILE 2
+/* MODIL_OPT_TAIL (default 1): the small coarse levels of each instance (from
+ * the first level that fits in one block's LDS together with the next one)
+ * are prolonged, and restricted with Adam, by one launch with one block per
+ * instance working in LDS; 0 launches one kernel per level instead.       */
+#define MODIL_OPT_TAIL 3
 int modil_set_option(modil_ctx *ctx, int32_t option, int64_t value);
 
 /* ---- health and timing ---------------------------------------------------
@@ -319,6 +324,68 @@ int modil_cnn_adam(modil_cnn *net, float *master, uint16_t *params_bf16, float *
                    const float *grad, const modil_adam_hp *hp, int64_t step);
 /* params_bf16 = round-to-nearest-even(master) */
 int modil_cnn_to_bf16(modil_cnn *net, const float *master, uint16_t *params_bf16);
+
+/* ---- L-BFGS ----------------------------------------------------------------
+ * Limited-memory BFGS on the loss and gradient of a context: the optimiser of
+ * most results of the paper (SciPy's L-BFGS-B without bounds, Section 2.1; a
+ * history of 50 pairs in Section 3.1).
+ *   direction  d = -H g, H the L-BFGS matrix of the stored pairs with
+ *              H0 = gamma I, gamma = s^T y / y^T y of the newest pair, applied
+ *              through its compact representation (Byrd, Nocedal & Schnabel
+ *              1994): two passes over the stored pairs per iteration;
+ *              d = -g while no pair is stored
+ *   step       a line search that brackets a step satisfying the strong Wolfe
+ *              conditions and zooms in (Nocedal & Wright, Algorithms 3.5 and
+ *              3.6) with safeguarded cubic trial steps; first trial step
+ *              min(1, 1/||d||) without pairs, else 1; the bracketing phase
+ *              doubles the step; after max_evals evaluations the best point
+ *              with sufficient decrease is taken (status 1), if there is one
+ *   memory     the pair s = alpha d, y = g_new - g is stored when
+ *              s^T y > eps y^T y (FP64 unit roundoff); beyond `history` pairs
+ *              the oldest is dropped; a non-descent direction clears it
+ * The objective is the sum of all loss terms of all batch instances; the
+ * instances are optimised as one vector.
+ *
+ * State: a caller-provided device workspace of modil_lbfgs_workspace bytes
+ * (256-byte aligned): history + 1 pair slots and four more pack-sized
+ * vectors in the problem dtype, and FP64 partial sums.  The small matrices S^T Y and Y^T Y
+ * stay on the host in FP64.  Dot products accumulate in FP64 in a fixed order
+ * (deterministic).  The object keeps pointers into the workspace and uses the
+ * context's stream; it allocates pinned host memory for the scalars it
+ * exchanges with the device.  Every line-search evaluation synchronises the
+ * stream once.
+ *
+ * modil_lbfgs_step: one iteration on theta (device pack, updated in place to
+ * the accepted point).  The first call after create / reset also evaluates
+ * the loss and gradient at theta.  Between calls theta must not change; call
+ * modil_lbfgs_reset after changing it.  On status 2 (no step found) theta is
+ * unchanged and the memory is cleared.                                    */
+typedef struct modil_lbfgs modil_lbfgs;
+
+#define MODIL_LBFGS_MAX_HISTORY 64
+
+typedef struct {
+  int32_t history;    /* stored pairs m, 1..MODIL_LBFGS_MAX_HISTORY */
+  int32_t max_evals;  /* loss-and-gradient evaluations per line search, >= 2 */
+  double c1, c2;      /* Wolfe constants, 0 < c1 < c2 < 1 */
+} modil_lbfgs_params;
+
+typedef struct {
+  double loss;        /* objective at theta after the call */
+  double grad_norm;   /* ||gradient||_2 at theta after the call */
+  double step;        /* accepted step length (0 if none) */
+  int32_t evals;      /* evaluations made by the call */
+  int32_t status;     /* 0 strong Wolfe step, 1 sufficient decrease only, 2 no step */
+  int32_t pairs;      /* stored pairs after the call */
+  int32_t iteration;  /* iterations since create / reset */
+} modil_lbfgs_info;
+
+int modil_lbfgs_workspace(const modil_ctx *ctx, int32_t history, size_t *bytes);
+int modil_lbfgs_create(modil_ctx *ctx, const modil_lbfgs_params *params, void *workspace,
+                       size_t workspace_bytes, modil_lbfgs **out);
+int modil_lbfgs_destroy(modil_lbfgs *lb);
+int modil_lbfgs_reset(modil_lbfgs *lb);
+int modil_lbfgs_step(modil_lbfgs *lb, void *theta, modil_lbfgs_info *info);
 
 #ifdef __cplusplus
 }

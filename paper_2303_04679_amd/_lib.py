@@ -22,6 +22,7 @@ SCALAR_RE = 0
 OPT_FUSED = 0
 OPT_MARCH = 1
 OPT_MARCH_TILE = 2
+OPT_TAIL = 3
 MAX_LEVELS, MAX_FIELDS = 8, 5
 TERM_NAMES = ("pde", "data", "reg", "ic", "bc")
 
@@ -84,6 +85,19 @@ class CnnLayout(ctypes.Structure):
                 ("workspace_bytes", ctypes.c_size_t)]
 
 
+class LbfgsParams(ctypes.Structure):
+    _fields_ = [("history", ctypes.c_int32), ("max_evals", ctypes.c_int32),
+                ("c1", ctypes.c_double), ("c2", ctypes.c_double)]
+
+
+class LbfgsInfo(ctypes.Structure):
+    _fields_ = [("loss", ctypes.c_double), ("grad_norm", ctypes.c_double), ("step", ctypes.c_double),
+                ("evals", ctypes.c_int32), ("status", ctypes.c_int32), ("pairs", ctypes.c_int32),
+                ("iteration", ctypes.c_int32)]
+
+
+LBFGS_MAX_HISTORY = 64
+
 _P = ctypes.c_void_p
 _I = ctypes.c_int
 _SIGS = {
@@ -119,6 +133,11 @@ _SIGS = {
     "modil_cnn_loss_backward": (_I, [_P, ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P]),
     "modil_cnn_adam": (_I, [_P, _P, _P, _P, _P, _P, ctypes.POINTER(AdamHP), ctypes.c_int64]),
     "modil_cnn_to_bf16": (_I, [_P, _P, _P]),
+    "modil_lbfgs_workspace": (_I, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
+    "modil_lbfgs_create": (_I, [_P, ctypes.POINTER(LbfgsParams), _P, ctypes.c_size_t, ctypes.POINTER(_P)]),
+    "modil_lbfgs_destroy": (_I, [_P]),
+    "modil_lbfgs_reset": (_I, [_P]),
+    "modil_lbfgs_step": (_I, [_P, _P, ctypes.POINTER(LbfgsInfo)]),
 }
 
 _lib = None

@@ -389,6 +389,12 @@ namespace modil {
 
 int set_global_error(int status, const std::string &msg) { return fail_global(status, msg); }
 
+int set_ctx_error(modil_ctx *c, int status, const std::string &msg) { return fail(c, status, msg); }
+
+int eval_loss_grad(modil_ctx *c, const void *theta, void *grad, double *terms) {
+  return evaluate(c, theta, grad, terms);
+}
+
 int op_fields(const modil_problem &p) {
   switch (p.op) {
     case MODIL_OP_POISSON:
@@ -483,6 +489,13 @@ int modil_create(const modil_problem *p, void *ws, size_t ws_bytes, void *stream
   c->ws = (char *)ws;
   c->ws_bytes = ws_bytes;
   (void)hipGetDevice(&c->device);
+  {
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) ==
+            hipSuccess &&
+        lds > 0)
+      c->lds_budget = std::min<size_t>((size_t)lds, 160 * 1024);
+  }
   const Carve cv = carve(*p, L);
   c->w_buf = c->ws + cv.w;
   c->g_buf = c->ws + cv.g;
@@ -708,6 +721,10 @@ int modil_set_option(modil_ctx *c, int32_t option, int64_t value) {
   }
   if (option == MODIL_OPT_MARCH) {
     c->march_enabled = value != 0;
+    return MODIL_OK;
+  }
+  if (option == MODIL_OPT_TAIL) {
+    c->tail_enabled = value != 0;
     return MODIL_OK;
   }
   if (option == MODIL_OPT_MARCH_TILE) {

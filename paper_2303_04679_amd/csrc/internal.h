@@ -105,6 +105,8 @@ struct modil_ctx {
   bool fused_ok = false;      // measurements admit the fused kernel
   bool march_enabled = true;  // MODIL_OPT_MARCH
   int march_tile = 0;         // MODIL_OPT_MARCH_TILE
+  bool tail_enabled = true;   // MODIL_OPT_TAIL
+  size_t lds_budget = 64 * 1024;  // LDS bytes one block of the tail kernels may use
 
   long n_fine_blocks = 0;   // partial blocks of the fine kernel per instance
   long n_data_blocks = 0;   // partial blocks of the data kernel per instance
@@ -135,6 +137,10 @@ Levels levels_of(const modil_ctx *c);
 
 // record the message returned by modil_last_error(NULL); returns status
 int set_global_error(int status, const std::string &msg);
+// record an error on a context (and globally); returns status
+int set_ctx_error(modil_ctx *c, int status, const std::string &msg);
+// loss terms [batch][5] and, if grad is not null, the gradient pack at theta
+int eval_loss_grad(modil_ctx *c, const void *theta, void *grad, double *terms);
 
 // Adam hyper-parameters as passed to the kernels (bias corrections folded in)
 struct AdamHost {

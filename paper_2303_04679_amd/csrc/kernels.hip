@@ -14,6 +14,7 @@
 // across the waves of a block, and one block per instance for the final sum.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "internal.h"
@@ -163,18 +164,33 @@ __global__ __launch_bounds__(kBlock) void prolong_kernel(Levels G, int l, const 
   dst[e] = th + prolong_value(G, l, inst, f, i, csrc);
 }
 
-// all levels l_hi-1 .. l_lo by one block (the small coarse levels); the
-// coarsest source is theta itself; w has the pack layout
+// The small coarse levels of one instance per block, in LDS: w_{L-1} =
+// theta_{L-1}, then w_l = theta_l + T w_{l+1} for l = L-2 .. l_stop; every
+// w_l it produces is also written to w (pack layout).  Level l sits in LDS
+// buffer (l - l_stop) % 2, sized for levels l_stop and l_stop + 1.
 template <typename T>
-__global__ __launch_bounds__(1024) void horner_tail_kernel(Levels G, int l_lo,
+__global__ __launch_bounds__(1024) void horner_tail_kernel(Levels G, int l_stop,
                                                            const T *__restrict__ theta, T *w) {
-  for (int l = G.L - 2; l >= l_lo; --l) {
-    const T *src = (l == G.L - 2) ? theta + G.off[l + 1] : w + G.off[l + 1];
-    const int total = G.stride[l] * G.batch;
-    for (int e = threadIdx.x; e < total; e += blockDim.x) {
-      int inst, f, i[3];
-      locate(G, l, e, inst, f, i);
-      w[G.off[l] + e] = theta[G.off[l] + e] + prolong_value(G, l, inst, f, i, src);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *buf[2] = {reinterpret_cast<T *>(smem_raw), reinterpret_cast<T *>(smem_raw) + G.stride[l_stop]};
+  const int inst = blockIdx.x;
+  {
+    const int l = G.L - 1;
+    T *dst = buf[(l - l_stop) & 1];
+    const T *src = theta + G.off[l] + inst * G.stride[l];
+    for (int e = threadIdx.x; e < G.stride[l]; e += blockDim.x) dst[e] = src[e];
+  }
+  __syncthreads();
+  for (int l = G.L - 2; l >= l_stop; --l) {
+    T *dst = buf[(l - l_stop) & 1];
+    const T *cs = buf[(l + 1 - l_stop) & 1];
+    const int base = G.off[l] + inst * G.stride[l];
+    for (int e = threadIdx.x; e < G.stride[l]; e += blockDim.x) {
+      int in0, f, i[3];
+      locate(G, l, e, in0, f, i);
+      const T val = theta[base + e] + prolong_value(G, l, 0, f, i, cs);
+      dst[e] = val;
+      w[base + e] = val;
     }
     __syncthreads();
   }
@@ -201,19 +217,35 @@ __global__ __launch_bounds__(kBlock) void restrict_kernel(Levels G, int l, T *g,
   if (ADAM) adam_elem_loaded(A, k, val, th, m, v);
 }
 
+// g_{l+1} = T^T g_l for l = l_lo .. L-2 of one instance per block, in LDS,
+// with Adam on every level produced; level l_lo is read from g, every level
+// produced is written back to g.  Two LDS buffers sized for levels l_lo and
+// l_lo + 1 alternate.
 template <typename T, bool ADAM>
 __global__ __launch_bounds__(1024) void restrict_tail_kernel(Levels G, int l_lo, T *g, AdamArgs<T> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *cur = reinterpret_cast<T *>(smem_raw);
+  T *nxt = cur + G.stride[l_lo];
+  const int inst = blockIdx.x;
+  {
+    const T *src = g + G.off[l_lo] + inst * G.stride[l_lo];
+    for (int e = threadIdx.x; e < G.stride[l_lo]; e += blockDim.x) cur[e] = src[e];
+  }
+  __syncthreads();
   for (int l = l_lo; l + 1 < G.L; ++l) {
-    const int total = G.stride[l + 1] * G.batch;
-    for (int e = threadIdx.x; e < total; e += blockDim.x) {
-      int inst, f, I[3];
-      locate(G, l + 1, e, inst, f, I);
-      const T val = restrict_value(G, l, inst, f, I, g + G.off[l]);
-      const int k = G.off[l + 1] + e;
-      g[k] = val;
-      if (ADAM) adam_elem(A, k, val);
+    const int base = G.off[l + 1] + inst * G.stride[l + 1];
+    for (int e = threadIdx.x; e < G.stride[l + 1]; e += blockDim.x) {
+      int in0, f, I[3];
+      locate(G, l + 1, e, in0, f, I);
+      const T val = restrict_value(G, l, 0, f, I, cur);
+      nxt[e] = val;
+      g[base + e] = val;
+      if (ADAM) adam_elem(A, base + e, val);
     }
     __syncthreads();
+    T *t = cur;
+    cur = nxt;
+    nxt = t;
   }
 }
 
@@ -456,8 +488,6 @@ __global__ void metric_kernel(const double *terms, double *r, int batch, double 
 // -------------------------------------------------------------- launchers
 static inline unsigned nblk(long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-constexpr long kTailMax = 0;  // coarse levels up to this many values go to one block (off)
-
 Levels levels_of(const modil_ctx *c) {
   Levels G{};
   G.L = c->prob.n_levels;
@@ -474,15 +504,26 @@ Levels levels_of(const modil_ctx *c) {
   return G;
 }
 
-// smallest level index l >= 1 such that levels l..L-1 hold at most kTailMax values
-static int tail_level(const Levels &G) {
-  long acc = 0;
-  int l = G.L;
-  while (l - 1 >= 1 && acc + (long)G.stride[l - 1] * G.batch <= kTailMax) {
-    --l;
-    acc += (long)G.stride[l] * G.batch;
+// Smallest level l >= lo such that levels l and l+1 of one instance fit the
+// LDS budget together and the levels below l, which one block (one compute
+// unit) then produces alone, hold few enough values to take less time than a
+// launch per level; L - 1 if there is none.  With many instances every
+// compute unit has a block, so each block may do more.
+static int tail_level(const Levels &G, int lo, size_t elem, size_t budget) {
+  const long cap = G.batch >= 128 ? 16384 : 2048;  // values one block produces
+  for (int l = lo; l + 1 < G.L; ++l) {
+    long work = 0;
+    for (int j = l + 1; j < G.L; ++j) work += G.stride[j];
+    if ((size_t)(G.stride[l] + G.stride[l + 1]) * elem <= budget && work <= cap) return l;
   }
-  return l;  // levels [l, L) are small; l == L means none
+  return G.L - 1;
+}
+
+template <typename K>
+static bool lds_ready(K kernel, size_t bytes) {
+  if (bytes <= 64 * 1024) return true;
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess;
 }
 
 template <typename T>
@@ -492,12 +533,16 @@ static hipError_t horner_t(modil_ctx *c, const void *theta_v, void *fine_dst_v, 
   T *w = (T *)c->w_buf;
   T *fine_dst = fine_dst_v ? (T *)fine_dst_v : w;
   if (G.L == 1) return hipSuccess;
-  const int lt = tail_level(G);  // w_l for l in [lt - 1 ... ] computed by one block down to lt
   int l = G.L - 2;
-  if (lt <= G.L - 2 && lt >= 1) {
-    // one block computes w_{L-2} .. w_{lt}
-    horner_tail_kernel<T><<<1, 1024, 0, c->stream>>>(G, lt, theta, w);
-    l = lt - 1;
+  // the tail produces w_{L-2} .. w_lt, the levels below the first one that is
+  // too large for it, and stops at level 1 (level 0 goes to fine_dst)
+  const int lt = c->tail_enabled ? std::max(1, tail_level(G, 0, sizeof(T), c->lds_budget) + 1) : G.L;
+  if (lt <= G.L - 3) {  // at least two levels in one launch
+    const size_t bytes = (size_t)(G.stride[lt] + G.stride[lt + 1]) * sizeof(T);
+    if (lds_ready(horner_tail_kernel<T>, bytes)) {
+      horner_tail_kernel<T><<<G.batch, 1024, bytes, c->stream>>>(G, lt, theta, w);
+      l = lt - 1;
+    }
   }
   const int l_end = skip_fine ? 1 : 0;
   for (; l >= l_end; --l) {
@@ -524,9 +569,13 @@ static hipError_t restrict_t(modil_ctx *c, void *g_v, int from, const void *th_i
     A.th_in = (const T *)th_in; A.th_out = (T *)th_out; A.m = (T *)m; A.v = (T *)v;
     A.b1 = T(ad->b1); A.b2 = T(ad->b2); A.step = T(ad->step); A.isb2 = T(ad->isb2); A.eps = T(ad->eps);
   }
-  const int lt = tail_level(G);  // levels [lt, L) are produced by one block
-  int l = from;
-  for (; l + 1 < G.L && l + 1 < lt; ++l) {
+  // levels lt+1 .. L-1 come from one launch of the LDS tail kernel
+  int lt = c->tail_enabled ? tail_level(G, from, sizeof(T), c->lds_budget) : G.L - 1;
+  const size_t bytes = lt + 1 < G.L ? (size_t)(G.stride[lt] + G.stride[lt + 1]) * sizeof(T) : 0;
+  if (lt + 1 < G.L && !(ad ? lds_ready(restrict_tail_kernel<T, true>, bytes)
+                          : lds_ready(restrict_tail_kernel<T, false>, bytes)))
+    lt = G.L - 1;
+  for (int l = from; l + 1 < G.L && l < lt; ++l) {
     if (c->march_enabled &&
         launch_restrict_march<T>(G, l, g, A, ad != nullptr, c->march_tile, c->stream))
       continue;
@@ -536,11 +585,11 @@ static hipError_t restrict_t(modil_ctx *c, void *g_v, int from, const void *th_i
     else
       restrict_kernel<T, false><<<nblk(total), kBlock, 0, c->stream>>>(G, l, g, A);
   }
-  if (l + 1 < G.L) {
+  if (lt + 1 < G.L) {
     if (ad)
-      restrict_tail_kernel<T, true><<<1, 1024, 0, c->stream>>>(G, l, g, A);
+      restrict_tail_kernel<T, true><<<G.batch, 1024, bytes, c->stream>>>(G, lt, g, A);
     else
-      restrict_tail_kernel<T, false><<<1, 1024, 0, c->stream>>>(G, l, g, A);
+      restrict_tail_kernel<T, false><<<G.batch, 1024, bytes, c->stream>>>(G, lt, g, A);
   }
   return hipGetLastError();
 }

@@ -255,6 +255,10 @@ class Context:
         with the per-cell gather kernel."""
         L.check(L.lib().modil_set_option(self.h, L.OPT_MARCH, 1 if enabled else 0), self.h)
 
+    def set_tail(self, enabled: bool):
+        """Do the small coarse levels of each instance in one LDS launch (default)."""
+        L.check(L.lib().modil_set_option(self.h, L.OPT_TAIL, 1 if enabled else 0), self.h)
+
     def set_march_tile(self, rows: int = 0, planes: int = 0):
         """Coarse rows and planes per wave of the marching kernel (0, 0: automatic)."""
         L.check(L.lib().modil_set_option(self.h, L.OPT_MARCH_TILE, 16 * rows + planes), self.h)
@@ -275,6 +279,50 @@ class Context:
     def close(self):
         if getattr(self, "h", None):
             L.lib().modil_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class LBFGS:
+    """Limited-memory BFGS on a context's loss (modil_lbfgs_* in include/modil.h).
+
+    Holds the device workspace (history + 1 pair slots and four pack-sized
+    vectors) and the library handle.  step(theta) does one iteration in place
+    and returns the iteration's info as a dict.
+    """
+
+    def __init__(self, ctx: Context, history: int = 50, max_evals: int = 20, c1: float = 1e-4,
+                 c2: float = 0.9):
+        self.ctx = ctx
+        nb = ctypes.c_size_t()
+        L.check(L.lib().modil_lbfgs_workspace(ctx.h, history, ctypes.byref(nb)), ctx.h)
+        n = int(nb.value)
+        self._ws_raw = torch.empty(n + 256, dtype=torch.uint8, device=ctx.device)
+        shift = (-self._ws_raw.data_ptr()) % 256
+        self._ws = self._ws_raw[shift:shift + n]
+        prm = L.LbfgsParams(history, max_evals, c1, c2)
+        h = ctypes.c_void_p()
+        L.check(L.lib().modil_lbfgs_create(ctx.h, ctypes.byref(prm), _ptr(self._ws), n, ctypes.byref(h)),
+                ctx.h)
+        self.h = h
+
+    def step(self, theta):
+        self.ctx._check_pack(theta, "theta")
+        info = L.LbfgsInfo()
+        L.check(L.lib().modil_lbfgs_step(self.h, _ptr(theta), ctypes.byref(info)), self.ctx.h)
+        return {k: getattr(info, k) for k, _ in L.LbfgsInfo._fields_}
+
+    def reset(self):
+        L.check(L.lib().modil_lbfgs_reset(self.h), self.ctx.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            L.lib().modil_lbfgs_destroy(self.h)
             self.h = None
 
     def __del__(self):

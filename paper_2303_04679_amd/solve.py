@@ -5,7 +5,10 @@ Runs a batch of independent instances at once (one parameter pack); every
 cell-integrated PDE residual, in FP64) is evaluated on the device and copied
 to the host, the first iteration at which an instance reaches r <= r_target
 is recorded, and the loop ends when all instances have converged or the
-iteration cap is reached.  The learning rate may follow a schedule.
+iteration cap is reached.  An optional monitor (for instance the error
+against a reference solution) is evaluated at the same checks with its own
+target; then an instance has converged once both targets are met.  The
+learning rate may follow a schedule.
 """
 import dataclasses
 import math
@@ -26,6 +29,8 @@ class SolveResult:
     seconds: float              # wall time of the loop (device synchronised)
     theta: torch.Tensor         # final parameter pack
     iters_run: int
+    iterations_monitor: Optional[np.ndarray] = None  # first check with monitor <= target
+    monitor_history: Optional[list] = None           # (iteration, monitor[batch]) every check
 
 
 def cosine_lr(lr0, lr_min, total):
@@ -39,7 +44,9 @@ def cosine_lr(lr0, lr_min, total):
 
 def solve(ctx: Context, theta: torch.Tensor, lr: float | Callable[[int], float], max_iters: int,
           r_target: float = 1e-6, check_every: int = 50, betas=(0.9, 0.999), eps=1e-8,
-          log: Optional[Callable[[int, np.ndarray], None]] = None) -> SolveResult:
+          log: Optional[Callable[[int, np.ndarray], None]] = None,
+          monitor: Optional[Callable[[torch.Tensor], np.ndarray]] = None,
+          monitor_target: float = 0.0) -> SolveResult:
     B = ctx.spec.batch
     a = theta.clone()
     b = ctx.new_pack()
@@ -47,7 +54,8 @@ def solve(ctx: Context, theta: torch.Tensor, lr: float | Callable[[int], float],
     r_dev = torch.empty((B,), dtype=torch.float64, device=ctx.device)
     r_host = torch.empty((B,), dtype=torch.float64, pin_memory=True)
     iters = np.full(B, -1, dtype=np.int64)
-    hist = []
+    iters_m = np.full(B, -1 if monitor else 0, dtype=np.int64)
+    hist, mhist = [], []
     lr_f = lr if callable(lr) else (lambda t: lr)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -61,13 +69,19 @@ def solve(ctx: Context, theta: torch.Tensor, lr: float | Callable[[int], float],
             hist.append((it, r))
             newly = (iters < 0) & (r <= r_target)
             iters[newly] = it
+            if monitor:
+                e = np.asarray(monitor(a), dtype=np.float64)
+                mhist.append((it, e))
+                iters_m[(iters_m < 0) & (e <= monitor_target)] = it
             if log:
                 log(it, r)
-            if np.all(iters >= 0) or it >= max_iters or not np.all(np.isfinite(r)):
+            done = np.all(iters >= 0) and np.all(iters_m >= 0)
+            if done or it >= max_iters or not np.all(np.isfinite(r)):
                 break
         ctx.step(a, b, m, v, it + 1, lr=lr_f(it), beta1=betas[0], beta2=betas[1], eps=eps)
         a, b = b, a
         it += 1
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
-    return SolveResult(iters, hist[-1][1], hist, secs, a, it)
+    return SolveResult(iters, hist[-1][1], hist, secs, a, it,
+                       iters_m if monitor else None, mhist if monitor else None)

@@ -1,0 +1,153 @@
+"""L-BFGS through the C ABI (compact representation on the device, strong-Wolfe
+line search on the host) against the oracle's L-BFGS (two-loop recursion,
+the same line-search rules) driven by the FP64 oracle loss and gradient:
+iterates, losses and evaluation counts per iteration; the memory ring when it
+wraps; convergence to the manufactured Poisson solution; determinism."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import lbfgs as ol
+from oracle import operators as ops
+from oracle import reference as ref
+from paper_2303_04679_amd.modil import LBFGS
+from tests.gpu_helpers import context_of, need_gpu, pack_of, rel
+from tests.oracle_cases import case, random_levels
+
+pytestmark = pytest.mark.gpu
+
+
+def _shapes(spec):
+    return ops.level_shapes(spec.op, spec.dims, spec.n_levels)
+
+
+def _unflat(x, shapes):
+    out, o = [], 0
+    for row in shapes:
+        r = []
+        for s in row:
+            n = int(np.prod(s))
+            r.append(x[o:o + n].reshape(s))
+            o += n
+        out.append(r)
+    return out
+
+
+def _flat(levels):
+    return np.concatenate([np.asarray(a, dtype=np.float64).ravel() for row in levels for a in row])
+
+
+def _oracle_fg(spec):
+    shapes = _shapes(spec)
+
+    def fg(x):
+        terms, grads = ops.loss_and_grad(spec, _unflat(x, shapes))
+        return float(sum(terms.values())), _flat(grads)
+    return fg
+
+
+PARITY = [("poisson", (32, 48), 4), ("burgers", (24, 40), 3), ("heat", (40, 72), 3),
+          ("ns3d", (8, 16, 8), 3), ("cavity", (32, 48), 4)]
+
+
+@pytest.mark.parametrize("op,dims,L", PARITY)
+def test_iterates_match_oracle(op, dims, L):
+    need_gpu()
+    spec = case(op, dims, L, seed=41)
+    lv = random_levels(spec, 42, lo=0.05, hi=0.6) if op == "burgers" else random_levels(spec, 42)
+    ctx = context_of(spec, "f64")
+    theta = pack_of(ctx, [lv])
+    lb = LBFGS(ctx, history=5)
+    it = ol.LBFGS(_oracle_fg(spec), _flat(lv), m=5)
+    for k in range(6):
+        info = lb.step(theta)
+        evals_before = it.evals
+        ls = it.step()
+        torch.cuda.synchronize()
+        x = theta.cpu().numpy()
+        assert info["status"] == ls.status, (op, k)
+        assert rel(x, it.x) <= 1e-10, (op, k, rel(x, it.x))
+        assert abs(info["loss"] - it.f) <= 1e-11 * abs(it.f), (op, k, info["loss"], it.f)
+        oracle_evals = it.evals - evals_before + (1 if k == 0 else 0)
+        # with status 1 the library evaluates the accepted point again unless it
+        # was the last one tried (the oracle keeps every gradient it computed)
+        extra = (0, 1) if ls.status == 1 else (0,)
+        assert info["evals"] - oracle_evals in extra, (op, k, info["evals"], oracle_evals)
+        assert info["pairs"] == len(it.S)
+    lb.close()
+
+
+def test_memory_ring_wraps():
+    """history 3 over 9 iterations: pairs are dropped oldest first."""
+    need_gpu()
+    spec = case("poisson", (16, 24), 3, seed=43)
+    lv = random_levels(spec, 44)
+    ctx = context_of(spec, "f64")
+    theta = pack_of(ctx, [lv])
+    lb = LBFGS(ctx, history=3)
+    it = ol.LBFGS(_oracle_fg(spec), _flat(lv), m=3)
+    for k in range(9):
+        info = lb.step(theta)
+        it.step()
+        torch.cuda.synchronize()
+        assert info["pairs"] == len(it.S) <= 3
+        assert rel(theta.cpu().numpy(), it.x) <= 1e-9, (k, rel(theta.cpu().numpy(), it.x))
+
+
+def test_reaches_manufactured_poisson_solution():
+    need_gpu()
+    n = 32
+    spec = case("poisson", (n, n), 4, seed=45)
+    u_ref = ref.poisson_reference((n, n))
+    spec.forcing = {0: ref.poisson_forcing(spec, u_ref)}
+    ctx = context_of(spec, "f64")
+    theta = ctx.new_pack()
+    lb = LBFGS(ctx, history=50)
+    for k in range(600):
+        info = lb.step(theta)
+        if info["loss"] < 1e-24 or info["status"] == 2:
+            break
+    fine = ctx.prolong(theta)
+    torch.cuda.synchronize()
+    err = np.max(np.abs(ctx.fine_views(fine)[0].cpu().numpy() - u_ref))
+    assert err < 1e-8, (k, info, err)
+
+
+def test_f32_channel_flow_descends():
+    need_gpu()
+    spec = case("ns3d", (32, 32, 32), 4, seed=46)
+    ctx = context_of(spec, "f32")
+    theta = pack_of(ctx, [random_levels(spec, 47, lo=-0.1, hi=0.1)])
+    lb = LBFGS(ctx, history=10)
+    losses = []
+    for k in range(10):
+        info = lb.step(theta)
+        assert info["status"] in (0, 1)
+        losses.append(info["loss"])
+    assert all(b < a for a, b in zip(losses, losses[1:]))
+    assert np.isfinite(theta.cpu().numpy()).all()
+
+
+def test_deterministic():
+    need_gpu()
+    spec = case("cavity", (32, 32), 3, seed=48)
+    lv = random_levels(spec, 49)
+    outs = []
+    for _ in range(2):
+        ctx = context_of(spec, "f32")
+        theta = pack_of(ctx, [lv])
+        lb = LBFGS(ctx, history=4)
+        for k in range(5):
+            lb.step(theta)
+        torch.cuda.synchronize()
+        outs.append(theta.cpu().clone())
+    assert torch.equal(outs[0], outs[1])
+
+
+def test_invalid_parameters_are_rejected():
+    need_gpu()
+    spec = case("poisson", (16, 16), 2, seed=50)
+    ctx = context_of(spec, "f64")
+    for kw in ({"history": 0}, {"history": 65}, {"max_evals": 1}, {"c1": 0.9, "c2": 0.5}):
+        with pytest.raises(Exception):
+            LBFGS(ctx, **kw)

@@ -136,3 +136,29 @@ def test_restrict_f32_matches_oracle():
     torch.cuda.synchronize()
     _, rgrad = ops.loss_and_grad(spec, lv)
     assert_levels(levels_of(ctx, g), rgrad, 1e-5, "f32", spec=spec)
+
+
+@pytest.mark.parametrize("op,dims,L,batch", [("poisson", (200,), 4, 1), ("heat", (64, 32), 4, 2),
+                                             ("cavity", (64, 64), 4, 3), ("ns3d", (32, 32, 32), 4, 1),
+                                             ("burgers", (64, 64), 5, 1)])
+def test_lds_tail_equals_per_level_launches(op, dims, L, batch):
+    """The one-launch LDS tail (small levels of each instance in one block)
+    gives the per-level kernels' prolongation, gradient and Adam state."""
+    need_gpu()
+    spec = case(op, dims, L, seed=34)
+    lvs = [random_levels(spec, 35 + b, lo=0.05, hi=0.6) for b in range(batch)]
+    outs = []
+    for tail in (True, False):
+        ctx = context_of(spec, "f64", batch=batch)
+        ctx.set_tail(tail)
+        a = pack_of(ctx, lvs)
+        fine = ctx.prolong(a)
+        b, m, v = ctx.new_pack(), ctx.new_pack(), ctx.new_pack()
+        for t in range(1, 3):
+            ctx.step(a, b, m, v, t, lr=1e-2)
+            a, b = b, a
+        _, g = ctx.loss_grad(a)
+        torch.cuda.synchronize()
+        outs.append([x.cpu().numpy() for x in (fine, a, m, v, g)])
+    for x, y in zip(*outs):
+        assert rel(x, y) <= 1e-13
