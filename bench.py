@@ -5,13 +5,16 @@ A step is one full iteration of the method on one batch of synthetic input:
 multigrid prolongation of every level, residuals / data terms and the FP64
 loss, the exact adjoint, restriction to every level and Adam on every level.
 
-    python bench.py [--steps K] [--warmup W] [--workload ns3d128]
+    python bench.py [--steps K] [--warmup W] [--workload ns3d128] [--optimizer adam|lbfgs]
 
 Prints one JSON line: fine-grid cell-iterations per second (fine cells x
 steps / seconds, inputs resident in HBM), the per-kernel-class durations from
 HIP events recorded on the library's stream during the timed steps, the
 roofline of the dominant kernel (algorithmic bytes / its average launch
 duration against 8 TB/s), and the CPU oracle timed on a bounded sample.
+With --optimizer lbfgs a step is one L-BFGS iteration instead (direction from
+the stored pairs, line search with one or more loss-and-gradient
+evaluations, new pair); the CPU baseline is not run in that mode.
 """
 import argparse
 import json
@@ -21,7 +24,7 @@ import sys
 import time
 
 HBM_PEAK_GBS = 8000.0
-CLASSES = ("fine", "horner", "restrict", "adam", "reduce")
+CLASSES = ("fine", "horner", "restrict", "adam", "reduce", "lbfgs_dots", "lbfgs_update")
 
 
 def parse():
@@ -34,10 +37,12 @@ def parse():
                     help="budget of the oracle CPU-baseline sample (0 disables it)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (for counter scaling)")
+    ap.add_argument("--optimizer", choices=("adam", "lbfgs"), default="adam")
+    ap.add_argument("--history", type=int, default=50, help="L-BFGS pairs")
     return ap.parse_args()
 
 
-def alg_bytes(ctx, spec, fused):
+def alg_bytes(ctx, spec, fused, adam=True):
     """Algorithmic bytes of one launch of each kernel class and of one iteration.
 
     Every array a kernel must read or write is counted once; halo re-reads
@@ -56,7 +61,12 @@ def alg_bytes(ctx, spec, fused):
     size = [int(lay.level_stride[l]) * spec.batch for l in range(L)]
     S = int(lay.total)
     chi = spec.batch * spec.fine_cells * b if spec.chi_fixed else 0
-    if fused:
+    if fused and not adam:  # loss and gradient only (L-BFGS evaluations)
+        fine = (2 * size[0] + (size[1] if L > 1 else 0)) * b + chi
+        horner = sum((2 * size[l] + size[l + 1]) * b for l in range(1, L - 1))
+        restrict = sum((size[l] + size[l + 1]) * b for l in range(L - 1))
+        adam = 0
+    elif fused:
         fine = (7 * size[0] + (size[1] if L > 1 else 0)) * b + chi
         horner = sum((2 * size[l] + size[l + 1]) * b for l in range(1, L - 1))
         restrict = sum((size[l] + 7 * size[l + 1]) * b for l in range(L - 1))
@@ -65,9 +75,28 @@ def alg_bytes(ctx, spec, fused):
         fine = 2 * size[0] * b + chi
         horner = sum((2 * size[l] + size[l + 1]) * b for l in range(L - 1))
         restrict = sum((size[l] + size[l + 1]) * b for l in range(L - 1))
-        adam = 7 * S * b
+        adam = 7 * S * b if adam else 0
     return {"fine": fine, "horner": horner, "restrict": restrict, "adam": adam,
-            "reduce": 0, "iteration": 6 * S * b}
+            "reduce": 0, "lbfgs_dots": 0, "lbfgs_update": 0, "iteration": 6 * S * b}
+
+
+def lbfgs_vector_bytes(n, b, infos, pairs0):
+    """Algorithmic bytes of the L-BFGS vector kernels over the timed iterations.
+
+    Per iteration with k stored pairs: the direction reads 2k + 1 vectors and
+    writes d; every line-search evaluation forms the trial point (2 reads,
+    1 write) and the dot product g . d (2 reads); the new pair reads d, g_new,
+    g and writes s, y; the accepted point is copied (1 read, 1 write); the dot
+    products with the new gradient and the new y read 2k + 3 + 2 vectors.
+    """
+    dots = update = 0
+    k = pairs0
+    for info in infos:
+        ev = info["evals"]
+        update += (2 * k + 2 + 3 * ev + 5 + 2) * n * b
+        dots += (2 * ev + 2 * k + 5) * n * b
+        k = info["pairs"]
+    return dots, update
 
 
 def measured_traffic(workload, kernel_class):
@@ -144,6 +173,8 @@ def main():
     print(f"[bench] workload {wl.name} dims {tuple(spec.dims)} L={spec.n_levels} {spec.dtype}",
           file=sys.stderr, flush=True)
     ctx, theta = configs.build(wl)
+    if args.optimizer == "lbfgs":
+        return main_lbfgs(args, wl, ctx, theta)
     a, b = theta, ctx.new_pack()
     m, v = ctx.new_pack(), ctx.new_pack()
     terms = torch.empty((spec.batch, 5), dtype=torch.float64, device=ctx.device)
@@ -229,6 +260,74 @@ def main():
         "ms_per_step_profiled": ms_prof / args.steps,
         "cpu_baseline": cpu,
     }
+    print(json.dumps(out), flush=True)
+
+
+def main_lbfgs(args, wl, ctx, theta):
+    """One step = one L-BFGS iteration (see lbfgs_vector_bytes for its vector work)."""
+    import torch
+
+    from paper_2303_04679_amd.modil import LBFGS
+    spec = wl.spec
+    lb = LBFGS(ctx, history=args.history)
+    th = theta.clone()
+    for _ in range(args.warmup):
+        lb.step(th)
+    torch.cuda.synchronize()
+    pairs0 = lb.step(th)["pairs"]
+    ctx.profile(True)
+    for k in range(len(CLASSES)):
+        ctx.profile_read(k)
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        infos.append(lb.step(th))
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    kern = {}
+    for k, name in enumerate(CLASSES):
+        tot, cnt = ctx.profile_read(k)
+        kern[name] = {"total_ms": tot, "launches": cnt, "avg_ms": tot / max(cnt, 1)}
+    ctx.profile(False)
+    ctx.check()
+    b = 4 if spec.dtype == "f32" else 8
+    fused = spec.op == "ns3d" and all(f < 4 for _, f, _, _, _, _ in wl.meas)
+    ab = alg_bytes(ctx, spec, fused, adam=False)
+    evals = sum(i["evals"] for i in infos)
+    dots, upd = lbfgs_vector_bytes(int(ctx.lay.total), b, infos, pairs0)
+    total_bytes = {n: ab[n] * kern[n]["launches"] for n in ("fine", "horner", "restrict", "reduce")}
+    total_bytes.update({"adam": 0, "lbfgs_dots": dots, "lbfgs_update": upd})
+    dom = max(CLASSES, key=lambda n: kern[n]["total_ms"])
+    launches = max(kern[dom]["launches"], 1)
+    achieved = total_bytes[dom] / (kern[dom]["total_ms"] * 1e-3) / 1e9 if kern[dom]["total_ms"] else 0.0
+    ms_it = secs * 1e3 / args.steps
+    out = {
+        "metric": "fine-grid cell-iters/s",
+        "value": spec.fine_cells * spec.batch * args.steps / secs,
+        "unit": "cell-iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_it,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": spec.dtype,
+        "data": "synthetic",
+        "config": {"workload": wl.name, "grid": "x".join(str(d) for d in spec.dims),
+                   "levels": spec.n_levels, "fields": len(spec.fields), "params": int(ctx.lay.total),
+                   "batch": spec.batch, "optimizer": f"lbfgs(m={args.history})", "loss_reduction": "f64"},
+        "evaluations_per_step": evals / args.steps,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "bytes_per_launch": total_bytes[dom] / launches,
+                     "avg_launch_ms": kern[dom]["avg_ms"], "traffic": None},
+        "kernels": kern,
+        "fused_fine_kernel": fused,
+        "final_loss": infos[-1]["loss"],
+        "cpu_baseline": None,
+    }
+    lb.close()
     print(json.dumps(out), flush=True)
 
 

@@ -260,7 +260,8 @@ int modil_set_option(modil_ctx *ctx, int32_t option, int64_t value);
  * launch class; modil_profile_read returns the accumulated milliseconds and
  * launch count of one class (synchronises), then resets it.
  * Classes: 0 fine-level kernel, 1 Horner (coarse prolongation),
- * 2 restriction, 3 Adam, 4 reductions / data terms.                      */
+ * 2 restriction, 3 Adam, 4 reductions / data terms, 5 L-BFGS dot products,
+ * 6 L-BFGS vector updates (direction, trial point, new pair, accepted point). */
 int modil_check(modil_ctx *ctx);
 int modil_profile(modil_ctx *ctx, int32_t enable);
 int modil_profile_read(modil_ctx *ctx, int32_t kernel_class, double *total_ms, int64_t *count);

@@ -215,31 +215,6 @@ void fill_layout(const modil_problem &p, modil_pack_layout &L) {
   L.workspace_bytes = carve(p, L).end;
 }
 
-// RAII timing of one launch class with HIP events (only when profiling).
-struct Timed {
-  modil_ctx *c;
-  EventPair ev{};
-  bool on;
-  Timed(modil_ctx *ctx, int cls) : c(ctx), on(ctx->profiling), cls_(cls) {
-    if (!on) return;
-    ProfileClass &pc = c->prof[cls_];
-    if (!pc.pool.empty()) {
-      ev = pc.pool.back();
-      pc.pool.pop_back();
-    } else {
-      (void)hipEventCreate(&ev.a);
-      (void)hipEventCreate(&ev.b);
-    }
-    (void)hipEventRecord(ev.a, c->stream);
-  }
-  ~Timed() {
-    if (!on) return;
-    (void)hipEventRecord(ev.b, c->stream);
-    c->prof[cls_].pending.push_back(ev);
-  }
-  int cls_;
-};
-
 int upload_measurements(modil_ctx *c) {
   std::vector<Meas> m = c->meas;
   std::stable_sort(m.begin(), m.end(), [](const Meas &a, const Meas &b) {
@@ -760,7 +735,7 @@ int modil_profile(modil_ctx *c, int32_t enable) {
 
 int modil_profile_read(modil_ctx *c, int32_t cls, double *total_ms, int64_t *count) {
   if (!c) return fail_global(MODIL_ERR_INVALID_ARG, "ctx is NULL");
-  if (cls < 0 || cls > 4 || !total_ms || !count) return fail(c, MODIL_ERR_INVALID_ARG, "bad class");
+  if (cls < 0 || cls >= kProfileClasses || !total_ms || !count) return fail(c, MODIL_ERR_INVALID_ARG, "bad class");
   HIP_OR_RETURN(c, hipStreamSynchronize(c->stream), "profile");
   ProfileClass &pc = c->prof[cls];
   for (auto &ev : pc.pending) {

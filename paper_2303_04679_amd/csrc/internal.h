@@ -52,7 +52,23 @@ struct Levels {
   int n[kMaxL][kMaxF][3];  // cells per axis (z, y, x) of every field
 };
 
-// Adam on pack elements: theta_out[e] = theta_in[e] - step * m / (sqrt(v) * isb2 + eps)
+// The Adam parameter update theta - step * m / (sqrt(v) * isb2 + eps), with
+// step = lr / (1 - b1^t) and isb2 = 1 / sqrt(1 - b2^t) folded on the host.  In
+// FP32 the square root and the reciprocal are the hardware approximations
+// (about 1 ulp each) instead of correctly rounded sequences; FP64 is exact.
+// Every kernel that applies Adam uses this one function, so all of them give
+// the same bits.
+template <typename T>
+__device__ inline T adam_theta(T th, T m, T v, T step, T isb2, T eps) {
+  return th - step * m / (sqrt(v) * isb2 + eps);
+}
+template <>
+__device__ inline float adam_theta<float>(float th, float m, float v, float step, float isb2,
+                                          float eps) {
+  return th - step * m * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(v) * isb2 + eps);
+}
+
+// Adam on pack elements: theta_out[e] = adam_theta(theta_in[e], m, v, ...)
 template <typename T>
 struct AdamArgs {
   const T *th_in;
@@ -75,6 +91,10 @@ struct ProfileClass {
   double ms = 0.0;
   int64_t count = 0;
 };
+
+// launch classes timed by modil_profile: 0 fine level, 1 Horner, 2 restriction,
+// 3 Adam, 4 reductions / data terms, 5 L-BFGS dot products, 6 L-BFGS vector updates
+constexpr int kProfileClasses = 7;
 
 }  // namespace modil
 
@@ -120,11 +140,37 @@ struct modil_ctx {
   const void *chi = nullptr;
 
   bool profiling = false;
-  modil::ProfileClass prof[5];
+  modil::ProfileClass prof[modil::kProfileClasses];
   std::string err;
 };
 
 namespace modil {
+
+// RAII timing of one launch class with HIP events on the context's stream
+// (only while profiling is enabled).
+struct Timed {
+  modil_ctx *c;
+  EventPair ev{};
+  bool on;
+  int cls_;
+  Timed(modil_ctx *ctx, int cls) : c(ctx), on(ctx->profiling), cls_(cls) {
+    if (!on) return;
+    ProfileClass &pc = c->prof[cls_];
+    if (!pc.pool.empty()) {
+      ev = pc.pool.back();
+      pc.pool.pop_back();
+    } else {
+      (void)hipEventCreate(&ev.a);
+      (void)hipEventCreate(&ev.b);
+    }
+    (void)hipEventRecord(ev.a, c->stream);
+  }
+  ~Timed() {
+    if (!on) return;
+    (void)hipEventRecord(ev.b, c->stream);
+    c->prof[cls_].pending.push_back(ev);
+  }
+};
 
 // layout helpers (api.cpp)
 int op_fields(const modil_problem &p);

@@ -137,7 +137,7 @@ __device__ inline void adam_elem(const AdamArgs<T> &A, int e, T g) {
   const T vv = A.b2 * A.v[e] + (T(1) - A.b2) * g * g;
   A.m[e] = mm;
   A.v[e] = vv;
-  A.th_out[e] = A.th_in[e] - A.step * mm / (sqrt(vv) * A.isb2 + A.eps);
+  A.th_out[e] = adam_theta(A.th_in[e], mm, vv, A.step, A.isb2, A.eps);
 }
 
 // Adam with the old state already loaded (lets the loads overlap the gather)
@@ -147,7 +147,7 @@ __device__ inline void adam_elem_loaded(const AdamArgs<T> &A, int e, T g, T th, 
   const T vv = A.b2 * v + (T(1) - A.b2) * g * g;
   A.m[e] = mm;
   A.v[e] = vv;
-  A.th_out[e] = th - A.step * mm / (sqrt(vv) * A.isb2 + A.eps);
+  A.th_out[e] = adam_theta(th, mm, vv, A.step, A.isb2, A.eps);
 }
 
 // ------------------------------------------------------------- prolongation
@@ -263,7 +263,7 @@ __global__ __launch_bounds__(kBlock) void adam_kernel(const T *__restrict__ th_i
   const T vv = b2 * v[e] + (T(1) - b2) * gg * gg;
   m[e] = mm;
   v[e] = vv;
-  th_out[e] = th_in[e] - step * mm / (sqrt(vv) * inv_sqrt_bc2 + eps);
+  th_out[e] = adam_theta(th_in[e], mm, vv, step, inv_sqrt_bc2, eps);
 }
 
 // ------------------------------------------------------- block-sum of terms

@@ -223,6 +223,7 @@ hipError_t multidot(modil_lbfgs *lb, const std::vector<const void *> &left,
   const int chunks = (A.n_left + kLbChunk - 1) / kLbChunk;
   const int blocks = (int)std::min<long>(kLbBlocks, std::max<long>(1, (lb->n + kLbBlock - 1) / kLbBlock));
   hipStream_t s = lb->c->stream;
+  Timed tm(lb->c, 5);
   multidot_kernel<T><<<dim3(blocks, chunks), kLbBlock, 0, s>>>(A);
   dot_reduce_kernel<<<dim3(A.n_left, A.n_right), 256, 0, s>>>(lb->partials, blocks, A.n_left,
                                                                lb->dots);
@@ -267,6 +268,7 @@ int objective(modil_lbfgs *lb, const void *theta, void *grad, const void *d, dou
 
 template <typename T>
 hipError_t launch_axpy(modil_lbfgs *lb, const void *x, double alpha, void *out) {
+  Timed tm(lb->c, 6);
   axpy_kernel<T><<<nblk_lb(lb->n), kLbBlock, 0, lb->c->stream>>>((const T *)x, (const T *)lb->d,
                                                                   alpha, (T *)out, lb->n);
   return hipGetLastError();
@@ -288,6 +290,7 @@ hipError_t launch_combine(modil_lbfgs *lb, int k) {
   A.d = (T *)lb->d;
   A.coef = lb->coef;
   A.n = lb->n;
+  Timed tm(lb->c, 6);
   combine_kernel<T><<<nblk_lb(lb->n), kLbBlock, 0, lb->c->stream>>>(A);
   return hipGetLastError();
 }
@@ -632,18 +635,21 @@ int modil_lbfgs_step(modil_lbfgs *lb, void *theta, modil_lbfgs_info *info) {
       ++evals;
     }
     const int sl = free_slot(lb);
-    hipStream_t s = lb->c->stream;
-    if (lb->elem == 8)
-      pair_kernel<double><<<nblk_lb(lb->n), kLbBlock, 0, s>>>(
-          (const double *)lb->d, ls.alpha, (const double *)lb->gt, (const double *)lb->g,
-          (double *)vec_at(lb, lb->S, sl), (double *)vec_at(lb, lb->Y, sl), lb->n);
-    else
-      pair_kernel<float><<<nblk_lb(lb->n), kLbBlock, 0, s>>>(
-          (const float *)lb->d, ls.alpha, (const float *)lb->gt, (const float *)lb->g,
-          (float *)vec_at(lb, lb->S, sl), (float *)vec_at(lb, lb->Y, sl), lb->n);
-    LB_HIP(lb, hipGetLastError(), "pair");
-    LB_HIP(lb, hipMemcpyAsync(theta, lb->xt, (size_t)lb->n * lb->elem, hipMemcpyDeviceToDevice, s),
-           "accept");
+    {
+      hipStream_t s = lb->c->stream;
+      Timed tm(lb->c, 6);
+      if (lb->elem == 8)
+        pair_kernel<double><<<nblk_lb(lb->n), kLbBlock, 0, s>>>(
+            (const double *)lb->d, ls.alpha, (const double *)lb->gt, (const double *)lb->g,
+            (double *)vec_at(lb, lb->S, sl), (double *)vec_at(lb, lb->Y, sl), lb->n);
+      else
+        pair_kernel<float><<<nblk_lb(lb->n), kLbBlock, 0, s>>>(
+            (const float *)lb->d, ls.alpha, (const float *)lb->gt, (const float *)lb->g,
+            (float *)vec_at(lb, lb->S, sl), (float *)vec_at(lb, lb->Y, sl), lb->n);
+      LB_HIP(lb, hipGetLastError(), "pair");
+      LB_HIP(lb, hipMemcpyAsync(theta, lb->xt, (size_t)lb->n * lb->elem, hipMemcpyDeviceToDevice, s),
+             "accept");
+    }
     std::swap(lb->g, lb->gt);
     lb->f = ls.f;
     st = refresh(lb, sl);  // stores the pair (dropping the oldest when full) or discards it

@@ -14,7 +14,8 @@
 // halo rows on each side) and two more waves for the four halo columns.  Each
 // thread keeps its column's last four prolonged planes and three planes of
 // residual seeds in registers; the current planes of fields and seeds are
-// staged in LDS for the xy neighbours.  Seeds are formed for the owned cells
+// staged in LDS for the xy neighbours (in FP32 also each cell's derivatives,
+// from its seed pass to its gradient pass).  Seeds are formed for the owned cells
 // plus a 1-cell halo, the gradient for the owned cells.  The coarse plane
 // interpolation is cached per column, so each coarse plane is read once per
 // two fine planes.  Blocks are mapped to tiles so that every XCD works on one
@@ -82,6 +83,12 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
   __shared__ T Al[2][4][NST_Y][NST_X];
   __shared__ T Dl[4][NST_Y][NST_X];
   __shared__ double red[NS_THREADS / 64][kTerms];
+  // In FP32 the derivatives and body terms of a cell (12 values) are kept from
+  // its seed pass for its gradient pass one plane later, instead of being
+  // formed again; in FP64 they do not fit in LDS beside the planes.
+  constexpr bool SAVE_L = sizeof(T) == 4;
+  constexpr int NLS = 12;
+  __shared__ T Ls[SAVE_L ? 2 : 1][SAVE_L ? NLS : 1][SAVE_L ? NS_THREADS : 1];
 
   const OpParams &p = A.p;
   const int tid = threadIdx.x;
@@ -224,6 +231,12 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
       }
       NSLocal<3, T> L;
       ns_local<3>(K, Us, L);
+      if (SAVE_L) {
+        for (int c = 0; c < 3; ++c) {
+          for (int k = 0; k < 3; ++k) Ls[sb][3 * c + k][tid] = L.du[c][k];
+          Ls[sb][9 + c][tid] = L.body[c];
+        }
+      }
       const T uc[3] = {U2[0], U2[1], U2[2]};
       T r[4];
       ns_residual<3, true>(K, L, uc, U2[4], r);
@@ -257,19 +270,26 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
 
     // ---- 4. gradient, and Adam, at plane q
     if (gather) {
-      T Uq[4][7];
-      for (int f = 0; f < 4; ++f) {
-        const T c = U1[f];
-        Uq[f][S_C] = c;
-        Uq[f][S_ZM] = q > 0 ? U0[f] : GV(f, 0, 0, c);
-        Uq[f][S_ZP] = q < nz - 1 ? U2[f] : GV(f, 0, 1, c);
-        Uq[f][S_YM] = y > 0 ? Ul[qb][f][Y - 1][X] : GV(f, 1, 0, c);
-        Uq[f][S_YP] = y < ny - 1 ? Ul[qb][f][Y + 1][X] : GV(f, 1, 1, c);
-        Uq[f][S_XM] = x > 0 ? Ul[qb][f][Y][X - 1] : GV(f, 2, 0, c);
-        Uq[f][S_XP] = x < nx - 1 ? Ul[qb][f][Y][X + 1] : GV(f, 2, 1, c);
-      }
       NSLocal<3, T> L;
-      ns_local<3>(K, Uq, L);
+      if (SAVE_L) {
+        for (int c = 0; c < 3; ++c) {
+          for (int k = 0; k < 3; ++k) L.du[c][k] = Ls[qb][3 * c + k][tid];
+          L.body[c] = Ls[qb][9 + c][tid];
+        }
+      } else {
+        T Uq[4][7];
+        for (int f = 0; f < 4; ++f) {
+          const T c = U1[f];
+          Uq[f][S_C] = c;
+          Uq[f][S_ZM] = q > 0 ? U0[f] : GV(f, 0, 0, c);
+          Uq[f][S_ZP] = q < nz - 1 ? U2[f] : GV(f, 0, 1, c);
+          Uq[f][S_YM] = y > 0 ? Ul[qb][f][Y - 1][X] : GV(f, 1, 0, c);
+          Uq[f][S_YP] = y < ny - 1 ? Ul[qb][f][Y + 1][X] : GV(f, 1, 1, c);
+          Uq[f][S_XM] = x > 0 ? Ul[qb][f][Y][X - 1] : GV(f, 2, 0, c);
+          Uq[f][S_XP] = x < nx - 1 ? Ul[qb][f][Y][X + 1] : GV(f, 2, 1, c);
+        }
+        ns_local<3>(K, Uq, L);
+      }
       const T uc[3] = {U1[0], U1[1], U1[2]};
       const T chic = U1[4];
       T g[5], cs[4], dchi, fs[4];
@@ -321,7 +341,7 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
           const T vv = A.adam.b2 * vq[f] + (T(1) - A.adam.b2) * g[f] * g[f];
           A.adam.m[k] = mm;
           A.adam.v[k] = vv;
-          A.adam.th_out[k] = tq[f] - A.adam.step * mm / (sqrt(vv) * A.adam.isb2 + A.adam.eps);
+          A.adam.th_out[k] = adam_theta(tq[f], mm, vv, A.adam.step, A.adam.isb2, A.adam.eps);
         }
       }
     }

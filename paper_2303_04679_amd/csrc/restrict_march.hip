@@ -152,7 +152,7 @@ __device__ inline void emit_rows(T *__restrict__ g, const AdamArgs<T> &A, long e
       const T vv = A.b2 * v[j] + (T(1) - A.b2) * val[j] * val[j];
       A.m[e] = mm;
       A.v[e] = vv;
-      A.th_out[e] = th[j] - A.step * mm / (sqrt(vv) * A.isb2 + A.eps);
+      A.th_out[e] = adam_theta(th[j], mm, vv, A.step, A.isb2, A.eps);
     }
   }
 }

@@ -45,7 +45,7 @@ def cold_solve(res, iters, lr0, progress=True):
     return ctx, out
 
 
-def dataset(seeds, iters, lr0, batch, keep=32):
+def dataset(seeds, iters, lr0, batch, keep=64):
     """Solves of the instances; returns (re, idx, u_obs, v_obs, targets,
     r_final, fine fields of the first `keep` instances)."""
     ys = [[], [], []]
@@ -151,17 +151,24 @@ def main():
     # held-out instances: reference solutions give their observations
     log("solving the held-out instances (cold start)")
     tres, tidx = W.instances(test_seeds)
-    ctx_ref, ref = cold_solve(tres, args.iters, lr_cold, progress=False)
+    # references from solves twice as long as any evaluated schedule, so that
+    # no evaluated run reproduces its reference; error statistics use only the
+    # instances whose reference converged (r <= 1e-8)
+    ctx_ref, ref = cold_solve(tres, 2 * args.iters, lr_cold, progress=False)
+    r_ref = ref.r_final.copy()
+    conv = r_ref <= 1e-8
     fine = W.fine_fields(ctx_ref, ref.theta)
     tu, tv = W.observe(fine, tidx)
     ty = W.canonical_targets(fine.double())
     ctx_ref.close()
     # schedule choice on training instances (first 32), frozen afterwards
     log("choosing step schedules on training instances")
-    sub = slice(0, 32)
+    sub = np.flatnonzero(data[5][:len(data[6])] <= 1e-8)[:32]
+    log(f"  {len(sub)} converged training instances for the choice")
     sres, sidx = data[0][sub], data[1][sub]
-    su, sv = data[2][sub].contiguous(), data[3][sub].contiguous()
-    sref = data[6][sub]
+    st = torch.as_tensor(sub, device=data[2].device)
+    su, sv = data[2][st].contiguous(), data[3][st].contiguous()
+    sref = data[6][st]
     grid = [(lr0, n) for lr0 in (3e-3, 1e-3, 3e-4, 1e-4, 3e-5, 1e-5)
             for n in (30000, 15000, 7500, 3000, 1500)]
     best = {}
@@ -236,7 +243,7 @@ def main():
     t_inf = (time.perf_counter() - t0) / 50
     # direct single-instance wall-clock solves
     direct = []
-    for k in range(args.direct):
+    for k in (int(i) for i in np.flatnonzero(conv)[:args.direct]):
         row = {"re": float(tres[k])}
         for which in ("cold", "warm"):
             _, _, lr0, n = best[which]
@@ -256,24 +263,28 @@ def main():
         log(f"direct {k}: {row}")
     summ = {}
     for key in ("iters_1e-6", "iters_err_1e-3", "iters_joint"):
-        summ[key] = {}
+        # the error criteria count only instances with a converged reference
+        sel = np.ones(len(tres), bool) if key == "iters_1e-6" else conv
+        summ[key] = {"instances": int(sel.sum())}
         for which in ("cold", "warm"):
-            it = np.array(results[which][key])
+            it = np.array(results[which][key])[sel]
             ok = it >= 0
             q = np.percentile(it[ok], [25, 50, 75]).tolist() if ok.any() else [None] * 3
             extra = t_inf if which == "warm" else 0.0
             summ[key][which] = {"reached": float(ok.mean()), "iters_quartiles": q,
                                 "seconds_median": (q[1] * t_iter + extra) if q[1] is not None else None}
-        both = (np.array(results["cold"][key]) >= 0) & (np.array(results["warm"][key]) >= 0)
+        ic, iw = np.array(results["cold"][key])[sel], np.array(results["warm"][key])[sel]
+        both = (ic >= 0) & (iw >= 0)
         if both.any():
-            ratio = np.array(results["cold"][key])[both] / np.maximum(np.array(results["warm"][key])[both], 1)
+            ratio = ic[both] / np.maximum(iw[both], 1)
             summ[key]["speedup_iters_median_on_common"] = float(np.median(ratio))
             summ[key]["common_fraction"] = float(both.mean())
     summary = {"n_train": args.n_train, "n_test": args.n_test, "train_loss": hist,
                "schedules": {k: {"lr0": v[2], "iters": v[3]} for k, v in best.items()},
                "seconds_per_iteration_single": t_iter, "seconds_inference_single": t_inf,
                "summary": summ, "per_instance": results, "direct": direct,
-               "train_r_final_median": float(np.median(data[5])), "total_seconds": time.time() - t_all}
+               "train_r_final_median": float(np.median(data[5])),
+               "reference_r": r_ref.tolist(), "reference_converged": float(conv.mean()), "total_seconds": time.time() - t_all}
     json.dump(summary, open(args.out, "w"))
     torch.save({"master": net.master.cpu()}, args.out.replace(".json", "_net.pt"))
     log(f"done: {json.dumps(summ)}")
