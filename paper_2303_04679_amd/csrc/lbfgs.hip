@@ -40,29 +40,67 @@ struct MultiDotArgs {
   double *partials;  // [chunk][block][right][kLbChunk]
 };
 
-// Every block covers a fixed contiguous range of elements; products are
-// accumulated in FP64 per thread, then summed over the block in a fixed tree.
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { using type = float4; static constexpr int n = 4; };
+template <> struct Vec4<double> { using type = double2; static constexpr int n = 2; };
+
+template <typename V>
+__device__ inline double lane_of(const V &v, int i);
+template <>
+__device__ inline double lane_of<float4>(const float4 &v, int i) {
+  return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
+}
+template <>
+__device__ inline double lane_of<double2>(const double2 &v, int i) {
+  return i == 0 ? v.x : v.y;
+}
+
+// Every block covers a fixed contiguous range of elements, read as 16-byte
+// vectors (all vectors are 256-byte aligned); products are accumulated in FP64
+// per thread, then summed over the block in a fixed tree.  The elements past
+// the last whole vector are added by block 0.
 template <typename T>
 __global__ __launch_bounds__(kLbBlock) void multidot_kernel(MultiDotArgs<T> A) {
+  using V = typename Vec4<T>::type;
+  constexpr int NV = Vec4<T>::n;
   const int chunk = blockIdx.y;
   const int l0 = chunk * kLbChunk;
   const int nl = min(kLbChunk, A.n_left - l0);
-  const long per = (A.n + gridDim.x - 1) / gridDim.x;
-  const long e0 = (long)blockIdx.x * per, e1 = min(A.n, e0 + per);
+  const long groups = A.n / NV;
+  const long per = (groups + gridDim.x - 1) / gridDim.x;
+  const long q0 = (long)blockIdx.x * per, q1 = min(groups, q0 + per);
   double acc[2][kLbChunk];
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int k = 0; k < kLbChunk; ++k) acc[r][k] = 0.0;
-  for (long e = e0 + threadIdx.x; e < e1; e += kLbBlock) {
-    const double r0 = (double)A.right[0][e];
-    const double r1 = A.n_right > 1 ? (double)A.right[1][e] : 0.0;
+  for (long q = q0 + threadIdx.x; q < q1; q += kLbBlock) {
+    const V r0 = reinterpret_cast<const V *>(A.right[0])[q];
+    V r1 = r0;
+    if (A.n_right > 1) r1 = reinterpret_cast<const V *>(A.right[1])[q];
 #pragma unroll
     for (int k = 0; k < kLbChunk; ++k) {
       if (k < nl) {
-        const double lv = (double)A.left[l0 + k][e];
-        acc[0][k] += lv * r0;
-        acc[1][k] += lv * r1;
+        const V lv = reinterpret_cast<const V *>(A.left[l0 + k])[q];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+          acc[0][k] += lane_of(lv, i) * lane_of(r0, i);
+          acc[1][k] += lane_of(lv, i) * lane_of(r1, i);
+        }
+      }
+    }
+  }
+  if (blockIdx.x == 0) {
+    for (long e = groups * NV + threadIdx.x; e < A.n; e += kLbBlock) {
+      const double r0 = (double)A.right[0][e];
+      const double r1 = A.n_right > 1 ? (double)A.right[1][e] : r0;
+#pragma unroll
+      for (int k = 0; k < kLbChunk; ++k) {
+        if (k < nl) {
+          const double lv = (double)A.left[l0 + k][e];
+          acc[0][k] += lv * r0;
+          acc[1][k] += lv * r1;
+        }
       }
     }
   }
@@ -110,13 +148,38 @@ struct CombineArgs {
   long n;
 };
 
+// d = c_g g + sum_k c_k v_k, 16-byte vectors per thread (FP64 sums), the
+// elements past the last whole vector one per thread
 template <typename T>
 __global__ __launch_bounds__(kLbBlock) void combine_kernel(CombineArgs<T> A) {
-  const long e = (long)blockIdx.x * kLbBlock + threadIdx.x;
-  if (e >= A.n) return;
-  double acc = A.coef[0] * (double)A.g[e];
-  for (int k = 0; k < A.nv; ++k) acc += A.coef[1 + k] * (double)A.v[k][e];
-  A.d[e] = (T)acc;
+  using V = typename Vec4<T>::type;
+  constexpr int NV = Vec4<T>::n;
+  const long groups = A.n / NV;
+  const long q = (long)blockIdx.x * kLbBlock + threadIdx.x;
+  if (q < groups) {
+    const V gv = reinterpret_cast<const V *>(A.g)[q];
+    double acc[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i] = A.coef[0] * lane_of(gv, i);
+    for (int k = 0; k < A.nv; ++k) {
+      const V x = reinterpret_cast<const V *>(A.v[k])[q];
+      const double c = A.coef[1 + k];
+#pragma unroll
+      for (int i = 0; i < NV; ++i) acc[i] += c * lane_of(x, i);
+    }
+    V out;
+    T *o = reinterpret_cast<T *>(&out);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) o[i] = (T)acc[i];
+    reinterpret_cast<V *>(A.d)[q] = out;
+  } else {
+    const long e = groups * NV + (q - groups);
+    if (q - groups < NV && e < A.n) {
+      double acc = A.coef[0] * (double)A.g[e];
+      for (int k = 0; k < A.nv; ++k) acc += A.coef[1 + k] * (double)A.v[k][e];
+      A.d[e] = (T)acc;
+    }
+  }
 }
 
 template <typename T>
@@ -221,7 +284,8 @@ hipError_t multidot(modil_lbfgs *lb, const std::vector<const void *> &left,
   A.n = lb->n;
   A.partials = lb->partials;
   const int chunks = (A.n_left + kLbChunk - 1) / kLbChunk;
-  const int blocks = (int)std::min<long>(kLbBlocks, std::max<long>(1, (lb->n + kLbBlock - 1) / kLbBlock));
+  const long groups = lb->n / Vec4<T>::n;
+  const int blocks = (int)std::min<long>(kLbBlocks, std::max<long>(1, (groups + kLbBlock - 1) / kLbBlock));
   hipStream_t s = lb->c->stream;
   Timed tm(lb->c, 5);
   multidot_kernel<T><<<dim3(blocks, chunks), kLbBlock, 0, s>>>(A);
@@ -291,7 +355,8 @@ hipError_t launch_combine(modil_lbfgs *lb, int k) {
   A.coef = lb->coef;
   A.n = lb->n;
   Timed tm(lb->c, 6);
-  combine_kernel<T><<<nblk_lb(lb->n), kLbBlock, 0, lb->c->stream>>>(A);
+  const long groups = lb->n / Vec4<T>::n;
+  combine_kernel<T><<<nblk_lb(groups + Vec4<T>::n), kLbBlock, 0, lb->c->stream>>>(A);
   return hipGetLastError();
 }
 
