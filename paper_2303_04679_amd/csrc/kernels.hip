@@ -41,9 +41,19 @@ __device__ inline void locate(const Levels &G, int l, int e, int &inst, int &f, 
 
 // (T w)(i) of field f at fine level l from the level-(l+1) array base cb
 template <typename T>
+__device__ inline T prolong_value_at(const Levels &G, int l, int f, const int (&i)[3],
+                                     const T *__restrict__ cb);
+
+template <typename T>
 __device__ inline T prolong_value(const Levels &G, int l, int inst, int f, const int (&i)[3],
                                   const T *__restrict__ cbase) {
-  const T *cb = cbase + inst * G.stride[l + 1] + G.foff[l + 1][f];
+  return prolong_value_at(G, l, f, i, cbase + inst * G.stride[l + 1] + G.foff[l + 1][f]);
+}
+
+// (T w)(i) from cb, the level-(l+1) array of field f of one instance
+template <typename T>
+__device__ inline T prolong_value_at(const Levels &G, int l, int f, const int (&i)[3],
+                                     const T *__restrict__ cb) {
   const int cnx = G.n[l + 1][f][2], cny = G.n[l + 1][f][1];
   const int sy = cnx, sz = cny * cnx;
   const bool span_z = G.n[l][f][0] != G.n[l + 1][f][0];
@@ -81,9 +91,19 @@ __device__ inline T prolong_value(const Levels &G, int l, int inst, int f, const
 // before it waits.  The end-cell rows in y and z sit in one branch that is
 // uniform across a wave running along x.
 template <typename T>
+__device__ inline T restrict_value_at(const Levels &G, int l, int f, const int (&I)[3],
+                                      const T *__restrict__ fb);
+
+template <typename T>
 __device__ inline T restrict_value(const Levels &G, int l, int inst, int f, const int (&I)[3],
                                    const T *__restrict__ fbase) {
-  const T *fb = fbase + inst * G.stride[l] + G.foff[l][f];
+  return restrict_value_at(G, l, f, I, fbase + inst * G.stride[l] + G.foff[l][f]);
+}
+
+// (T^T g)(I) from fb, the level-l array of field f of one instance
+template <typename T>
+__device__ inline T restrict_value_at(const Levels &G, int l, int f, const int (&I)[3],
+                                      const T *__restrict__ fb) {
   const int sy = G.n[l][f][2], sz = G.n[l][f][1] * sy;
   const bool span_z = G.n[l][f][0] != G.n[l + 1][f][0];
   const bool span_y = G.n[l][f][1] != G.n[l + 1][f][1];
@@ -164,31 +184,69 @@ __global__ __launch_bounds__(kBlock) void prolong_kernel(Levels G, int l, const 
   dst[e] = th + prolong_value(G, l, inst, f, i, csrc);
 }
 
-// The small coarse levels of one instance per block, in LDS: w_{L-1} =
-// theta_{L-1}, then w_l = theta_l + T w_{l+1} for l = L-2 .. l_stop; every
-// w_l it produces is also written to w (pack layout).  Level l sits in LDS
-// buffer (l - l_stop) % 2, sized for levels l_stop and l_stop + 1.
+// cells of field f on level l and the 3-D index of cell e of it
+__device__ inline int field_cells(const Levels &G, int l, int f) {
+  return G.n[l][f][0] * G.n[l][f][1] * G.n[l][f][2];
+}
+__device__ inline void field_index(const Levels &G, int l, int f, int e, int (&i)[3]) {
+  const int nx = G.n[l][f][2], ny = G.n[l][f][1];
+  i[2] = e % nx;
+  e /= nx;
+  i[1] = e % ny;
+  i[0] = e / ny;
+}
+
+// The small coarse levels of one field of one instance per block, in LDS:
+// w_{L-1} = theta_{L-1}, then w_l = theta_l + T w_{l+1} for l = L-2 .. l_stop;
+// every w_l it produces is also written to w (pack layout).  Level l sits in
+// LDS buffer (l - l_stop) % 2, sized for levels l_stop and l_stop + 1.
 template <typename T>
-__global__ __launch_bounds__(1024) void horner_tail_kernel(Levels G, int l_stop,
+__global__ __launch_bounds__(1024) void horner_tail_kernel(Levels G, int l_stop, int cap0,
                                                            const T *__restrict__ theta, T *w) {
+  constexpr int kPf = 4;  // theta values per thread of the last (largest) level, loaded first
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T *buf[2] = {reinterpret_cast<T *>(smem_raw), reinterpret_cast<T *>(smem_raw) + G.stride[l_stop]};
-  const int inst = blockIdx.x;
+  T *buf[2] = {reinterpret_cast<T *>(smem_raw), reinterpret_cast<T *>(smem_raw) + cap0};
+  const int inst = blockIdx.x / G.nf, f = blockIdx.x % G.nf;
+  const int bd = blockDim.x, tid = threadIdx.x;
+  const int bstop = G.off[l_stop] + inst * G.stride[l_stop] + G.foff[l_stop][f];
+  const int nstop = field_cells(G, l_stop, f);
+  T pth[kPf];
+#pragma unroll
+  for (int u = 0; u < kPf; ++u) {
+    const int e = tid + u * bd;
+    pth[u] = e < nstop ? theta[bstop + e] : T(0);
+  }
   {
     const int l = G.L - 1;
     T *dst = buf[(l - l_stop) & 1];
-    const T *src = theta + G.off[l] + inst * G.stride[l];
-    for (int e = threadIdx.x; e < G.stride[l]; e += blockDim.x) dst[e] = src[e];
+    const T *src = theta + G.off[l] + inst * G.stride[l] + G.foff[l][f];
+    for (int e = tid; e < field_cells(G, l, f); e += bd) dst[e] = src[e];
   }
   __syncthreads();
   for (int l = G.L - 2; l >= l_stop; --l) {
     T *dst = buf[(l - l_stop) & 1];
     const T *cs = buf[(l + 1 - l_stop) & 1];
-    const int base = G.off[l] + inst * G.stride[l];
-    for (int e = threadIdx.x; e < G.stride[l]; e += blockDim.x) {
-      int in0, f, i[3];
-      locate(G, l, e, in0, f, i);
-      const T val = theta[base + e] + prolong_value(G, l, 0, f, i, cs);
+    const int base = G.off[l] + inst * G.stride[l] + G.foff[l][f];
+    const int n = field_cells(G, l, f);
+    int e0 = tid;
+    if (l == l_stop) {
+#pragma unroll
+      for (int u = 0; u < kPf; ++u) {
+        const int e = tid + u * bd;
+        if (e < n) {
+          int i[3];
+          field_index(G, l, f, e, i);
+          const T val = pth[u] + prolong_value_at(G, l, f, i, cs);
+          dst[e] = val;
+          w[base + e] = val;
+        }
+      }
+      e0 = tid + kPf * bd;
+    }
+    for (int e = e0; e < n; e += bd) {
+      int i[3];
+      field_index(G, l, f, e, i);
+      const T val = theta[base + e] + prolong_value_at(G, l, f, i, cs);
       dst[e] = val;
       w[base + e] = val;
     }
@@ -217,30 +275,69 @@ __global__ __launch_bounds__(kBlock) void restrict_kernel(Levels G, int l, T *g,
   if (ADAM) adam_elem_loaded(A, k, val, th, m, v);
 }
 
-// g_{l+1} = T^T g_l for l = l_lo .. L-2 of one instance per block, in LDS,
-// with Adam on every level produced; level l_lo is read from g, every level
-// produced is written back to g.  Two LDS buffers sized for levels l_lo and
-// l_lo + 1 alternate.
+// g_{l+1} = T^T g_l for l = l_lo .. L-2 of one field of one instance per
+// block, in LDS, with Adam on every level produced; level l_lo is read from g,
+// every level produced is written back to g.  Two LDS buffers sized for
+// levels l_lo and l_lo + 1 alternate.
 template <typename T, bool ADAM>
-__global__ __launch_bounds__(1024) void restrict_tail_kernel(Levels G, int l_lo, T *g, AdamArgs<T> A) {
+__global__ __launch_bounds__(1024) void restrict_tail_kernel(Levels G, int l_lo, int cap0, T *g,
+                                                             AdamArgs<T> A) {
+  constexpr int kPf = 2;  // outputs per thread of the first level whose Adam state is prefetched
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *cur = reinterpret_cast<T *>(smem_raw);
-  T *nxt = cur + G.stride[l_lo];
-  const int inst = blockIdx.x;
+  T *nxt = cur + cap0;
+  const int inst = blockIdx.x / G.nf, f = blockIdx.x % G.nf;
+  const int bd = blockDim.x, tid = threadIdx.x;
+  const int base1 = G.off[l_lo + 1] + inst * G.stride[l_lo + 1] + G.foff[l_lo + 1][f];
+  const int n1 = field_cells(G, l_lo + 1, f);
+  T pth[kPf], pm[kPf], pv[kPf];
+#pragma unroll
+  for (int u = 0; u < kPf; ++u) {
+    const int e = tid + u * bd;
+    pth[u] = pm[u] = pv[u] = T(0);
+    if (ADAM && e < n1) {
+      pth[u] = A.th_in[base1 + e];
+      pm[u] = A.m[base1 + e];
+      pv[u] = A.v[base1 + e];
+    }
+  }
   {
-    const T *src = g + G.off[l_lo] + inst * G.stride[l_lo];
-    for (int e = threadIdx.x; e < G.stride[l_lo]; e += blockDim.x) cur[e] = src[e];
+    const T *src = g + G.off[l_lo] + inst * G.stride[l_lo] + G.foff[l_lo][f];
+    for (int e = tid; e < field_cells(G, l_lo, f); e += bd) cur[e] = src[e];
   }
   __syncthreads();
   for (int l = l_lo; l + 1 < G.L; ++l) {
-    const int base = G.off[l + 1] + inst * G.stride[l + 1];
-    for (int e = threadIdx.x; e < G.stride[l + 1]; e += blockDim.x) {
-      int in0, f, I[3];
-      locate(G, l + 1, e, in0, f, I);
-      const T val = restrict_value(G, l, 0, f, I, cur);
+    const int base = G.off[l + 1] + inst * G.stride[l + 1] + G.foff[l + 1][f];
+    const int n = field_cells(G, l + 1, f);
+    int e0 = tid;
+    if (l == l_lo) {
+#pragma unroll
+      for (int u = 0; u < kPf; ++u) {
+        const int e = tid + u * bd;
+        if (e < n) {
+          int I[3];
+          field_index(G, l + 1, f, e, I);
+          const T val = restrict_value_at(G, l, f, I, cur);
+          nxt[e] = val;
+          g[base + e] = val;
+          if (ADAM) adam_elem_loaded(A, base + e, val, pth[u], pm[u], pv[u]);
+        }
+      }
+      e0 = tid + kPf * bd;
+    }
+    for (int e = e0; e < n; e += bd) {
+      T th = T(0), m = T(0), v = T(0);
+      if (ADAM) {
+        th = A.th_in[base + e];
+        m = A.m[base + e];
+        v = A.v[base + e];
+      }
+      int I[3];
+      field_index(G, l + 1, f, e, I);
+      const T val = restrict_value_at(G, l, f, I, cur);
       nxt[e] = val;
       g[base + e] = val;
-      if (ADAM) adam_elem(A, base + e, val);
+      if (ADAM) adam_elem_loaded(A, base + e, val, th, m, v);
     }
     __syncthreads();
     T *t = cur;
@@ -504,20 +601,37 @@ Levels levels_of(const modil_ctx *c) {
   return G;
 }
 
-// Smallest level l >= lo such that levels l and l+1 of one instance fit the
-// LDS budget together and the levels below l, which one block (one compute
-// unit) then produces alone, hold few enough values to take less time than a
-// launch per level; L - 1 if there is none.  With many instances every
-// compute unit has a block, so each block may do more.
-static int tail_level(const Levels &G, int lo, size_t elem, size_t budget) {
-  const long cap = G.batch >= 128 ? 16384 : 2048;  // values one block produces
+static long field_size(const Levels &G, int l, int f) {
+  return (long)G.n[l][f][0] * G.n[l][f][1] * G.n[l][f][2];
+}
+
+// Largest per-field cell count of level l
+static long max_field(const Levels &G, int l) {
+  long m = 0;
+  for (int f = 0; f < G.nf; ++f) m = std::max(m, field_size(G, l, f));
+  return m;
+}
+
+// The LDS tail kernels give the small coarse levels one block per field and
+// instance.  tail_level returns the smallest level l >= lo whose next level
+// (levels l and l + 1 of a field) fits the LDS budget and below which a block
+// produces at most `cap` values, L - 1 if there is none.  A restriction output
+// gathers up to 96 values, a prolongation output 8, hence separate caps.
+static int tail_level(const Levels &G, int lo, size_t elem, size_t budget, long cap, bool from_next) {
   for (int l = lo; l + 1 < G.L; ++l) {
     long work = 0;
-    for (int j = l + 1; j < G.L; ++j) work += G.stride[j];
-    if ((size_t)(G.stride[l] + G.stride[l + 1]) * elem <= budget && work <= cap) return l;
+    for (int f = 0; f < G.nf; ++f) {
+      long wf = 0;
+      for (int j = from_next ? l + 1 : l; j < G.L; ++j) wf += field_size(G, j, f);
+      work = std::max(work, wf);
+    }
+    if ((size_t)(max_field(G, l) + max_field(G, l + 1)) * elem <= budget && work <= cap) return l;
   }
   return G.L - 1;
 }
+
+constexpr long kTailCapRestrict = 2048;   // values one block restricts
+constexpr long kTailCapProlong = 16384;   // values one block prolongs
 
 template <typename K>
 static bool lds_ready(K kernel, size_t bytes) {
@@ -534,13 +648,16 @@ static hipError_t horner_t(modil_ctx *c, const void *theta_v, void *fine_dst_v, 
   T *fine_dst = fine_dst_v ? (T *)fine_dst_v : w;
   if (G.L == 1) return hipSuccess;
   int l = G.L - 2;
-  // the tail produces w_{L-2} .. w_lt, the levels below the first one that is
-  // too large for it, and stops at level 1 (level 0 goes to fine_dst)
-  const int lt = c->tail_enabled ? std::max(1, tail_level(G, 0, sizeof(T), c->lds_budget) + 1) : G.L;
-  if (lt <= G.L - 3) {  // at least two levels in one launch
-    const size_t bytes = (size_t)(G.stride[lt] + G.stride[lt + 1]) * sizeof(T);
+  // the tail produces w_{L-2} .. w_lt (at least two levels, none below 1;
+  // level 0 goes to fine_dst)
+  int lt = c->tail_enabled
+               ? tail_level(G, 1, sizeof(T), c->lds_budget, kTailCapProlong, false)
+               : G.L;
+  if (lt <= G.L - 3) {
+    const int cap0 = (int)max_field(G, lt);
+    const size_t bytes = (size_t)(cap0 + max_field(G, lt + 1)) * sizeof(T);
     if (lds_ready(horner_tail_kernel<T>, bytes)) {
-      horner_tail_kernel<T><<<G.batch, 1024, bytes, c->stream>>>(G, lt, theta, w);
+      horner_tail_kernel<T><<<G.batch * G.nf, 1024, bytes, c->stream>>>(G, lt, cap0, theta, w);
       l = lt - 1;
     }
   }
@@ -570,8 +687,11 @@ static hipError_t restrict_t(modil_ctx *c, void *g_v, int from, const void *th_i
     A.b1 = T(ad->b1); A.b2 = T(ad->b2); A.step = T(ad->step); A.isb2 = T(ad->isb2); A.eps = T(ad->eps);
   }
   // levels lt+1 .. L-1 come from one launch of the LDS tail kernel
-  int lt = c->tail_enabled ? tail_level(G, from, sizeof(T), c->lds_budget) : G.L - 1;
-  const size_t bytes = lt + 1 < G.L ? (size_t)(G.stride[lt] + G.stride[lt + 1]) * sizeof(T) : 0;
+  int lt = c->tail_enabled
+               ? tail_level(G, from, sizeof(T), c->lds_budget, kTailCapRestrict, true)
+               : G.L - 1;
+  const int cap0 = lt + 1 < G.L ? (int)max_field(G, lt) : 0;
+  const size_t bytes = lt + 1 < G.L ? (size_t)(cap0 + max_field(G, lt + 1)) * sizeof(T) : 0;
   if (lt + 1 < G.L && !(ad ? lds_ready(restrict_tail_kernel<T, true>, bytes)
                           : lds_ready(restrict_tail_kernel<T, false>, bytes)))
     lt = G.L - 1;
@@ -587,9 +707,9 @@ static hipError_t restrict_t(modil_ctx *c, void *g_v, int from, const void *th_i
   }
   if (lt + 1 < G.L) {
     if (ad)
-      restrict_tail_kernel<T, true><<<G.batch, 1024, bytes, c->stream>>>(G, lt, g, A);
+      restrict_tail_kernel<T, true><<<G.batch * G.nf, 1024, bytes, c->stream>>>(G, lt, cap0, g, A);
     else
-      restrict_tail_kernel<T, false><<<G.batch, 1024, bytes, c->stream>>>(G, lt, g, A);
+      restrict_tail_kernel<T, false><<<G.batch * G.nf, 1024, bytes, c->stream>>>(G, lt, cap0, g, A);
   }
   return hipGetLastError();
 }

@@ -34,6 +34,7 @@ constexpr int NS_MAIN = NSO_X * NST_Y;  // threads on the full-width rows
 constexpr int NS_HALO = 4 * NST_Y;       // threads for the four halo columns
 constexpr int NS_THREADS = NS_MAIN + (NS_HALO + 63) / 64 * 64;  // whole waves
 constexpr int NS_XCD = 8;
+constexpr int NF_MAX_COARSE = 5;  // unknown fields with a coarse hierarchy
 static_assert(NS_THREADS - NS_MAIN >= NS_HALO, "every halo-column position needs a thread");
 #ifndef NS_WAVES_PER_EU
 #define NS_WAVES_PER_EU 3
@@ -62,14 +63,20 @@ struct NS3DArgs {
   AdamArgs<T> adam;   // level-0 pointers of theta_in / theta_out / m / v
 };
 
+// Level-1 (coarse) window of a tile: the coarse cells that the xy
+// interpolation of its 36 x 20 fine columns touches, 20 x 12 per field.
+constexpr int NCT_X = NST_X / 2 + 2, NCT_Y = NST_Y / 2 + 2;
+constexpr int NCT = NCT_X * NCT_Y;
+
+// xy interpolation of one coarse plane of every field from its LDS window;
+// lx, ly are window coordinates of the taps
 template <typename T, int NF>
-__device__ inline void coarse_xy(const NS3DArgs<T> &A, int inst, int K, const int (&jx)[2],
-                                 const T (&wx)[2], const int (&jy)[2], const T (&wy)[2], T (&W)[NF]) {
-  const T *b = A.w1 + inst * A.w1_inst + K * A.nc[1] * A.nc[2];
+__device__ inline void coarse_xy(const T *cw, const int (&lx)[2], const T (&wx)[2],
+                                 const int (&ly)[2], const T (&wy)[2], T (&W)[NF]) {
   for (int f = 0; f < NF; ++f) {
-    const T *bf = b + f * A.csize;
-    const T r0 = wx[0] * bf[jy[0] * A.nc[2] + jx[0]] + wx[1] * bf[jy[0] * A.nc[2] + jx[1]];
-    const T r1 = wx[0] * bf[jy[1] * A.nc[2] + jx[0]] + wx[1] * bf[jy[1] * A.nc[2] + jx[1]];
+    const T *bf = cw + f * NCT;
+    const T r0 = wx[0] * bf[ly[0] * NCT_X + lx[0]] + wx[1] * bf[ly[0] * NCT_X + lx[1]];
+    const T r1 = wx[0] * bf[ly[1] * NCT_X + lx[0]] + wx[1] * bf[ly[1] * NCT_X + lx[1]];
     W[f] = wy[0] * r0 + wy[1] * r1;
   }
 }
@@ -89,6 +96,10 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
   constexpr bool SAVE_L = sizeof(T) == 4;
   constexpr int NLS = 12;
   __shared__ T Ls[SAVE_L ? 2 : 1][SAVE_L ? NLS : 1][SAVE_L ? NS_THREADS : 1];
+  // two coarse planes (coarse plane K in slot K & 1): the one a fine plane
+  // interpolates from and the next; the next one is loaded a plane ahead
+  static_assert(NF_MAX_COARSE * NCT <= 2 * NS_THREADS, "two coarse values per thread");
+  __shared__ T Cw[2][NF_MAX_COARSE * NCT];
 
   const OpParams &p = A.p;
   const int tid = threadIdx.x;
@@ -136,6 +147,48 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
   T Wlo[NF], Whi[NF];
   for (int f = 0; f < NF; ++f) Wlo[f] = Whi[f] = T(0);
   int kmin_c = -1000;
+  // coarse window origin (ox, oy are even) and the taps in window coordinates
+  const int cxb = (ox >> 1) - 1, cyb = (oy >> 1) - 1;
+  const int lx[2] = {jx[0] - cxb, jx[1] - cxb}, ly[2] = {jy[0] - cyb, jy[1] - cyb};
+  // lower coarse plane of the interpolation of fine plane z (valid z)
+  auto kbase = [&](int z) {
+    if (z == 0) return 0;
+    if (z == nz - 1) return A.nc[0] - 2;
+    return (z & 1) ? z / 2 : z / 2 - 1;
+  };
+  // each thread moves two values of a coarse plane window: global -> registers -> LDS
+  auto cload = [&](int Kc, T (&r)[2]) {
+    for (int u = 0; u < 2; ++u) {
+      const int e = tid + u * NS_THREADS;
+      r[u] = T(0);
+      if (e < NF * NCT) {
+        const int f = e / NCT, rem = e - f * NCT, j = rem / NCT_X, i = rem - j * NCT_X;
+        const int cy = cyb + j, cx = cxb + i;
+        if (cy >= 0 && cy < A.nc[1] && cx >= 0 && cx < A.nc[2])
+          r[u] = A.w1[inst * A.w1_inst + f * A.csize + (Kc * A.nc[1] + cy) * A.nc[2] + cx];
+      }
+    }
+  };
+  auto cstore = [&](int Kc, const T (&r)[2]) {
+    for (int u = 0; u < 2; ++u) {
+      const int e = tid + u * NS_THREADS;
+      if (e < NF * NCT) Cw[Kc & 1][e] = r[u];
+    }
+  };
+  // planes resident in the two slots; prologue: the first fine plane's pair
+  int res[2] = {-1, -1};
+  if (A.has_coarse) {
+    const int zf = max(z0 - 2, 0);
+    const int k0 = kbase(zf);
+    T r0[2], r1[2];
+    cload(k0, r0);
+    cload(k0 + 1, r1);
+    cstore(k0, r0);
+    cstore(k0 + 1, r1);
+    res[k0 & 1] = k0;
+    res[(k0 + 1) & 1] = k0 + 1;
+    __syncthreads();
+  }
 
   T U0[NS], U1[NS], U2[NS], U3[NS];  // planes pz-3 .. pz
   T A0[4], A1[4], A2[4];             // seeds at planes pz-3 .. pz-1
@@ -159,7 +212,18 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
   }
 
   for (int pz = z0 - 2; pz <= z1 + 1; ++pz) {
-    // ---- 0. issue the loads needed later: theta of plane pz+1, m and v of plane pz-2
+    // ---- 0. issue the loads needed later: the coarse plane the next fine plane
+    // adds (stored to LDS at the end of this iteration), theta of plane pz+1,
+    // m and v of plane pz-2
+    T cpre[2];
+    int cnext = -1;
+    if (A.has_coarse && pz + 1 <= z1 + 1 && pz + 1 >= 0 && pz + 1 < nz) {
+      const int kn = kbase(pz + 1) + 1;
+      if (res[kn & 1] != kn) {
+        cnext = kn;
+        cload(kn, cpre);
+      }
+    }
     T th[NF], chi_pz = chin;
     for (int f = 0; f < NF; ++f) th[f] = thn[f];
     if (in_xy && pz + 1 >= 0 && pz + 1 < nz) {
@@ -191,10 +255,10 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
         if (km != kmin_c) {
           if (km == kmin_c + 1) {
             for (int f = 0; f < NF; ++f) Wlo[f] = Whi[f];
-            coarse_xy<T, NF>(A, inst, km + 1, jx, wx, jy, wy, Whi);
+            coarse_xy<T, NF>(Cw[(km + 1) & 1], lx, wx, ly, wy, Whi);
           } else {
-            coarse_xy<T, NF>(A, inst, km, jx, wx, jy, wy, Wlo);
-            coarse_xy<T, NF>(A, inst, km + 1, jx, wx, jy, wy, Whi);
+            coarse_xy<T, NF>(Cw[km & 1], lx, wx, ly, wy, Wlo);
+            coarse_xy<T, NF>(Cw[(km + 1) & 1], lx, wx, ly, wy, Whi);
           }
           kmin_c = km;
         }
@@ -344,6 +408,12 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
           A.adam.th_out[k] = adam_theta(tq[f], mm, vv, A.adam.step, A.adam.isb2, A.adam.eps);
         }
       }
+    }
+    // the slot taken by the next coarse plane held the one below this fine
+    // plane's pair, which nobody reads after step 1
+    if (cnext >= 0) {
+      cstore(cnext, cpre);
+      res[cnext & 1] = cnext;
     }
     __syncthreads();
   }
