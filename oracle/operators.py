@@ -66,14 +66,18 @@ def field_shape(op, field, dims):
     return tuple(dims)
 
 
-def level_shapes(op, dims, n_levels):
-    """Shape of every (level, field) array: list over levels of list over fields."""
+def level_shapes(op, dims, n_levels, centering="cell"):
+    """Shape of every (level, field) array: list over levels of list over fields.
+
+    dims are cells per axis; node-based fields hold one more value per axis
+    (the nodes, boundary nodes included)."""
+    extra = 1 if centering == "node" else 0
     out = []
     for lvl in range(n_levels):
         row = []
         for f in FIELDS[op]:
             s = field_shape(op, f, dims)
-            row.append(tuple(n // 2 ** lvl for n in s))
+            row.append(tuple(n // 2 ** lvl + extra for n in s))
         out.append(row)
     return out
 
@@ -171,6 +175,32 @@ def _shift(xp, axis, s):
 
 
 # ------------------------------------------------------------------ residuals
+def poisson_node_residual(spec, u):
+    """Node-based Poisson (Section 3.1): the finite-difference Laplacian minus
+    the forcing at the interior nodes; the Dirichlet condition is the
+    boundary-integral term of the loss (poisson_node_boundary)."""
+    inner = tuple(slice(1, -1) for _ in range(u.dim()))
+    f = spec.forcing.get(0)
+    R = torch.zeros_like(u[inner]) if f is None else -torch.as_tensor(f, dtype=DT)[inner]
+    for a, h in enumerate(spec.h):
+        lo = tuple(slice(0, -2) if b == a else slice(1, -1) for b in range(u.dim()))
+        hi = tuple(slice(2, None) if b == a else slice(1, -1) for b in range(u.dim()))
+        R = R + (u[hi] - 2.0 * u[inner] + u[lo]) / h ** 2
+    return [R]
+
+
+def poisson_node_boundary(u):
+    """Values at the boundary nodes (every node with an index 0 or N on some axis)."""
+    mask = torch.zeros(u.shape, dtype=torch.bool)
+    for a in range(u.dim()):
+        idx = [slice(None)] * u.dim()
+        idx[a] = 0
+        mask[tuple(idx)] = True
+        idx[a] = -1
+        mask[tuple(idx)] = True
+    return u[mask]
+
+
 def poisson_residual(spec, u):
     """Laplacian minus forcing at every cell (Section 3.1, cell-based)."""
     f = spec.forcing.get(0)
@@ -371,6 +401,8 @@ def cavity_residual(spec, fields):
 def residuals(spec, fine):
     """PDE residual arrays of the problem for the list of fine fields."""
     op = spec.op
+    if op == "poisson" and spec.centering == "node":
+        return poisson_node_residual(spec, fine[0])
     if op == "poisson":
         return poisson_residual(spec, fine[0])
     if op == "burgers":
@@ -398,6 +430,11 @@ def loss_terms(spec, fine):
     if spec.op == "heat":
         left, right = heat_boundary(spec, fine[0])
         terms["bc"] = W["bc"] * spec.h[0] * ((left * left).sum() + (right * right).sum())
+    if spec.op == "poisson" and spec.centering == "node":
+        # the boundary integral of u^2, each boundary node with the surface
+        # element h^(d-1) of a uniform grid
+        ub = poisson_node_boundary(fine[0])
+        terms["bc"] = W["bc"] * V ** ((spec.ndim - 1) / spec.ndim) * (ub * ub).sum()
     for fi, term, idx, vals, wt in spec.meas:
         x = fine[fi].reshape(-1)[torch.as_tensor(idx, dtype=torch.long)]
         d = x - torch.as_tensor(vals, dtype=DT)
@@ -454,7 +491,7 @@ def residual_metric(spec, levels):
         R = residuals(spec, fine_fields(spec, lv))
         V = spec.cell_measure
         s = math.fsum(float(v) for r in R for v in (V * r).reshape(-1) ** 2)
-        count = math.prod(spec.dims) * len(R)
+        count = sum(r.numel() for r in R)
     return math.sqrt(s / count)
 
 

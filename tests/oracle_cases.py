@@ -25,6 +25,11 @@ def case(op, dims, n_levels, seed=0, with_forcing=False):
         spec = ops.Spec("poisson", dims, (1.0,) * nd, n_levels, weights={"pde": 1.0})
         spec.forcing = {0: synth.rng(seed + 5).uniform(-50, 50, size=dims)}
         return spec
+    if op == "poisson_node":
+        spec = ops.Spec("poisson", dims, (1.0,) * nd, n_levels, weights={"pde": 1.0, "bc": 1.0},
+                        centering="node")
+        spec.forcing = {0: synth.rng(seed + 5).uniform(-50, 50, size=tuple(d + 1 for d in dims))}
+        return spec
     if op == "burgers":
         spec = ops.Spec("burgers", dims, (1.0, 2.0), n_levels,
                         weights={"pde": 1.0, "data": 100.0, "reg": 1e-4})
@@ -63,5 +68,5 @@ def case(op, dims, n_levels, seed=0, with_forcing=False):
 
 
 def random_levels(spec, seed, lo=-1.0, hi=1.0):
-    shapes = ops.level_shapes(spec.op, spec.dims, spec.n_levels)
+    shapes = ops.level_shapes(spec.op, spec.dims, spec.n_levels, spec.centering)
     return synth.uniform_levels(shapes, seed, lo, hi)

@@ -17,6 +17,9 @@ from tests.oracle_cases import case, random_levels
 
 CASES = [
     ("poisson", (8,), 3),
+    ("poisson_node", (8,), 3),
+    ("poisson_node", (8, 4), 2),
+    ("poisson_node", (4, 4, 4), 2),
     ("poisson", (8, 8), 3),
     ("poisson", (4, 4, 4), 2),
     ("burgers", (8, 8), 3),

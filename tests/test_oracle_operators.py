@@ -319,3 +319,78 @@ def test_cavity_pressure_gauge_invariance():
     a = ops.loss_value(spec, [f])["pde"]
     b = ops.loss_value(spec, [[f[0], f[1], f[2] + 3.25]])["pde"]
     assert abs(a - b) <= 1e-13 * a
+
+
+# ------------------------------------------------------- node-based Poisson
+def _node_grid(n, d):
+    x = np.arange(n + 1) / n
+    return np.meshgrid(*([x] * d), indexing="ij")
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_node_poisson_exact_for_product_of_quadratics(d):
+    """u = prod x_a (1 - x_a) vanishes on the boundary, and the 3-point second
+    difference of x (1 - x) is exactly -2, so f = -2 sum_a prod_{b != a}
+    x_b (1 - x_b) makes every term of the node-based loss zero."""
+    n = 8
+    X = _node_grid(n, d)
+    q = [x * (1 - x) for x in X]
+    u = np.prod(q, axis=0)
+    f = np.zeros_like(u)
+    for a in range(d):
+        f += -2.0 * np.prod([q[b] for b in range(d) if b != a], axis=0) if d > 1 else -2.0
+    spec = ops.Spec("poisson", (n,) * d, (1.0,) * d, 1, weights={"pde": 1.0, "bc": 1.0},
+                    centering="node", forcing={0: f})
+    terms = ops.loss_value(spec, [[u]])
+    assert terms["pde"] < 1e-26 and terms["bc"] < 1e-30, terms
+
+
+@pytest.mark.parametrize("d,expected", [(1, 2.0), (2, 4.0), (3, 6.0 + 2.0 / 64)])
+def test_node_boundary_term_is_the_boundary_measure(d, expected):
+    """u = 1: the boundary term is h^(d-1) times the number of boundary nodes,
+    i.e. the measure of the boundary of [0,1]^d (2 points, perimeter 4, area 6
+    plus the doubly counted edges 2 / N^2 for N = 8)."""
+    n = 8
+    spec = ops.Spec("poisson", (n,) * d, (1.0,) * d, 1, weights={"pde": 1.0, "bc": 1.0},
+                    centering="node")
+    terms = ops.loss_value(spec, [[np.ones((n + 1,) * d)]])
+    assert abs(terms["bc"] - expected) < 1e-12
+    assert terms["pde"] == 0.0
+
+
+def test_node_level_shapes():
+    assert ops.level_shapes("poisson", (32, 16), 3, "node") == [[(33, 17)], [(17, 9)], [(9, 5)]]
+
+
+def test_node_lbfgs_converges_fast_in_1d():
+    """Section 3.1: in 1-D, L-BFGS reaches machine precision in about 50
+    iterations with three or more levels (node-based)."""
+    from oracle import lbfgs as ol
+    n = 32
+    x = np.arange(n + 1) / n
+    v = 5.0 * (1.0 - x) * x
+    u_ref = (v ** 5 / (1.0 + v ** 5)) ** 0.2
+    f = np.zeros(n + 1)
+    f[1:-1] = (u_ref[2:] - 2 * u_ref[1:-1] + u_ref[:-2]) * n * n
+    spec = ops.Spec("poisson", (n,), (1.0,), 3, weights={"pde": 1.0, "bc": 1.0},
+                    centering="node", forcing={0: f})
+    shapes = ops.level_shapes("poisson", (n,), 3, "node")
+    sizes = [s[0][0] for s in shapes]
+
+    def split(xv):
+        out, o = [], 0
+        for m in sizes:
+            out.append([xv[o:o + m]])
+            o += m
+        return out
+
+    def fg(xv):
+        t, g = ops.loss_and_grad(spec, split(xv))
+        return sum(t.values()), np.concatenate([gg[0] for gg in g])
+
+    it = ol.LBFGS(fg, np.zeros(sum(sizes)), m=50)
+    for k in range(80):
+        if it.step().status == 2:
+            break
+    fine = ops.fine_fields(spec, [[torch.as_tensor(a[0])] for a in split(it.x)])[0].numpy()
+    assert np.max(np.abs(fine - u_ref)) < 1e-12, (k, np.max(np.abs(fine - u_ref)))
