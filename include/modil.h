@@ -61,8 +61,8 @@ extern "C" {
 #define MODIL_F32 0
 #define MODIL_F64 1
 
-#define MODIL_CELL 0 /* values at cell centres (the only layout built)   */
-#define MODIL_NODE 1 /* values at grid nodes: reserved, rejected         */
+#define MODIL_CELL 0 /* values at cell centres                           */
+#define MODIL_NODE 1 /* values at grid nodes, MODIL_OP_POISSON only      */
 
 /* Residual operators (the discretised PDEs of Sections 3.1-3.5).
  *   POISSON   d = 1,2,3; Laplacian u = f, Dirichlet u = 0 by quadratic
@@ -114,13 +114,21 @@ extern "C" {
  *   CAVITY [y][x].  For space-time grids lengths[0] is the time horizon.
  * Validation: ndim matches the operator, dims[a] divisible by
  * 2^(n_levels-1) with at least 2 coarsest cells per axis (cell-based
- * extrapolation needs two), lengths > 0, batch >= 1, 1 <= n_levels <= 8.  */
+ * extrapolation needs two), lengths > 0, batch >= 1, 1 <= n_levels <= 8.
+ * MODIL_NODE (POISSON only; Section 3.1, node-based variant): dims are cells
+ * per axis and a field holds (dims[a] >> l) + 1 nodes per axis on level l,
+ * boundary nodes included; T is the node-based interpolation of Section 2.2
+ * (even fine nodes copy the coarse node, odd ones average two).  Interior
+ * nodes carry the finite-difference Laplacian (weight w_pde h^d); every
+ * boundary node carries the term w_bc h^(d-1) u^2 of the boundary integral
+ * of u^2 (grids with equal h on every axis).  Forcing arrays and
+ * measurement indices address nodes; the forcing enters interior rows only. */
 typedef struct {
   int32_t ndim;
   int32_t dims[3];
   double lengths[3];
   int32_t n_levels;
-  int32_t centering; /* MODIL_CELL */
+  int32_t centering; /* MODIL_CELL, or MODIL_NODE (see below)               */
   int32_t dtype;     /* MODIL_F32 / MODIL_F64 */
   int32_t op;        /* MODIL_OP_* */
   int32_t flags;     /* MODIL_FLAG_* */

@@ -69,8 +69,8 @@ int validate(const modil_problem *p, std::string &msg) {
     msg = "dtype must be MODIL_F32 or MODIL_F64";
     return MODIL_ERR_DTYPE;
   }
-  if (p->centering != MODIL_CELL) {
-    msg = "only cell-based centering is implemented";
+  if (p->centering != MODIL_CELL && !(p->centering == MODIL_NODE && p->op == MODIL_OP_POISSON)) {
+    msg = "node-based values are implemented for MODIL_OP_POISSON only";
     return MODIL_ERR_DTYPE;
   }
   const int want = expected_ndim(p->op);
@@ -210,7 +210,7 @@ void fill_layout(const modil_problem &p, modil_pack_layout &L) {
   }
   L.total = off;
   L.fine_cells = 1;
-  for (int a = 0; a < p.ndim; ++a) L.fine_cells *= p.dims[a];
+  for (int a = 0; a < p.ndim; ++a) L.fine_cells *= p.dims[a] + (p.centering == MODIL_NODE ? 1 : 0);
   L.fine_total = L.level_stride[0] * p.batch;
   L.workspace_bytes = carve(p, L).end;
 }
@@ -401,7 +401,8 @@ bool field_is_x_only(const modil_problem &p, int f) { return p.op == MODIL_OP_HE
 FieldGeom field_geom(const modil_problem &p, int level, int f) {
   FieldGeom g{};
   for (int a = 0; a < 3; ++a) g.n[a] = 1;
-  for (int k = 0; k < p.ndim; ++k) g.n[3 - p.ndim + k] = p.dims[k] >> level;
+  const int extra = p.centering == MODIL_NODE ? 1 : 0;  // nodes: cells + 1 per axis
+  for (int k = 0; k < p.ndim; ++k) g.n[3 - p.ndim + k] = (p.dims[k] >> level) + extra;
   if (field_is_x_only(p, f)) g.n[0] = g.n[1] = 1;
   g.stride[2] = 1;
   g.stride[1] = g.n[2];

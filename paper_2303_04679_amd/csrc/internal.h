@@ -46,6 +46,7 @@ struct FineFields {
 // Geometry of every level of a parameter pack, 32-bit (validated to fit).
 struct Levels {
   int L, nf, batch;
+  int node;                // node-based values (Section 2.2); else cell-based
   int off[kMaxL];          // pack offset of level l
   int stride[kMaxL];       // elements of one instance on level l
   int foff[kMaxL][kMaxF];  // field offsets inside one instance

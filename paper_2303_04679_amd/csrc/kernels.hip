@@ -54,6 +54,24 @@ __device__ inline T prolong_value(const Levels &G, int l, int inst, int f, const
 template <typename T>
 __device__ inline T prolong_value_at(const Levels &G, int l, int f, const int (&i)[3],
                                      const T *__restrict__ cb) {
+  if (G.node) {
+    const int cnx = G.n[l + 1][f][2], cny = G.n[l + 1][f][1];
+    const bool sz_ = G.n[l][f][0] != G.n[l + 1][f][0], sy_ = G.n[l][f][1] != cny;
+    int ix[2], iy[2], iz[2];
+    T wx[2], wy[2], wz[2];
+    prolong_taps_node(i[2], ix, wx);
+    if (sy_) prolong_taps_node(i[1], iy, wy); else { iy[0] = iy[1] = i[1]; wy[0] = T(1); wy[1] = T(0); }
+    if (sz_) prolong_taps_node(i[0], iz, wz); else { iz[0] = iz[1] = i[0]; wz[0] = T(1); wz[1] = T(0); }
+    T acc = T(0);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const T *r = cb + ((long)iz[a] * cny + iy[b]) * cnx;
+        acc += wz[a] * wy[b] * (wx[0] * r[ix[0]] + wx[1] * r[ix[1]]);
+      }
+    return acc;
+  }
   const int cnx = G.n[l + 1][f][2], cny = G.n[l + 1][f][1];
   const int sy = cnx, sz = cny * cnx;
   const bool span_z = G.n[l][f][0] != G.n[l + 1][f][0];
@@ -104,6 +122,26 @@ __device__ inline T restrict_value(const Levels &G, int l, int inst, int f, cons
 template <typename T>
 __device__ inline T restrict_value_at(const Levels &G, int l, int f, const int (&I)[3],
                                       const T *__restrict__ fb) {
+  if (G.node) {
+    const int nx = G.n[l][f][2], ny = G.n[l][f][1], nz = G.n[l][f][0];
+    const bool sz_ = nz != G.n[l + 1][f][0], sy_ = ny != G.n[l + 1][f][1];
+    int ix[3], iy[3], iz[3];
+    T wx[3], wy[3], wz[3];
+    restrict_taps_node(I[2], nx, ix, wx);
+    if (sy_) restrict_taps_node(I[1], ny, iy, wy);
+    else { iy[0] = iy[1] = iy[2] = I[1]; wy[0] = wy[2] = T(0); wy[1] = T(1); }
+    if (sz_) restrict_taps_node(I[0], nz, iz, wz);
+    else { iz[0] = iz[1] = iz[2] = I[0]; wz[0] = wz[2] = T(0); wz[1] = T(1); }
+    T acc = T(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const T *r = fb + ((long)iz[a] * ny + iy[b]) * nx;
+        acc += wz[a] * wy[b] * (wx[0] * r[ix[0]] + wx[1] * r[ix[1]] + wx[2] * r[ix[2]]);
+      }
+    return acc;
+  }
   const int sy = G.n[l][f][2], sz = G.n[l][f][1] * sy;
   const bool span_z = G.n[l][f][0] != G.n[l + 1][f][0];
   const bool span_y = G.n[l][f][1] != G.n[l + 1][f][1];
@@ -462,7 +500,8 @@ __device__ inline void cell_residual(const FineArgs<T> &A, int inst, const int (
   chi = A.chi ? A.chi[(long)inst * A.ncell + lin] : T(0);
   Op::eval(A.p, j, inst, U, chi, r, wv, term);
   for (int e = 0; e < Op::NE && e < 4; ++e)
-    if (A.forcing[e] && wv[e] != T(0)) r[e] -= A.forcing[e][(long)inst * A.ncell + lin];
+    if (A.forcing[e] && wv[e] != T(0) && (!Op::kForcePdeOnly || term[e] == MODIL_TERM_PDE))
+      r[e] -= A.forcing[e][(long)inst * A.ncell + lin];
 }
 
 template <class Op, typename T>
@@ -590,6 +629,7 @@ Levels levels_of(const modil_ctx *c) {
   G.L = c->prob.n_levels;
   G.nf = c->lay.n_fields;
   G.batch = c->prob.batch;
+  G.node = c->prob.centering == MODIL_NODE ? 1 : 0;
   for (int l = 0; l < G.L; ++l) {
     G.off[l] = (int)c->lay.level_offset[l];
     G.stride[l] = (int)c->lay.level_stride[l];
@@ -741,9 +781,10 @@ static FineArgs<T> fine_args(modil_ctx *c, const void *u, void *g, bool want_gra
   OpParams &p = A.p;
   p.ndim = (P.op == MODIL_OP_POISSON) ? P.ndim : (P.op == MODIL_OP_NS3D ? 3 : 2);
   for (int a = 0; a < 3; ++a) { p.n[a] = 1; p.h[a] = 1.0; }
+  const int extra = P.centering == MODIL_NODE ? 1 : 0;  // nodes: one more value per axis
   for (int k = 0; k < P.ndim; ++k) {
     const int a = 3 - P.ndim + k;
-    p.n[a] = P.dims[k];
+    p.n[a] = P.dims[k] + extra;
     p.h[a] = P.lengths[k] / P.dims[k];
   }
   p.V = 1.0;
@@ -781,7 +822,10 @@ static hipError_t launch_fine_t(modil_ctx *c, const void *u, void *g, bool want_
   const modil_problem &P = c->prob;
   switch (P.op) {
     case MODIL_OP_POISSON:
-      fine_kernel<OpPoisson, T><<<grid, kBlock, 0, c->stream>>>(A);
+      if (P.centering == MODIL_NODE)
+        fine_kernel<OpPoissonNode, T><<<grid, kBlock, 0, c->stream>>>(A);
+      else
+        fine_kernel<OpPoisson, T><<<grid, kBlock, 0, c->stream>>>(A);
       break;
     case MODIL_OP_BURGERS:
       fine_kernel<OpBurgers, T><<<grid, kBlock, 0, c->stream>>>(A);
@@ -854,8 +898,12 @@ hipError_t launch_metric(modil_ctx *c, const double *terms, double *r) {
   const modil_problem &P = c->prob;
   double V = 1.0;
   for (int k = 0; k < P.ndim; ++k) V *= P.lengths[k] / P.dims[k];
-  const double scale =
-      V / (P.w_pde * (double)op_pde_equations(P) * (double)c->lay.fine_cells);
+  double rows = (double)c->lay.fine_cells;  // points carrying the PDE equations
+  if (P.centering == MODIL_NODE) {
+    rows = 1.0;
+    for (int k = 0; k < P.ndim; ++k) rows *= P.dims[k] - 1;  // interior nodes
+  }
+  const double scale = V / (P.w_pde * (double)op_pde_equations(P) * rows);
   metric_kernel<<<(P.batch + 63) / 64, 64, 0, c->stream>>>(terms, r, P.batch, scale);
   return hipGetLastError();
 }

@@ -64,4 +64,27 @@ __device__ inline void restrict_taps6(int J, int n, int (&idx)[6], T (&w)[6]) {
   w[5] = s + 3 < 2 * n - 1 ? t_entry<T>(2 * n - 1, J, n) : T(0);
 }
 
+// Node-based T (Section 2.2): n + 1 coarse nodes -> 2n + 1 fine nodes; even
+// fine nodes copy the coincident coarse node, odd ones take the mean of the
+// two neighbours.  Fine node i of 2n + 1:
+template <typename T>
+__device__ inline void prolong_taps_node(int i, int (&idx)[2], T (&w)[2]) {
+  const int J = i >> 1;
+  if (i & 1) {
+    idx[0] = J; w[0] = T(0.5); idx[1] = J + 1; w[1] = T(0.5);
+  } else {
+    idx[0] = J; w[0] = T(1); idx[1] = J; w[1] = T(0);
+  }
+}
+
+// Column J of the node-based T (coarse node J of n + 1): fine nodes 2J - 1,
+// 2J, 2J + 1 with weights 1/2, 1, 1/2, clamped to the grid (weight 0 outside).
+template <typename T>
+__device__ inline void restrict_taps_node(int J, int n_fine_nodes, int (&idx)[3], T (&w)[3]) {
+  idx[1] = 2 * J; w[1] = T(1);
+  idx[0] = 2 * J - 1 >= 0 ? 2 * J - 1 : 0; w[0] = 2 * J - 1 >= 0 ? T(0.5) : T(0);
+  idx[2] = 2 * J + 1 < n_fine_nodes ? 2 * J + 1 : n_fine_nodes - 1;
+  w[2] = 2 * J + 1 < n_fine_nodes ? T(0.5) : T(0);
+}
+
 }  // namespace modil

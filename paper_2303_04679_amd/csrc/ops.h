@@ -50,6 +50,7 @@ __device__ inline T sgn0(T x) {  // sign with sgn(0) = 0
 // ------------------------------------------------------------------ Poisson
 struct OpPoisson {
   static constexpr int NF = 1, NE = 1;
+  static constexpr bool kForcePdeOnly = false;
   __device__ static bool needs_nb(int) { return true; }
   __device__ static GhostRule ghost(const OpParams &, int, int, int) {
     return GhostRule{0.0, -2.0, 1.0 / 3.0};
@@ -78,10 +79,62 @@ struct OpPoisson {
   }
 };
 
+// Node-based Poisson (Section 3.1): unknowns at every node, boundary nodes
+// included.  Interior nodes carry the finite-difference Laplacian (its
+// neighbours are unknowns, no ghosts); a boundary node carries the term of the
+// boundary integral of u^2, weight w_bc h^(d-1) (uniform grids).  The forcing
+// enters the interior rows only.
+struct OpPoissonNode {
+  static constexpr int NF = 1, NE = 1;
+  static constexpr bool kForcePdeOnly = true;
+  __device__ static bool needs_nb(int) { return true; }
+  __device__ static GhostRule ghost(const OpParams &, int, int, int) {
+    return GhostRule{0.0, 0.0, 0.0};  // never used by an equation
+  }
+  __device__ static bool on_boundary(const OpParams &p, const int *j) {
+    bool b = false;
+    for (int a = 3 - p.ndim; a < 3; ++a) b |= j[a] == 0 || j[a] == p.n[a] - 1;
+    return b;
+  }
+  template <typename T>
+  __device__ static void eval(const OpParams &p, const int *j, int, const T (&U)[NF][7], T, T *r,
+                              T *wv, int *term) {
+    if (on_boundary(p, j)) {
+      r[0] = U[0][S_C];
+      wv[0] = T(p.w_bc * pow(p.V, double(p.ndim - 1) / double(p.ndim)));
+      term[0] = MODIL_TERM_BC;
+      return;
+    }
+    T acc = 0;
+    for (int a = 3 - p.ndim; a < 3; ++a) {
+      T ih2 = T(1.0 / (p.h[a] * p.h[a]));
+      acc += (U[0][slot_p(a)] - T(2) * U[0][S_C] + U[0][slot_m(a)]) * ih2;
+    }
+    r[0] = acc;
+    wv[0] = T(p.w_pde * p.V);
+    term[0] = MODIL_TERM_PDE;
+  }
+  template <typename T>
+  __device__ static void vjp(const OpParams &p, const int *j, int, const T (&)[NF][7], T,
+                             const T *a, T (&s)[NF][7]) {
+    if (on_boundary(p, j)) {
+      s[0][S_C] += a[0];
+      return;
+    }
+    for (int ax = 3 - p.ndim; ax < 3; ++ax) {
+      T ih2 = T(1.0 / (p.h[ax] * p.h[ax]));
+      s[0][slot_p(ax)] += a[0] * ih2;
+      s[0][slot_m(ax)] += a[0] * ih2;
+      s[0][S_C] -= T(2) * a[0] * ih2;
+    }
+  }
+};
+
 // ------------------------------------------------------------------ Burgers
 // grid axes: 1 = t (rows), 2 = x
 struct OpBurgers {
   static constexpr int NF = 1, NE = 3;
+  static constexpr bool kForcePdeOnly = false;
   __device__ static bool needs_nb(int) { return true; }
   __device__ static GhostRule ghost(const OpParams &, int, int, int) {
     return GhostRule{0.0, 0.0, 0.0};  // no equation reaches outside the grid
@@ -139,6 +192,7 @@ struct OpBurgers {
 // grid axes: 1 = t, 2 = x; field 0 = u [t][x], field 1 = q [x]
 struct OpHeat {
   static constexpr int NF = 2, NE = 3;
+  static constexpr bool kForcePdeOnly = false;
   __device__ static bool needs_nb(int) { return true; }
   __device__ static GhostRule ghost(const OpParams &, int, int, int) {
     return GhostRule{0.0, 0.0, 0.0};  // no equation reaches outside the grid
@@ -362,6 +416,7 @@ __host__ __device__ inline GhostRule ns_ghost(const OpParams &p, int f, int axis
 // CHI: 0 no body, 1 fixed chi array, 2 unknown chihat field.
 template <int D, int CHI>
 struct OpNS {
+  static constexpr bool kForcePdeOnly = false;
   static constexpr int NF = D + 1 + (CHI == 2 ? 1 : 0);
   static constexpr int NE = D + 1;
   static constexpr int P = D;  // pressure field index

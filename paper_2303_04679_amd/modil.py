@@ -41,6 +41,7 @@ class ProblemSpec:
     w_pde: float = 1.0
     w_reg: float = 0.0
     w_bc: float = 0.0
+    centering: str = "cell"   # "cell", or "node" (Poisson)
 
     @property
     def torch_dtype(self):
@@ -58,9 +59,10 @@ class ProblemSpec:
 
     @property
     def fine_cells(self):
+        """Values of one fine field (nodes for node-based grids)."""
         n = 1
         for d in self.dims:
-            n *= int(d)
+            n *= int(d) + (1 if self.centering == "node" else 0)
         return n
 
     def to_c(self):
@@ -70,7 +72,7 @@ class ProblemSpec:
             p.dims[a] = int(n)
             p.lengths[a] = float(x)
         p.n_levels = int(self.n_levels)
-        p.centering = L.CELL
+        p.centering = L.NODE if self.centering == "node" else L.CELL
         p.dtype = DTYPES[self.dtype][0]
         p.op = OPS[self.op]
         p.flags = L.FLAG_CHI_FIXED if self.chi_fixed else 0

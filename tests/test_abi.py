@@ -77,8 +77,17 @@ def test_validation_errors(kw, status):
     assert L.lib().modil_last_error(None)
 
 
-def test_node_centering_rejected():
-    p = ProblemSpec("poisson", (16,), (1.0,), 2).to_c()
+def test_node_centering_only_for_poisson():
+    p = ProblemSpec("cavity", (16, 16), (1.0, 1.0), 2).to_c()
     p.centering = L.NODE
     out = L.PackLayout()
     assert L.lib().modil_layout(ctypes.byref(p), ctypes.byref(out)) == L.ERR_DTYPE
+
+
+def test_node_layout():
+    """Node-based Poisson: (dims >> l) + 1 values per axis on level l."""
+    lay = layout(ProblemSpec("poisson", (32, 16), (1.0, 1.0), 3, centering="node"))
+    dims = [tuple(lay.field_dims[l][0])[1:] for l in range(3)]
+    assert dims == [(33, 17), (17, 9), (9, 5)]
+    assert lay.fine_cells == 33 * 17
+    assert lay.total == 33 * 17 + 17 * 9 + 9 * 5

@@ -18,7 +18,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _shapes(spec):
-    return ops.level_shapes(spec.op, spec.dims, spec.n_levels)
+    return ops.level_shapes(spec.op, spec.dims, spec.n_levels, spec.centering)
 
 
 def _unflat(x, shapes):
@@ -47,7 +47,7 @@ def _oracle_fg(spec):
 
 
 PARITY = [("poisson", (32, 48), 4), ("burgers", (24, 40), 3), ("heat", (40, 72), 3),
-          ("ns3d", (8, 16, 8), 3), ("cavity", (32, 48), 4)]
+          ("ns3d", (8, 16, 8), 3), ("cavity", (32, 48), 4), ("poisson_node", (32, 48), 4)]
 
 
 @pytest.mark.parametrize("op,dims,L", PARITY)

@@ -31,6 +31,9 @@ CASES = [
     ("ns3d", (16, 16, 24), 3),
     ("ns3d_fixed", (8, 16, 24), 3),
     ("cavity", (32, 48), 4),
+    ("poisson_node", (64,), 4),
+    ("poisson_node", (16, 24), 3),
+    ("poisson_node", (8, 16, 8), 2),
 ]
 
 
@@ -60,7 +63,8 @@ def test_loss_grad(op, dims, L, dtype):
 
 
 @pytest.mark.parametrize("op,dims,L", [("poisson", (48, 32), 4), ("heat", (32, 64), 4),
-                                       ("ns3d", (8, 16, 8), 3)])
+                                       ("ns3d", (8, 16, 8), 3), ("poisson_node", (48, 32), 4),
+                                       ("poisson_node", (16, 8, 16), 3)])
 def test_prolong_and_restrict(op, dims, L):
     need_gpu()
     spec = case(op, dims, L, seed=1)
@@ -71,7 +75,7 @@ def test_prolong_and_restrict(op, dims, L):
     torch.cuda.synchronize()
     for f, name in enumerate(spec.fields):
         axes = ops.field_axes(spec.op, name, spec.ndim)
-        ref = mg.decompose_horner([torch.tensor(r[f]) for r in lv], axes).numpy()
+        ref = mg.decompose_horner([torch.tensor(r[f]) for r in lv], axes, spec.centering).numpy()
         got = ctx.fine_views(fine)[f].cpu().numpy()
         assert rel(got, ref) <= 1e-14
     g = torch.randn(fine.numel(), dtype=torch.float64, device="cuda")
@@ -80,7 +84,8 @@ def test_prolong_and_restrict(op, dims, L):
     gl = levels_of(ctx, pk)
     for f, name in enumerate(spec.fields):
         axes = ops.field_axes(spec.op, name, spec.ndim)
-        ref = mg.decompose_transpose(torch.tensor(ctx.fine_views(g)[f].cpu().numpy()), L, axes)
+        ref = mg.decompose_transpose(torch.tensor(ctx.fine_views(g)[f].cpu().numpy()), L, axes,
+                                     spec.centering)
         for li in range(L):
             assert rel(gl[li][f], ref[li].numpy()) <= 1e-14
 
@@ -109,7 +114,8 @@ def test_adam(dtype):
 
 
 @pytest.mark.parametrize("op,dims,L", [("burgers", (32, 32), 4), ("heat", (32, 32), 4),
-                                       ("ns3d", (8, 8, 16), 3), ("cavity", (32, 32), 4)])
+                                       ("ns3d", (8, 8, 16), 3), ("cavity", (32, 32), 4),
+                                       ("poisson_node", (32, 32), 4)])
 def test_step_sequence_f64(op, dims, L):
     """Three modil_step calls (ping-pong theta) follow the oracle's loss, gradient and Adam."""
     need_gpu()

@@ -139,6 +139,7 @@ def test_restrict_f32_matches_oracle():
 
 
 @pytest.mark.parametrize("op,dims,L,batch", [("poisson", (200,), 4, 1), ("heat", (64, 32), 4, 2),
+                                             ("poisson_node", (32, 32), 4, 2),
                                              ("cavity", (64, 64), 4, 3), ("ns3d", (32, 32, 32), 4, 1),
                                              ("burgers", (64, 64), 5, 1)])
 def test_lds_tail_equals_per_level_launches(op, dims, L, batch):
