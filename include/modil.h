@@ -119,9 +119,10 @@ extern "C" {
  * per axis and a field holds (dims[a] >> l) + 1 nodes per axis on level l,
  * boundary nodes included; T is the node-based interpolation of Section 2.2
  * (even fine nodes copy the coarse node, odd ones average two).  Interior
- * nodes carry the finite-difference Laplacian (weight w_pde h^d); every
- * boundary node carries the term w_bc h^(d-1) u^2 of the boundary integral
- * of u^2 (grids with equal h on every axis).  Forcing arrays and
+ * nodes carry the finite-difference Laplacian (weight w_pde h^d).  The zero
+ * Dirichlet condition is imposed on the boundary nodes directly: they carry no
+ * equation, enter their neighbours' stencils as zero whatever the prolonged
+ * field holds there, and get a zero gradient.  Forcing arrays and
  * measurement indices address nodes; the forcing enters interior rows only. */
 typedef struct {
   int32_t ndim;

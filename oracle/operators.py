@@ -177,8 +177,11 @@ def _shift(xp, axis, s):
 # ------------------------------------------------------------------ residuals
 def poisson_node_residual(spec, u):
     """Node-based Poisson (Section 3.1): the finite-difference Laplacian minus
-    the forcing at the interior nodes; the Dirichlet condition is the
-    boundary-integral term of the loss (poisson_node_boundary)."""
+    the forcing at the interior nodes.  The zero Dirichlet condition is imposed
+    on the boundary nodes directly: the fine field's boundary values are
+    replaced by zero before the stencil is applied, so they carry no unknown
+    and the boundary integral of u^2 in the loss vanishes."""
+    u = u * poisson_node_interior(u.shape)
     inner = tuple(slice(1, -1) for _ in range(u.dim()))
     f = spec.forcing.get(0)
     R = torch.zeros_like(u[inner]) if f is None else -torch.as_tensor(f, dtype=DT)[inner]
@@ -189,16 +192,16 @@ def poisson_node_residual(spec, u):
     return [R]
 
 
-def poisson_node_boundary(u):
-    """Values at the boundary nodes (every node with an index 0 or N on some axis)."""
-    mask = torch.zeros(u.shape, dtype=torch.bool)
-    for a in range(u.dim()):
-        idx = [slice(None)] * u.dim()
+def poisson_node_interior(shape):
+    """1 at the interior nodes, 0 at the boundary nodes (index 0 or N on some axis)."""
+    m = torch.ones(shape, dtype=DT)
+    for a in range(len(shape)):
+        idx = [slice(None)] * len(shape)
         idx[a] = 0
-        mask[tuple(idx)] = True
+        m[tuple(idx)] = 0.0
         idx[a] = -1
-        mask[tuple(idx)] = True
-    return u[mask]
+        m[tuple(idx)] = 0.0
+    return m
 
 
 def poisson_residual(spec, u):
@@ -430,11 +433,6 @@ def loss_terms(spec, fine):
     if spec.op == "heat":
         left, right = heat_boundary(spec, fine[0])
         terms["bc"] = W["bc"] * spec.h[0] * ((left * left).sum() + (right * right).sum())
-    if spec.op == "poisson" and spec.centering == "node":
-        # the boundary integral of u^2, each boundary node with the surface
-        # element h^(d-1) of a uniform grid
-        ub = poisson_node_boundary(fine[0])
-        terms["bc"] = W["bc"] * V ** ((spec.ndim - 1) / spec.ndim) * (ub * ub).sum()
     for fi, term, idx, vals, wt in spec.meas:
         x = fine[fi].reshape(-1)[torch.as_tensor(idx, dtype=torch.long)]
         d = x - torch.as_tensor(vals, dtype=DT)

@@ -79,11 +79,11 @@ struct OpPoisson {
   }
 };
 
-// Node-based Poisson (Section 3.1): unknowns at every node, boundary nodes
-// included.  Interior nodes carry the finite-difference Laplacian (its
-// neighbours are unknowns, no ghosts); a boundary node carries the term of the
-// boundary integral of u^2, weight w_bc h^(d-1) (uniform grids).  The forcing
-// enters the interior rows only.
+// Node-based Poisson (Section 3.1): values at the nodes; the zero Dirichlet
+// condition is imposed on the boundary nodes directly, so a boundary node
+// carries no equation and enters its interior neighbours' stencils as zero
+// (whatever the prolonged field holds there), and the gradient there is zero.
+// Interior nodes carry the finite-difference Laplacian minus the forcing.
 struct OpPoissonNode {
   static constexpr int NF = 1, NE = 1;
   static constexpr bool kForcePdeOnly = true;
@@ -99,32 +99,30 @@ struct OpPoissonNode {
   template <typename T>
   __device__ static void eval(const OpParams &p, const int *j, int, const T (&U)[NF][7], T, T *r,
                               T *wv, int *term) {
+    term[0] = MODIL_TERM_PDE;
     if (on_boundary(p, j)) {
-      r[0] = U[0][S_C];
-      wv[0] = T(p.w_bc * pow(p.V, double(p.ndim - 1) / double(p.ndim)));
-      term[0] = MODIL_TERM_BC;
+      r[0] = T(0);
+      wv[0] = T(0);
       return;
     }
     T acc = 0;
     for (int a = 3 - p.ndim; a < 3; ++a) {
-      T ih2 = T(1.0 / (p.h[a] * p.h[a]));
-      acc += (U[0][slot_p(a)] - T(2) * U[0][S_C] + U[0][slot_m(a)]) * ih2;
+      const T ih2 = T(1.0 / (p.h[a] * p.h[a]));
+      const T um = j[a] - 1 == 0 ? T(0) : U[0][slot_m(a)];
+      const T up = j[a] + 1 == p.n[a] - 1 ? T(0) : U[0][slot_p(a)];
+      acc += (up - T(2) * U[0][S_C] + um) * ih2;
     }
     r[0] = acc;
     wv[0] = T(p.w_pde * p.V);
-    term[0] = MODIL_TERM_PDE;
   }
   template <typename T>
   __device__ static void vjp(const OpParams &p, const int *j, int, const T (&)[NF][7], T,
                              const T *a, T (&s)[NF][7]) {
-    if (on_boundary(p, j)) {
-      s[0][S_C] += a[0];
-      return;
-    }
+    if (on_boundary(p, j)) return;
     for (int ax = 3 - p.ndim; ax < 3; ++ax) {
-      T ih2 = T(1.0 / (p.h[ax] * p.h[ax]));
-      s[0][slot_p(ax)] += a[0] * ih2;
-      s[0][slot_m(ax)] += a[0] * ih2;
+      const T ih2 = T(1.0 / (p.h[ax] * p.h[ax]));
+      if (j[ax] + 1 != p.n[ax] - 1) s[0][slot_p(ax)] += a[0] * ih2;
+      if (j[ax] - 1 != 0) s[0][slot_m(ax)] += a[0] * ih2;
       s[0][S_C] -= T(2) * a[0] * ih2;
     }
   }

@@ -345,17 +345,22 @@ def test_node_poisson_exact_for_product_of_quadratics(d):
     assert terms["pde"] < 1e-26 and terms["bc"] < 1e-30, terms
 
 
-@pytest.mark.parametrize("d,expected", [(1, 2.0), (2, 4.0), (3, 6.0 + 2.0 / 64)])
-def test_node_boundary_term_is_the_boundary_measure(d, expected):
-    """u = 1: the boundary term is h^(d-1) times the number of boundary nodes,
-    i.e. the measure of the boundary of [0,1]^d (2 points, perimeter 4, area 6
-    plus the doubly counted edges 2 / N^2 for N = 8)."""
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_node_boundary_values_are_imposed(d):
+    """The boundary nodes carry the Dirichlet value itself: the loss does not
+    depend on the fine field there, and its gradient there is zero."""
     n = 8
+    rng = np.random.default_rng(d)
     spec = ops.Spec("poisson", (n,) * d, (1.0,) * d, 1, weights={"pde": 1.0, "bc": 1.0},
-                    centering="node")
-    terms = ops.loss_value(spec, [[np.ones((n + 1,) * d)]])
-    assert abs(terms["bc"] - expected) < 1e-12
-    assert terms["pde"] == 0.0
+                    centering="node", forcing={0: rng.standard_normal((n + 1,) * d)})
+    u = rng.standard_normal((n + 1,) * d)
+    mask = ops.poisson_node_interior(u.shape).numpy()
+    t1 = ops.loss_value(spec, [[u]])
+    t2 = ops.loss_value(spec, [[u * mask + 7.0 * (1 - mask)]])
+    assert t1 == t2
+    _, g = ops.loss_and_grad(spec, [[u]])
+    assert np.all(g[0][0][mask == 0] == 0.0)
+    assert np.linalg.norm(g[0][0]) > 0
 
 
 def test_node_level_shapes():
@@ -393,4 +398,5 @@ def test_node_lbfgs_converges_fast_in_1d():
         if it.step().status == 2:
             break
     fine = ops.fine_fields(spec, [[torch.as_tensor(a[0])] for a in split(it.x)])[0].numpy()
+    fine = fine * ops.poisson_node_interior(fine.shape).numpy()  # boundary values imposed
     assert np.max(np.abs(fine - u_ref)) < 1e-12, (k, np.max(np.abs(fine - u_ref)))
