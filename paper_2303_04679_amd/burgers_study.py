@@ -6,8 +6,8 @@
 Unit space-time domain (x, t) in [0, 1]^2, 64 x 64 cells, inviscid Burgers
 with the first-order upwind flux.  The reference solution comes from the
 initial condition u = (1 - cos 6 pi x) / 2 marched row by row with the same
-discrete residual (implicit time level, zero flux through the walls standing
-for the zero Dirichlet condition).  The reference values are imposed at 84
+discrete residual (implicit time level; the zero Dirichlet condition as a
+ghost value 0 beyond each wall, so the upwind flux lets the wave leave).  The reference values are imposed at 84
 points spaced evenly along the edges of a centred square (the paper gives the
 number of points, not the rectangle; three sizes are run: sides 0.95, 0.75 and
 1/3 of the domain), with weight 1/84 each; the loss has no smoothing term.  A
@@ -39,20 +39,26 @@ def reference(n, x):
         prev = rows[-1]
         u = prev.copy()
         for _ in range(50):  # Newton on r(u) = (u - prev)/dt + (F_{i+1/2} - F_{i-1/2})/dx
-            a, b = u[:-1], u[1:]
-            F = upwind_flux(a, b)
-            flux = np.concatenate([[0.0], F, [0.0]])
+            # faces -1/2 .. n-1/2; the zero Dirichlet condition as a ghost value 0
+            # outside each wall, so the wall faces carry the upwind flux
+            ue = np.concatenate([[0.0], u, [0.0]])
+            a, b = ue[:-1], ue[1:]
+            flux = upwind_flux(a, b)
             r = (u - prev) / dt + (flux[1:] - flux[:-1]) / dx
             m = 0.5 * (a + b)
             s = np.sign(m)
             dFa = 0.5 * a - 0.25 * s * (b - a) + 0.5 * np.abs(m)
             dFb = 0.5 * b - 0.25 * s * (b - a) - 0.5 * np.abs(m)
             J = np.eye(n) / dt
-            for i in range(n - 1):  # face i + 1/2 between cells i and i + 1
-                J[i, i] += dFa[i] / dx
-                J[i, i + 1] += dFb[i] / dx
-                J[i + 1, i] -= dFa[i] / dx
-                J[i + 1, i + 1] -= dFb[i] / dx
+            for k in range(n + 1):  # face k - 1/2 between cells k - 1 and k
+                if k - 1 >= 0:
+                    J[k - 1, k - 1] += dFa[k] / dx
+                    if k < n:
+                        J[k - 1, k] += dFb[k] / dx
+                if k < n:
+                    if k - 1 >= 0:
+                        J[k, k - 1] -= dFa[k] / dx
+                    J[k, k] -= dFb[k] / dx
             du = np.linalg.solve(J, -r)
             u = u + du
             if np.max(np.abs(du)) < 1e-14:
