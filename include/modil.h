@@ -244,10 +244,11 @@ int modil_residual_metric(modil_ctx *ctx, const void *theta_pack, double *r);
  * exists (NS3D with measurements on velocity / pressure only); 0 selects the
  * generic stencil engine.  Both compute the same iteration.               */
 #define MODIL_OPT_FUSED 0
-/* MODIL_OPT_MARCH (default 1): restrict levels whose fields span every axis
- * they have with the marching kernel (each fine value loaded once per wave,
- * Adam fused); 0 selects the per-cell gather kernel.  Same results up to the
- * order of the sums.
+/* MODIL_OPT_MARCH (default 1): transfer levels whose fields span every axis
+ * they have with the lane-shuffle kernels -- the marching restriction (each
+ * fine value loaded once per wave, Adam fused) and the block prolongation
+ * (one coarse cell per thread writing its 2^d fine cells); 0 selects the
+ * per-cell kernels.  Same results up to the order of the sums.
  * MODIL_OPT_MARCH_TILE (default 0 = automatic): coarse rows and planes per
  * wave of the marching kernel as 16 * rows + planes; rows 2 or 4, planes 1, 2
  * or 4 (8 with 4 rows).  A tile that does not divide a level's grid leaves

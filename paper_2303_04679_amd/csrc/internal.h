@@ -209,6 +209,12 @@ hipError_t launch_restrict_chain(modil_ctx *c, void *g, int from_level, const vo
 template <typename T>
 bool launch_restrict_march(const Levels &G, int l, T *g, const AdamArgs<T> &A, bool adam, int tile,
                            hipStream_t s);
+// Horner step of level l by coarse-cell blocks (prolong_block.hip): theta and
+// dst are level-l bases, csrc the level-(l+1) base; false (nothing launched)
+// when the level's shape does not admit it.
+template <typename T>
+bool launch_prolong_block(const Levels &G, int l, const T *theta, const T *csrc, T *dst,
+                          hipStream_t s);
 hipError_t launch_adam(modil_ctx *c, const void *theta_in, void *theta_out, void *m, void *v,
                        const void *g, long n, const AdamHost &h);
 hipError_t launch_fine(modil_ctx *c, const void *u, void *g, bool want_grad);

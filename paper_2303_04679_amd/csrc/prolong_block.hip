@@ -1,0 +1,174 @@
+// Horner step by blocks: w_l = theta_l + T w_{l+1} for cell-based fields that
+// span every axis they have (Section 2.2: T is the tensor product of the 1-D
+// cell-based interpolation).
+//
+// A thread owns one coarse cell J and writes the 2 x 2 (x 2) fine cells it
+// covers.  Along each axis the two fine cells 2J, 2J+1 need the coarse cells
+// J-1, J, J+1 (interior: 1/4, 3/4 and 3/4, 1/4; the end cells extrapolate with
+// 5/4, -1/4).  Along x the neighbours come from the adjacent lanes by
+// shuffles, so a thread loads one value of each of the 3 (or 9) coarse rows
+// around it; theta and the result move as pairs along x.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace modil {
+
+template <typename T> struct PPair;
+template <> struct PPair<float> { using type = float2; };
+template <> struct PPair<double> { using type = double2; };
+
+struct ProlongPlan {
+  int W, wshift, groups, nseg;  // lanes per coarse row, rows per wave, 64-lane segments
+  long n_rows;                  // coarse rows over instances, fields and planes
+};
+
+// weights of coarse cells J-1, J, J+1 for the fine cells 2J (e = 0), 2J+1 (e = 1)
+template <typename T>
+__device__ inline void pair_weights(int J, int n, T (&w)[2][3]) {
+  if (J >= 1) { w[0][0] = T(0.25); w[0][1] = T(0.75); w[0][2] = T(0); }
+  else { w[0][0] = T(0); w[0][1] = T(1.25); w[0][2] = T(-0.25); }
+  if (J <= n - 2) { w[1][0] = T(0); w[1][1] = T(0.75); w[1][2] = T(0.25); }
+  else { w[1][0] = T(-0.25); w[1][1] = T(1.25); w[1][2] = T(0); }
+}
+
+template <typename T, bool SPANZ, bool SEG>
+__global__ __launch_bounds__(256) void prolong_block_kernel(Levels G, int l, const T *__restrict__ theta,
+                                                            const T *__restrict__ csrc,
+                                                            T *__restrict__ dst, ProlongPlan P) {
+  using P2 = typename PPair<T>::type;
+  const int lane = threadIdx.x & 63;
+  const long wave = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int W = P.W, grp = lane >> P.wshift, gl = lane & (W - 1);
+  long row = wave * P.groups + grp;  // coarse row index over (inst, f, cz, cy) and segments
+  const int seg = (int)(row % P.nseg);
+  row /= P.nseg;
+  const bool active = row < P.n_rows;  // whole row groups leave together
+  if (!active) row = 0;                // keep the addresses valid for the shuffles
+  const int nz = G.n[l][0][0], ny = G.n[l][0][1], nx = G.n[l][0][2];
+  const int cnz = G.n[l + 1][0][0], cny = G.n[l + 1][0][1], cnx = G.n[l + 1][0][2];
+  const int cy = (int)(row % cny);
+  long r2 = row / cny;
+  const int cz = SPANZ ? (int)(r2 % cnz) : 0;
+  r2 = SPANZ ? r2 / cnz : r2;
+  const int f = (int)(r2 % G.nf), inst = (int)(r2 / G.nf);
+  const int cx = seg * 64 + gl;
+
+  const T *cb = csrc + inst * G.stride[l + 1] + G.foff[l + 1][f];
+  const long fbase = (long)inst * G.stride[l] + G.foff[l][f];
+
+  T wx[2][3], wy[2][3], wz[2][3];
+  pair_weights(cx, cnx, wx);
+  pair_weights(cy, cny, wy);
+  if (SPANZ) pair_weights(cz, cnz, wz);
+  const int ym = cy > 0 ? cy - 1 : 0, yp = cy < cny - 1 ? cy + 1 : cny - 1;
+  const int zm = cz > 0 ? cz - 1 : 0, zp = cz < cnz - 1 ? cz + 1 : cnz - 1;
+  const int ys[3] = {ym, cy, yp}, zs[3] = {zm, cz, zp};
+  const int lo = (SEG && gl == 0 && cx > 0) ? cx - 1 : cx;
+  const int hi = (SEG && gl == W - 1 && cx < cnx - 1) ? cx + 1 : cx;
+
+  // x-interpolated coarse rows: X[dz][dy][e] for the fine x cells 2cx + e
+  constexpr int NZ = SPANZ ? 3 : 1;
+  T c[NZ][3], el[NZ][3], eh[NZ][3];
+#pragma unroll
+  for (int a = 0; a < NZ; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const T *r = cb + ((long)(SPANZ ? zs[a] : cz) * cny + ys[b]) * cnx;
+      c[a][b] = r[cx];
+      el[a][b] = SEG ? r[lo] : T(0);
+      eh[a][b] = SEG ? r[hi] : T(0);
+    }
+  T X[NZ][3][2];
+#pragma unroll
+  for (int a = 0; a < NZ; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      T left = __shfl_up(c[a][b], 1, W);
+      T right = __shfl_down(c[a][b], 1, W);
+      if (SEG && gl == 0) left = el[a][b];
+      if (SEG && gl == W - 1) right = eh[a][b];
+      if (cx == 0) left = c[a][b];          // weight 0 there; keep it finite
+      if (cx == cnx - 1) right = c[a][b];
+#pragma unroll
+      for (int e = 0; e < 2; ++e)
+        X[a][b][e] = wx[e][0] * left + wx[e][1] * c[a][b] + wx[e][2] * right;
+    }
+  if (!active) return;
+#pragma unroll
+  for (int ez = 0; ez < (SPANZ ? 2 : 1); ++ez)
+#pragma unroll
+    for (int ey = 0; ey < 2; ++ey) {
+      T v[2];
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        T acc = T(0);
+#pragma unroll
+        for (int a = 0; a < NZ; ++a) {
+          const T yv = wy[ey][0] * X[a][0][e] + wy[ey][1] * X[a][1][e] + wy[ey][2] * X[a][2][e];
+          acc += (SPANZ ? wz[ez][a] : T(1)) * yv;
+        }
+        v[e] = acc;
+      }
+      const int z = SPANZ ? 2 * cz + ez : cz, y = 2 * cy + ey;
+      const long o = fbase + ((long)z * ny + y) * nx + 2 * cx;
+      const P2 th = *reinterpret_cast<const P2 *>(theta + o);
+      P2 out;
+      out.x = th.x + v[0];
+      out.y = th.y + v[1];
+      *reinterpret_cast<P2 *>(dst + o) = out;
+    }
+  (void)nz;
+}
+
+// Launch the block Horner step of level l (w_l into dst; theta and dst are
+// level-l bases in the pack layout, csrc the level-(l+1) base) if the level
+// admits it; returns false (nothing launched) otherwise.
+template <typename T>
+bool launch_prolong_block(const Levels &G, int l, const T *theta, const T *csrc, T *dst,
+                          hipStream_t s) {
+  if (G.node || l + 1 >= G.L) return false;
+  const uintptr_t al = 2 * sizeof(T);
+  if (reinterpret_cast<uintptr_t>(theta) % al || reinterpret_cast<uintptr_t>(dst) % al)
+    return false;
+  for (int f = 1; f < G.nf; ++f)
+    for (int a = 0; a < 3; ++a)
+      if (G.n[l][f][a] != G.n[l][0][a] || G.n[l + 1][f][a] != G.n[l + 1][0][a]) return false;
+  const int nz = G.n[l][0][0], ny = G.n[l][0][1], nx = G.n[l][0][2];
+  const int cnz = G.n[l + 1][0][0], cny = G.n[l + 1][0][1], cnx = G.n[l + 1][0][2];
+  if (nx != 2 * cnx || ny != 2 * cny || cnx < 2 || cny < 2) return false;
+  const bool spanz = nz > 1;
+  if (spanz ? (nz != 2 * cnz || cnz < 2) : cnz != 1) return false;
+  ProlongPlan P{};
+  if (cnx % 64 == 0) {
+    P.W = 64;
+    P.nseg = cnx / 64;
+  } else if (cnx < 64 && (cnx & (cnx - 1)) == 0) {
+    P.W = cnx;
+    P.nseg = 1;
+  } else {
+    return false;
+  }
+  P.wshift = 0;
+  while ((1 << P.wshift) < P.W) ++P.wshift;
+  P.groups = 64 / P.W;
+  P.n_rows = (long)G.batch * G.nf * (spanz ? cnz : 1) * cny;
+  const long waves = (P.n_rows * P.nseg + P.groups - 1) / P.groups;
+  const unsigned blocks = (unsigned)((waves + 3) / 4);
+  const bool seg = P.nseg > 1;
+  if (spanz) {
+    if (seg) prolong_block_kernel<T, true, true><<<blocks, 256, 0, s>>>(G, l, theta, csrc, dst, P);
+    else prolong_block_kernel<T, true, false><<<blocks, 256, 0, s>>>(G, l, theta, csrc, dst, P);
+  } else {
+    if (seg) prolong_block_kernel<T, false, true><<<blocks, 256, 0, s>>>(G, l, theta, csrc, dst, P);
+    else prolong_block_kernel<T, false, false><<<blocks, 256, 0, s>>>(G, l, theta, csrc, dst, P);
+  }
+  return true;
+}
+
+template bool launch_prolong_block<float>(const Levels &, int, const float *, const float *, float *,
+                                          hipStream_t);
+template bool launch_prolong_block<double>(const Levels &, int, const double *, const double *,
+                                           double *, hipStream_t);
+
+}  // namespace modil

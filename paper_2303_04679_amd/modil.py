@@ -253,8 +253,9 @@ class Context:
         L.check(L.lib().modil_set_option(self.h, L.OPT_FUSED, 1 if enabled else 0), self.h)
 
     def set_march(self, enabled: bool):
-        """Restrict with the marching kernel where a level admits it (default) or
-        with the per-cell gather kernel."""
+        """Transfer levels with the lane-shuffle kernels (marching restriction,
+        block prolongation) where a level admits them (default), or with the
+        per-cell kernels."""
         L.check(L.lib().modil_set_option(self.h, L.OPT_MARCH, 1 if enabled else 0), self.h)
 
     def set_tail(self, enabled: bool):

@@ -163,3 +163,23 @@ def test_lds_tail_equals_per_level_launches(op, dims, L, batch):
         outs.append([x.cpu().numpy() for x in (fine, a, m, v, g)])
     for x, y in zip(*outs):
         assert rel(x, y) <= 1e-13
+
+
+@pytest.mark.parametrize("op,dims,L", SHAPES + [("poisson", (16, 8, 64), 3), ("heat", (64, 32), 3)])
+def test_block_prolongation_matches_oracle(op, dims, L):
+    """The block Horner step (one coarse cell per thread, x neighbours by
+    shuffles) against the oracle's decomposition and the per-cell kernel."""
+    need_gpu()
+    spec = case(op, dims, L, seed=36)
+    lv = random_levels(spec, 37)
+    ctx = context_of(spec, "f64")
+    theta = pack_of(ctx, [lv])
+    fine = ctx.prolong(theta)
+    ctx.set_march(False)
+    fine2 = ctx.prolong(theta)
+    torch.cuda.synchronize()
+    for f, name in enumerate(spec.fields):
+        axes = ops.field_axes(spec.op, name, spec.ndim)
+        ref = mg.decompose_horner([torch.tensor(r[f]) for r in lv], axes).numpy()
+        assert rel(ctx.fine_views(fine)[f].cpu().numpy(), ref) <= 1e-14
+    assert rel(fine.cpu().numpy(), fine2.cpu().numpy()) <= 1e-14
