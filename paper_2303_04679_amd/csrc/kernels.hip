@@ -553,17 +553,31 @@ __global__ __launch_bounds__(kBlock) void fine_kernel(FineArgs<T> A) {
 }
 
 // column sums of the x-only field's per-cell contributions (rows = t)
+// Column sums of the per-cell contributions of the x-only field: a block
+// takes 64 columns of one instance; 16 row groups sum every 16th row, then the
+// group sums are added in group order (fixed order: deterministic).
+constexpr int kColX = 64, kColY = 16;
+
 template <typename T>
-__global__ __launch_bounds__(kBlock) void colsum_kernel(const T *__restrict__ gq, T *__restrict__ g,
-                                                        long inst_stride, long foff, int nt, int nx,
-                                                        int batch) {
-  const long e = (long)blockIdx.x * kBlock + threadIdx.x;
-  if (e >= (long)batch * nx) return;
-  const int inst = (int)(e / nx), ix = (int)(e % nx);
-  const T *src = gq + (long)inst * nt * nx + ix;
+__global__ __launch_bounds__(kColX * kColY) void colsum_kernel(const T *__restrict__ gq,
+                                                               T *__restrict__ g, long inst_stride,
+                                                               long foff, int nt, int nx) {
+  __shared__ T sh[kColY][kColX];
+  const int inst = blockIdx.y;
+  const int ix = blockIdx.x * kColX + threadIdx.x;
   T acc = T(0);
-  for (int it = 0; it < nt; ++it) acc += src[(long)it * nx];
-  g[(long)inst * inst_stride + foff + ix] = acc;
+  if (ix < nx) {
+    const T *src = gq + (long)inst * nt * nx + ix;
+#pragma unroll 4
+    for (int it = threadIdx.y; it < nt; it += kColY) acc += src[(long)it * nx];
+  }
+  sh[threadIdx.y][threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.y == 0 && ix < nx) {
+    T s = T(0);
+    for (int k = 0; k < kColY; ++k) s += sh[k][threadIdx.x];
+    g[(long)inst * inst_stride + foff + ix] = s;
+  }
 }
 
 // measurement misfits; entries sorted by (instance, field, index, term)
@@ -861,15 +875,15 @@ hipError_t launch_colsum(modil_ctx *c, void *g_fine) {
     if (field_is_x_only(c->prob, f)) xf = f;
   if (xf < 0) return hipSuccess;
   const int nt = c->prob.dims[0], nx = c->prob.dims[1];
-  const long n = (long)c->prob.batch * nx;
+  const dim3 grid((nx + kColX - 1) / kColX, c->prob.batch), block(kColX, kColY);
   if (c->prob.dtype == MODIL_F64)
-    colsum_kernel<double><<<nblk(n), kBlock, 0, c->stream>>>(
+    colsum_kernel<double><<<grid, block, 0, c->stream>>>(
         (const double *)c->gq_buf, (double *)g_fine, c->lay.level_stride[0],
-        c->lay.field_offset[0][xf], nt, nx, c->prob.batch);
+        c->lay.field_offset[0][xf], nt, nx);
   else
-    colsum_kernel<float><<<nblk(n), kBlock, 0, c->stream>>>(
+    colsum_kernel<float><<<grid, block, 0, c->stream>>>(
         (const float *)c->gq_buf, (float *)g_fine, c->lay.level_stride[0],
-        c->lay.field_offset[0][xf], nt, nx, c->prob.batch);
+        c->lay.field_offset[0][xf], nt, nx);
   return hipGetLastError();
 }
 
