@@ -34,6 +34,7 @@ constexpr int NS_MAIN = NSO_X * NST_Y;  // threads on the full-width rows
 constexpr int NS_HALO = 4 * NST_Y;       // threads for the four halo columns
 constexpr int NS_THREADS = NS_MAIN + (NS_HALO + 63) / 64 * 64;  // whole waves
 constexpr int NS_XCD = 8;
+constexpr long kComputeUnits = 256;  // compute units of the chip (32 per XCD)
 constexpr int NF_MAX_COARSE = 5;  // unknown fields with a coarse hierarchy
 static_assert(NS_THREADS - NS_MAIN >= NS_HALO, "every halo-column position needs a thread");
 #ifndef NS_WAVES_PER_EU
@@ -439,10 +440,15 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
 // ------------------------------------------------------------------ host side
 void ns3d_tiles(const modil_problem &P, int &tz, int &nzt, int &ntx, int &nty, int &ox, int &oy) {
   const int nz = P.dims[0], ny = P.dims[1], nx = P.dims[2];
-  tz = nz >= 64 ? 16 : 8;
-  nzt = (nz + tz - 1) / tz;
   ntx = (nx + NSO_X - 1) / NSO_X;
   nty = (ny + NSO_Y - 1) / NSO_Y;
+  // z-chunk: the longest of 16, 8, 4, 2 planes that still gives every compute
+  // unit a block (one block fills a CU's LDS); a chunk marches 4 halo planes
+  // besides its own, so shorter chunks cost more per output plane
+  const long xy = (long)ntx * nty * P.batch;
+  tz = 16;
+  while (tz > 2 && xy * ((nz + tz - 1) / tz) < kComputeUnits) tz /= 2;
+  nzt = (nz + tz - 1) / tz;
   ox = NSO_X;
   oy = NSO_Y;
 }

@@ -14,7 +14,7 @@ import torch
 from oracle import adam as oadam
 from oracle import multigrid as mg
 from oracle import operators as ops
-from tests.gpu_helpers import (TOL, assert_levels, assert_terms, context_of, levels_of, need_gpu,
+from tests.gpu_helpers import (TERMS, TOL, assert_levels, assert_terms, context_of, levels_of, need_gpu,
                                pack_of, rel, rounded)
 from tests.oracle_cases import case, random_levels
 
@@ -257,6 +257,33 @@ def test_fused_channel_kernel(op, dims, L, dtype):
     pairs = list(zip(outs[0], outs[1]))[0 if dtype == "f64" else 1:]
     for a, b in pairs:
         assert_levels(levels_of(ctx, a), levels_of(ctx, b), 1e-12 if dtype == "f64" else 1e-5, "step")
+
+
+@pytest.mark.parametrize("batch", [4, 26, 52, 86])
+def test_fused_channel_zchunks(batch):
+    """z-chunk lengths 2, 4, 8 and 16: a batch of one-tile instances with 40
+    planes (the longer chunks end ragged).  The chunk is the longest that gives
+    every compute unit a block, so these batch sizes select the four lengths.
+    Every instance matches the generic engine; the first and last the oracle."""
+    need_gpu()
+    dims = (40, 12, 20)
+    print(f"\n[parity] fused z-chunks {dims} batch={batch}", flush=True)
+    specs = [case("ns3d", dims, 3, seed=300 + b) for b in range(batch)]
+    ctx = context_of(specs[0], "f64", batch=batch, specs=specs)
+    lvs = [_levels(s, 400 + b) for b, s in enumerate(specs)]
+    theta = pack_of(ctx, lvs)
+    tf, gf = ctx.loss_grad(theta)
+    ctx.set_fused(False)
+    tg, gg = ctx.loss_grad(theta)
+    torch.cuda.synchronize()
+    for b in range(batch):
+        assert_terms(tf[b].cpu().numpy(), {t: float(tg[b, k]) for k, t in enumerate(TERMS)},
+                     1e-12, ("generic", b))
+        assert_levels(levels_of(ctx, gf, b), levels_of(ctx, gg, b), 1e-12, ("generic", b))
+    for b in (0, batch - 1):
+        rt, rg = ops.loss_and_grad(specs[b], lvs[b])
+        assert_terms(tf[b].cpu().numpy(), rt, 1e-12, ("oracle", b))
+        assert_levels(levels_of(ctx, gf, b), rg, 1e-12, ("oracle", b))
 
 
 def test_fused_channel_batch():
