@@ -213,7 +213,7 @@ def main():
         tot, cnt = ctx.profile_read(k)
         kern[name] = {"total_ms": tot, "launches": cnt, "avg_ms": tot / max(cnt, 1)}
     ctx.profile(False)
-    fused = spec.op == "ns3d" and all(f < 4 for _, f, _, _, _, _ in wl.meas)
+    fused = ctx.fused_active()
     ab = alg_bytes(ctx, spec, fused)
     dom = max(CLASSES, key=lambda n: kern[n]["total_ms"])
     avg_s = kern[dom]["avg_ms"] * 1e-3
@@ -291,7 +291,7 @@ def main_lbfgs(args, wl, ctx, theta):
     ctx.profile(False)
     ctx.check()
     b = 4 if spec.dtype == "f32" else 8
-    fused = spec.op == "ns3d" and all(f < 4 for _, f, _, _, _, _ in wl.meas)
+    fused = ctx.fused_active()
     ab = alg_bytes(ctx, spec, fused, adam=False)
     evals = sum(i["evals"] for i in infos)
     dots, upd = lbfgs_vector_bytes(int(ctx.lay.total), b, infos, pairs0)

@@ -241,8 +241,9 @@ int modil_residual_metric(modil_ctx *ctx, const void *theta_pack, double *r);
 
 /* ---- options --------------------------------------------------------------
  * MODIL_OPT_FUSED (default 1): use the fused finest-level kernel where one
- * exists (NS3D with measurements on velocity / pressure only); 0 selects the
- * generic stencil engine.  Both compute the same iteration.               */
+ * exists (NS3D in FP32, one Reynolds number for the batch, measurements on
+ * velocity / pressure only); 0 selects the generic stencil engine.  Both
+ * compute the same iteration.                                             */
 #define MODIL_OPT_FUSED 0
 /* MODIL_OPT_MARCH (default 1): transfer levels whose fields span every axis
  * they have with the lane-shuffle kernels -- the marching restriction (each
@@ -261,6 +262,11 @@ int modil_residual_metric(modil_ctx *ctx, const void *theta_pack, double *r);
  * instance working in LDS; 0 launches one kernel per level instead.       */
 #define MODIL_OPT_TAIL 3
 int modil_set_option(modil_ctx *ctx, int32_t option, int64_t value);
+/* modil_fused_active: 1 if the next loss / gradient / step of this context
+ * runs the fused finest-level kernel (option on and the problem, its
+ * measurements and Reynolds numbers admit it), 0 if the generic engine, or a
+ * negative status for a NULL context.                                      */
+int modil_fused_active(const modil_ctx *ctx);
 
 /* ---- health and timing ---------------------------------------------------
  * modil_check: synchronises the stream; returns MODIL_ERR_NONFINITE if a

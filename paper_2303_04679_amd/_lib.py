@@ -122,6 +122,7 @@ _SIGS = {
     "modil_residual_metric": (_I, [_P, _P, _P]),
     "modil_check": (_I, [_P]),
     "modil_set_option": (_I, [_P, ctypes.c_int32, ctypes.c_int64]),
+    "modil_fused_active": (_I, [_P]),
     "modil_profile": (_I, [_P, ctypes.c_int32]),
     "modil_profile_read": (_I, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                 ctypes.POINTER(ctypes.c_int64)]),

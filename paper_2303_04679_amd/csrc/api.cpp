@@ -295,7 +295,8 @@ int upload_measurements(modil_ctx *c) {
 }
 
 bool use_fused(const modil_ctx *c) {
-  return c->fused_enabled && c->fused_ok && c->prob.op == MODIL_OP_NS3D;
+  return c->fused_enabled && c->fused_ok && c->prob.op == MODIL_OP_NS3D &&
+         c->prob.dtype == MODIL_F32 && ns3d_offsets_fit(c->prob);
 }
 
 // Loss terms at theta; with grad the gradient of every level; with adam
@@ -712,6 +713,11 @@ int modil_set_option(modil_ctx *c, int32_t option, int64_t value) {
     return MODIL_OK;
   }
   return fail(c, MODIL_ERR_INVALID_ARG, "unknown option");
+}
+
+int modil_fused_active(const modil_ctx *c) {
+  if (!c) return fail_global(MODIL_ERR_INVALID_ARG, "ctx is NULL");
+  return use_fused(c) ? 1 : 0;
 }
 
 int modil_check(modil_ctx *c) {

@@ -224,6 +224,8 @@ hipError_t launch_reduce(modil_ctx *c, double *terms, long n_a, long off_b, long
 hipError_t launch_ns3d_fused(modil_ctx *c, const void *theta, void *g, const AdamHost *adam,
                              void *th_out, void *m, void *v);
 void ns3d_tiles(const modil_problem &P, int &tz, int &nzt, int &ntx, int &nty, int &ox, int &oy);
+// the fused kernel addresses a plane's fields by 32-bit byte offsets
+bool ns3d_offsets_fit(const modil_problem &P);
 hipError_t launch_metric(modil_ctx *c, const double *terms, double *r);
 
 }  // namespace modil

@@ -14,12 +14,16 @@
 // halo rows on each side) and two more waves for the four halo columns.  Each
 // thread keeps its column's last four prolonged planes and three planes of
 // residual seeds in registers; the current planes of fields and seeds are
-// staged in LDS for the xy neighbours (in FP32 also each cell's derivatives,
-// from its seed pass to its gradient pass).  Seeds are formed for the owned cells
+// staged in LDS for the xy neighbours, and so is each cell's derivatives,
+// from its seed pass to its gradient pass.  Seeds are formed for the owned cells
 // plus a 1-cell halo, the gradient for the owned cells.  The coarse plane
 // interpolation is cached per column, so each coarse plane is read once per
 // two fine planes.  Blocks are mapped to tiles so that every XCD works on one
 // contiguous slab of z-chunks and neighbouring tiles share its L2.
+//
+// The kernel is built for FP32 fields (FP64 loss partials).  An FP64 build
+// needs more registers than the 768-thread block allows and spills heavily;
+// FP64 problems run on the generic engine.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -82,6 +86,21 @@ __device__ inline void coarse_xy(const T *cw, const int (&lx)[2], const T (&wx)[
   }
 }
 
+// Global accesses of the march: a base that is uniform over the block (an
+// array and instance) plus a 32-bit byte offset, the column's offset in its
+// field (per thread, fixed) plus the plane's (uniform, formed in the plane
+// loop).  Formed in the loop, the offset stays 32-bit and the access takes the
+// scalar-base + 32-bit-offset form: no 64-bit vector address arithmetic.
+// Offsets are never formed for planes before the grid (no wrap-around).
+template <typename T>
+__device__ inline T ld_at(const T *base, uint32_t byte_off) {
+  return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+template <typename T>
+__device__ inline void st_at(T *base, uint32_t byte_off, T v) {
+  *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off) = v;
+}
+
 // CHI: 1 fixed chi array, 2 unknown chihat (field 4)
 template <typename T, int CHI, bool ADAM>
 __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel(NS3DArgs<T> A) {
@@ -91,12 +110,12 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
   __shared__ T Al[2][4][NST_Y][NST_X];
   __shared__ T Dl[4][NST_Y][NST_X];
   __shared__ double red[NS_THREADS / 64][kTerms];
-  // In FP32 the derivatives and body terms of a cell (12 values) are kept from
-  // its seed pass for its gradient pass one plane later, instead of being
-  // formed again; in FP64 they do not fit in LDS beside the planes.
-  constexpr bool SAVE_L = sizeof(T) == 4;
+  static_assert(sizeof(T) == 4, "FP32 fields");
+  // the derivatives and body terms of a cell (12 values) are kept from its
+  // seed pass for its gradient pass one plane later, instead of being formed
+  // again
   constexpr int NLS = 12;
-  __shared__ T Ls[SAVE_L ? 2 : 1][SAVE_L ? NLS : 1][SAVE_L ? NS_THREADS : 1];
+  __shared__ T Ls[2][NLS][NS_THREADS];
   // two coarse planes (coarse plane K in slot K & 1): the one a fine plane
   // interpolates from and the next; the next one is loaded a plane ahead
   static_assert(NF_MAX_COARSE * NCT <= 2 * NS_THREADS, "two coarse values per thread");
@@ -137,6 +156,15 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
   const NSCoef<T> &K = A.K;
   const T wv = T(p.w_pde * p.V);
   const T *th_base = A.theta + inst * A.th_inst;
+  // byte offset of this column in field f of plane 0 from the instance's
+  // level-0 base (the host checks the largest offset used fits in 32 bits)
+  const uint32_t plane_b = (uint32_t)plane * (uint32_t)sizeof(T);
+  uint32_t fo[NS];
+  for (int f = 0; f < NS; ++f)
+    fo[f] = ((uint32_t)f * (uint32_t)A.fsize + (uint32_t)(in_xy ? col : 0)) * (uint32_t)sizeof(T);
+  // byte offset of plane z (uniform); planes before the grid map to plane 0
+  auto pofs = [&](int z) { return (uint32_t)max(z, 0) * plane_b; };
+  const T *chi_base = CHI == 1 ? A.chi + inst * A.fsize : nullptr;
 
   // xy interpolation taps of this column from level 1
   int jx[2] = {0, 0}, jy[2] = {0, 0};
@@ -158,17 +186,22 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
     return (z & 1) ? z / 2 : z / 2 - 1;
   };
   // each thread moves two values of a coarse plane window: global -> registers -> LDS
-  auto cload = [&](int Kc, T (&r)[2]) {
-    for (int u = 0; u < 2; ++u) {
-      const int e = tid + u * NS_THREADS;
-      r[u] = T(0);
-      if (e < NF * NCT) {
-        const int f = e / NCT, rem = e - f * NCT, j = rem / NCT_X, i = rem - j * NCT_X;
-        const int cy = cyb + j, cx = cxb + i;
-        if (cy >= 0 && cy < A.nc[1] && cx >= 0 && cx < A.nc[2])
-          r[u] = A.w1[inst * A.w1_inst + f * A.csize + (Kc * A.nc[1] + cy) * A.nc[2] + cx];
-      }
+  // the two window values this thread moves: byte offset within a coarse plane
+  uint32_t co[2] = {0u, 0u};
+  bool cin[2] = {false, false};
+  for (int u = 0; u < 2; ++u) {
+    const int e = tid + u * NS_THREADS;
+    if (e < NF * NCT) {
+      const int f = e / NCT, rem = e - f * NCT, j = rem / NCT_X, i = rem - j * NCT_X;
+      const int cy = cyb + j, cx = cxb + i;
+      cin[u] = cy >= 0 && cy < A.nc[1] && cx >= 0 && cx < A.nc[2];
+      if (cin[u])
+        co[u] = ((uint32_t)f * (uint32_t)A.csize + (uint32_t)(cy * A.nc[2] + cx)) * (uint32_t)sizeof(T);
     }
+  }
+  auto cload = [&](int Kc, T (&r)[2]) {
+    const T *cb = A.w1 + inst * A.w1_inst + Kc * A.nc[1] * A.nc[2];
+    for (int u = 0; u < 2; ++u) r[u] = cin[u] ? ld_at(cb, co[u]) : T(0);
   };
   auto cstore = [&](int Kc, const T (&r)[2]) {
     for (int u = 0; u < 2; ++u) {
@@ -207,9 +240,9 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
   T thn[NF], chin = T(0);
   for (int f = 0; f < NF; ++f) thn[f] = T(0);
   if (in_xy && z0 - 2 >= 0) {
-    const int cell = (z0 - 2) * plane + col;
-    for (int f = 0; f < NF; ++f) thn[f] = th_base[f * A.fsize + cell];
-    if (CHI == 1) chin = A.chi[inst * A.fsize + cell];
+    const uint32_t zb = pofs(z0 - 2);
+    for (int f = 0; f < NF; ++f) thn[f] = ld_at(th_base, fo[f] + zb);
+    if (CHI == 1) chin = ld_at(chi_base, fo[0] + zb);
   }
 
   for (int pz = z0 - 2; pz <= z1 + 1; ++pz) {
@@ -228,19 +261,19 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
     T th[NF], chi_pz = chin;
     for (int f = 0; f < NF; ++f) th[f] = thn[f];
     if (in_xy && pz + 1 >= 0 && pz + 1 < nz) {
-      const int cell = (pz + 1) * plane + col;
-      for (int f = 0; f < NF; ++f) thn[f] = th_base[f * A.fsize + cell];
-      if (CHI == 1) chin = A.chi[inst * A.fsize + cell];
+      const uint32_t zb = pofs(pz + 1);
+      for (int f = 0; f < NF; ++f) thn[f] = ld_at(th_base, fo[f] + zb);
+      if (CHI == 1) chin = ld_at(chi_base, fo[0] + zb);
     }
     T mq[NF], vq[NF], tq[NF];
     const int q = pz - 2, qb = q & 1;
     const bool gather = own_xy && q >= z0 && q < z1;
+    const uint32_t qofs = pofs(q);
     if (ADAM && gather) {
-      const int k0 = inst * A.th_inst + q * plane + col;
       for (int f = 0; f < NF; ++f) {
-        mq[f] = A.adam.m[k0 + f * A.fsize];
-        vq[f] = A.adam.v[k0 + f * A.fsize];
-        tq[f] = th_base[f * A.fsize + q * plane + col];
+        mq[f] = ld_at(A.adam.m + inst * A.th_inst, fo[f] + qofs);
+        vq[f] = ld_at(A.adam.v + inst * A.th_inst, fo[f] + qofs);
+        tq[f] = ld_at(th_base, fo[f] + qofs);
       }
     }
     // ---- 1. prolong plane pz of this column
@@ -296,18 +329,15 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
       }
       NSLocal<3, T> L;
       ns_local<3>(K, Us, L);
-      if (SAVE_L) {
-        for (int c = 0; c < 3; ++c) {
-          for (int k = 0; k < 3; ++k) Ls[sb][3 * c + k][tid] = L.du[c][k];
-          Ls[sb][9 + c][tid] = L.body[c];
-        }
+      for (int c = 0; c < 3; ++c) {
+        for (int k = 0; k < 3; ++k) Ls[sb][3 * c + k][tid] = L.du[c][k];
+        Ls[sb][9 + c][tid] = L.body[c];
       }
       const T uc[3] = {U2[0], U2[1], U2[2]};
       T r[4];
       ns_residual<3, true>(K, L, uc, U2[4], r);
-      const int cell = s * plane + col;
       for (int e = 0; e < 4; ++e) {
-        if (A.forcing[e]) r[e] -= A.forcing[e][inst * A.fsize + cell];
+        if (A.forcing[e]) r[e] -= ld_at(A.forcing[e] + inst * A.fsize, fo[0] + pofs(s));
         an[e] = T(2) * wv * r[e];
       }
       if (own_xy && s >= z0 && s < z1)
@@ -335,25 +365,11 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
 
     // ---- 4. gradient, and Adam, at plane q
     if (gather) {
+      // ns_centre_sens reads the derivatives and body terms only
       NSLocal<3, T> L;
-      if (SAVE_L) {
-        for (int c = 0; c < 3; ++c) {
-          for (int k = 0; k < 3; ++k) L.du[c][k] = Ls[qb][3 * c + k][tid];
-          L.body[c] = Ls[qb][9 + c][tid];
-        }
-      } else {
-        T Uq[4][7];
-        for (int f = 0; f < 4; ++f) {
-          const T c = U1[f];
-          Uq[f][S_C] = c;
-          Uq[f][S_ZM] = q > 0 ? U0[f] : GV(f, 0, 0, c);
-          Uq[f][S_ZP] = q < nz - 1 ? U2[f] : GV(f, 0, 1, c);
-          Uq[f][S_YM] = y > 0 ? Ul[qb][f][Y - 1][X] : GV(f, 1, 0, c);
-          Uq[f][S_YP] = y < ny - 1 ? Ul[qb][f][Y + 1][X] : GV(f, 1, 1, c);
-          Uq[f][S_XM] = x > 0 ? Ul[qb][f][Y][X - 1] : GV(f, 2, 0, c);
-          Uq[f][S_XP] = x < nx - 1 ? Ul[qb][f][Y][X + 1] : GV(f, 2, 1, c);
-        }
-        ns_local<3>(K, Uq, L);
+      for (int c = 0; c < 3; ++c) {
+        for (int k = 0; k < 3; ++k) L.du[c][k] = Ls[qb][3 * c + k][tid];
+        L.body[c] = Ls[qb][9 + c][tid];
       }
       const T uc[3] = {U1[0], U1[1], U1[2]};
       const T chic = U1[4];
@@ -396,17 +412,16 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
       NS_XY_NEIGHBOUR(x < nx - 1, 2, 1, 0, 1, -1)
 #undef NS_XY_NEIGHBOUR
       for (int f = 0; f < 4; ++f) g[f] += Dl[f][Y][X];
-      const int cell = q * plane + col;
-      const int base = inst * A.th_inst + cell;
+      const int base = inst * A.th_inst;
       for (int f = 0; f < NF; ++f) {
-        const int k = base + f * A.fsize;
-        A.g[k] = g[f];
+        st_at(A.g + base, fo[f] + qofs, g[f]);
         if (ADAM) {
           const T mm = A.adam.b1 * mq[f] + (T(1) - A.adam.b1) * g[f];
           const T vv = A.adam.b2 * vq[f] + (T(1) - A.adam.b2) * g[f] * g[f];
-          A.adam.m[k] = mm;
-          A.adam.v[k] = vv;
-          A.adam.th_out[k] = adam_theta(tq[f], mm, vv, A.adam.step, A.adam.isb2, A.adam.eps);
+          st_at(A.adam.m + base, fo[f] + qofs, mm);
+          st_at(A.adam.v + base, fo[f] + qofs, vv);
+          st_at(A.adam.th_out + base, fo[f] + qofs,
+                adam_theta(tq[f], mm, vv, A.adam.step, A.adam.isb2, A.adam.eps));
         }
       }
     }
@@ -451,6 +466,12 @@ void ns3d_tiles(const modil_problem &P, int &tz, int &nzt, int &ntx, int &nty, i
   nzt = (nz + tz - 1) / tz;
   ox = NSO_X;
   oy = NSO_Y;
+}
+
+bool ns3d_offsets_fit(const modil_problem &P) {
+  const unsigned long long cells = (unsigned long long)P.dims[0] * P.dims[1] * P.dims[2];
+  const unsigned long long ts = P.dtype == MODIL_F64 ? 8 : 4;
+  return 5ull * cells * ts < (1ull << 32);  // fields of level 0; level 1 is smaller
 }
 
 template <typename T>
@@ -517,10 +538,11 @@ static hipError_t fused_t(modil_ctx *c, const void *theta, void *g, const AdamHo
   return hipGetLastError();
 }
 
+// FP32 only: the problem's FP64 channel flow runs on the generic engine
 hipError_t launch_ns3d_fused(modil_ctx *c, const void *theta, void *g, const AdamHost *adam,
                              void *th_out, void *m, void *v) {
-  return c->prob.dtype == MODIL_F64 ? fused_t<double>(c, theta, g, adam, th_out, m, v)
-                                    : fused_t<float>(c, theta, g, adam, th_out, m, v);
+  if (c->prob.dtype != MODIL_F32) return hipErrorInvalidValue;
+  return fused_t<float>(c, theta, g, adam, th_out, m, v);
 }
 
 }  // namespace modil

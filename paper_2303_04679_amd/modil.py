@@ -252,6 +252,13 @@ class Context:
         """Use the fused finest-level kernel where one exists (default) or the generic engine."""
         L.check(L.lib().modil_set_option(self.h, L.OPT_FUSED, 1 if enabled else 0), self.h)
 
+    def fused_active(self) -> bool:
+        """True if the finest level runs the fused kernel (option on and the
+        problem admits it), False if the generic engine."""
+        r = L.lib().modil_fused_active(self.h)
+        L.check(min(r, 0), self.h)
+        return r == 1
+
     def set_march(self, enabled: bool):
         """Transfer levels with the lane-shuffle kernels (marching restriction,
         block prolongation) where a level admits them (default), or with the

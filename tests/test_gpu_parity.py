@@ -223,27 +223,31 @@ def test_theta_pingpong_required():
     assert ei.value.status == L.ERR_INVALID_ARG
 
 
-@pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("op,dims,L", [("ns3d", (24, 36, 60), 3), ("ns3d_fixed", (16, 28, 24), 3),
                                        ("ns3d", (64, 16, 32), 4), ("ns3d", (8, 8, 8), 1)])
-def test_fused_channel_kernel(op, dims, L, dtype):
-    """The fused channel-flow pass (ragged xy tiles, several z-chunks) matches the
-    oracle and the generic engine, for loss_grad and for the full step."""
+def test_fused_channel_kernel(op, dims, L):
+    """The fused channel-flow pass (FP32; ragged xy tiles, several z-chunks)
+    matches the oracle and the generic engine, for loss_grad and for the full
+    step."""
     need_gpu()
+    dtype = "f32"
     print(f"\n[parity] fused {op} {dims} L={L} {dtype}", flush=True)
     spec = case(op, dims, L, seed=13, with_forcing=True)
     lv = rounded(_levels(spec, 14), dtype)
     rterms, rgrad = ops.loss_and_grad(spec, lv)
     ctx = context_of(spec, dtype)
+    assert ctx.fused_active()
     theta = pack_of(ctx, [lv])
     tf, gf = ctx.loss_grad(theta)
     ctx.set_fused(False)
+    assert not ctx.fused_active()
     tg, gg = ctx.loss_grad(theta)
     torch.cuda.synchronize()
     tol = TOL[dtype]
     assert_terms(tf[0].cpu().numpy(), rterms, tol, "fused")
     assert_levels(levels_of(ctx, gf), rgrad, tol, "fused")
     assert_terms(tg[0].cpu().numpy(), rterms, tol, "generic")
+    assert_levels(levels_of(ctx, gf), levels_of(ctx, gg), tol, "fused vs generic")
     # full step: fused Adam on every level against the generic step
     outs = []
     for fused in (True, False):
@@ -254,9 +258,16 @@ def test_fused_channel_kernel(op, dims, L, dtype):
         outs.append((o, m, v))
     torch.cuda.synchronize()
     # in FP32 Adam's first steps are sign-like for near-zero gradients: compare m, v only
-    pairs = list(zip(outs[0], outs[1]))[0 if dtype == "f64" else 1:]
-    for a, b in pairs:
-        assert_levels(levels_of(ctx, a), levels_of(ctx, b), 1e-12 if dtype == "f64" else 1e-5, "step")
+    for a, b in list(zip(outs[0], outs[1]))[1:]:
+        assert_levels(levels_of(ctx, a), levels_of(ctx, b), tol, "step")
+
+
+def test_fused_channel_kernel_fp32_only():
+    """FP64 channel flow runs on the generic engine (the fused kernel is FP32)."""
+    need_gpu()
+    spec = case("ns3d", (16, 16, 16), 2, seed=3)
+    assert not context_of(spec, "f64").fused_active()
+    assert context_of(spec, "f32").fused_active()
 
 
 @pytest.mark.parametrize("batch", [4, 26, 52, 86])
@@ -264,37 +275,41 @@ def test_fused_channel_zchunks(batch):
     """z-chunk lengths 2, 4, 8 and 16: a batch of one-tile instances with 40
     planes (the longer chunks end ragged).  The chunk is the longest that gives
     every compute unit a block, so these batch sizes select the four lengths.
-    Every instance matches the generic engine; the first and last the oracle."""
+    Every instance matches the generic engine; the first and last the oracle
+    (FP32 inputs, promoted to FP64 for the oracle)."""
     need_gpu()
     dims = (40, 12, 20)
     print(f"\n[parity] fused z-chunks {dims} batch={batch}", flush=True)
     specs = [case("ns3d", dims, 3, seed=300 + b) for b in range(batch)]
-    ctx = context_of(specs[0], "f64", batch=batch, specs=specs)
-    lvs = [_levels(s, 400 + b) for b, s in enumerate(specs)]
+    ctx = context_of(specs[0], "f32", batch=batch, specs=specs)
+    assert ctx.fused_active()
+    lvs = [rounded(_levels(s, 400 + b), "f32") for b, s in enumerate(specs)]
     theta = pack_of(ctx, lvs)
     tf, gf = ctx.loss_grad(theta)
     ctx.set_fused(False)
     tg, gg = ctx.loss_grad(theta)
     torch.cuda.synchronize()
+    tol = TOL["f32"]
     for b in range(batch):
         assert_terms(tf[b].cpu().numpy(), {t: float(tg[b, k]) for k, t in enumerate(TERMS)},
-                     1e-12, ("generic", b))
-        assert_levels(levels_of(ctx, gf, b), levels_of(ctx, gg, b), 1e-12, ("generic", b))
+                     tol, ("generic", b))
+        assert_levels(levels_of(ctx, gf, b), levels_of(ctx, gg, b), tol, ("generic", b))
     for b in (0, batch - 1):
         rt, rg = ops.loss_and_grad(specs[b], lvs[b])
-        assert_terms(tf[b].cpu().numpy(), rt, 1e-12, ("oracle", b))
-        assert_levels(levels_of(ctx, gf, b), rg, 1e-12, ("oracle", b))
+        assert_terms(tf[b].cpu().numpy(), rt, tol, ("oracle", b))
+        assert_levels(levels_of(ctx, gf, b), rg, tol, ("oracle", b))
 
 
 def test_fused_channel_batch():
     need_gpu()
     specs = [case("ns3d", (16, 24, 32), 3, seed=40 + b) for b in range(2)]
-    ctx = context_of(specs[0], "f64", batch=2, specs=specs)
-    lvs = [_levels(s, 50 + b) for b, s in enumerate(specs)]
+    ctx = context_of(specs[0], "f32", batch=2, specs=specs)
+    assert ctx.fused_active()
+    lvs = [rounded(_levels(s, 50 + b), "f32") for b, s in enumerate(specs)]
     theta = pack_of(ctx, lvs)
     terms, grad = ctx.loss_grad(theta)
     torch.cuda.synchronize()
     for b, s in enumerate(specs):
         rt, rg = ops.loss_and_grad(s, lvs[b])
-        assert_terms(terms[b].cpu().numpy(), rt, 1e-12, b)
-        assert_levels(levels_of(ctx, grad, b), rg, 1e-12, b)
+        assert_terms(terms[b].cpu().numpy(), rt, TOL["f32"], b)
+        assert_levels(levels_of(ctx, grad, b), rg, TOL["f32"], b)
