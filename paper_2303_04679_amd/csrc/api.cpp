@@ -324,6 +324,7 @@ int evaluate(modil_ctx *c, const void *theta, void *grad, double *terms, const A
     return MODIL_OK;
   }
   const void *u = theta;
+  bool summed = false;  // the data kernel summed the partials
   if (c->prob.n_levels > 1) {
     Timed t(c, 1);
     HIP_OR_RETURN(c, launch_horner(c, theta, nullptr, false), "prolong");
@@ -336,14 +337,14 @@ int evaluate(modil_ctx *c, const void *theta, void *grad, double *terms, const A
   {
     Timed t(c, 4);
     if (want) HIP_OR_RETURN(c, launch_colsum(c, grad), "column sum");
-    HIP_OR_RETURN(c, launch_data(c, u, grad, want), "data kernel");
+    HIP_OR_RETURN(c, launch_data(c, u, grad, want, terms, summed), "data kernel");
   }
   if (want) {
     Timed t(c, 2);
     HIP_OR_RETURN(c, launch_restrict_chain(c, grad, 0, nullptr, nullptr, nullptr, nullptr, nullptr),
                   "restrict");
   }
-  {
+  if (!summed) {
     Timed t(c, 4);
     const long generic_blocks = (long)((c->lay.fine_cells + kBlock - 1) / kBlock);
     HIP_OR_RETURN(c, launch_reduce(c, terms, generic_blocks, c->n_fine_blocks, c->n_data_blocks),

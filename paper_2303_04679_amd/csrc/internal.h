@@ -69,6 +69,36 @@ __device__ inline float adam_theta<float>(float th, float m, float v, float step
   return th - step * m * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(v) * isb2 + eps);
 }
 
+// Fixed-order final sum of one instance's FP64 loss partials: slots [0, n_a)
+// and [off_b, off_b + n_b) of src.  The first kBlock threads of the calling
+// block add kBlock-strided slots, then each wave's lanes by shuffles, then the
+// waves in order, so every caller sums in the same order.  Writes the kTerms
+// sums to terms and raises flag on a non-finite one.  Every thread of the
+// block calls it (it holds a barrier); the block has at least kBlock threads.
+__device__ inline void final_terms(const double *src, long n_a, long off_b, long n_b,
+                                   double *terms, int32_t *flag) {
+  __shared__ double sh[kBlock / 64][kTerms];
+  const int tid = threadIdx.x;
+  double t[kTerms];
+  for (int k = 0; k < kTerms; ++k) t[k] = 0.0;
+  if (tid < kBlock)
+    for (long b = tid; b < n_a + n_b; b += kBlock) {
+      const long slot = b < n_a ? b : off_b + (b - n_a);
+      for (int k = 0; k < kTerms; ++k) t[k] += src[slot * kTerms + k];
+    }
+  for (int k = 0; k < kTerms; ++k)
+    for (int off = 32; off >= 1; off >>= 1) t[k] += __shfl_down(t[k], off, 64);
+  if (tid < kBlock && (tid & 63) == 0)
+    for (int k = 0; k < kTerms; ++k) sh[tid >> 6][k] = t[k];
+  __syncthreads();
+  if (tid < kTerms) {
+    double s = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) s += sh[w][tid];
+    terms[tid] = s;
+    if (!isfinite(s)) flag[0] = 1;
+  }
+}
+
 // Adam on pack elements: theta_out[e] = adam_theta(theta_in[e], m, v, ...)
 template <typename T>
 struct AdamArgs {
@@ -219,7 +249,11 @@ hipError_t launch_adam(modil_ctx *c, const void *theta_in, void *theta_out, void
                        const void *g, long n, const AdamHost &h);
 hipError_t launch_fine(modil_ctx *c, const void *u, void *g, bool want_grad);
 hipError_t launch_colsum(modil_ctx *c, void *g_fine);
-hipError_t launch_data(modil_ctx *c, const void *u, void *g, bool want_grad);
+// measurement misfits; with one data block per instance that block also sums
+// the fine and data partials into terms (returns whether it did)
+hipError_t launch_data(modil_ctx *c, const void *u, void *g, bool want_grad, double *terms,
+                       bool &summed);
+// fixed-order sum of the partials [0, n_a) and [off_b, off_b + n_b) per instance
 hipError_t launch_reduce(modil_ctx *c, double *terms, long n_a, long off_b, long n_b);
 hipError_t launch_ns3d_fused(modil_ctx *c, const void *theta, void *g, const AdamHost *adam,
                              void *th_out, void *m, void *v);

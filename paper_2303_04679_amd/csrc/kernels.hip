@@ -586,7 +586,8 @@ __global__ __launch_bounds__(kBlock) void data_kernel(
     const T *__restrict__ u, T *__restrict__ g, FineFields ff, const int32_t *__restrict__ ptr,
     const int32_t *__restrict__ fld, const int32_t *__restrict__ idx, const int32_t *__restrict__ trm,
     const double *__restrict__ val, const double *__restrict__ wt, double *partials,
-    long n_part_blocks, long first_block, int want_grad) {
+    long n_part_blocks, long first_block, int want_grad, long n_fine, double *terms,
+    int32_t *flag) {
   const int inst = blockIdx.y;
   const long b0 = ptr[inst], b1 = ptr[inst + 1];
   const long e = b0 + (long)blockIdx.x * kBlock + threadIdx.x;
@@ -606,28 +607,22 @@ __global__ __launch_bounds__(kBlock) void data_kernel(
       *gp = *gp + T(gs);
     }
   }
-  block_terms(part, partials + ((long)inst * n_part_blocks + first_block + blockIdx.x) * kTerms);
+  double *src = partials + (long)inst * n_part_blocks * kTerms;
+  block_terms(part, src + (first_block + blockIdx.x) * kTerms);
+  // with one data block per instance (terms given), the block also sums the
+  // fine kernel's partials [0, n_fine) (an earlier launch) and its own
+  if (terms) {
+    __syncthreads();
+    final_terms(src, n_fine, first_block, 1, terms + (long)inst * kTerms, flag);
+  }
 }
 
 // fixed-order sum of the partial blocks [0, n_a) and [off_b, off_b + n_b) of one instance
 __global__ __launch_bounds__(kBlock) void reduce_kernel(const double *__restrict__ partials,
                                                         long n_part_blocks, long n_a, long off_b,
                                                         long n_b, double *terms, int32_t *flag) {
-  const int inst = blockIdx.x;
-  double t[kTerms] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  const double *src = partials + (long)inst * n_part_blocks * kTerms;
-  for (long b = threadIdx.x; b < n_a + n_b; b += kBlock) {
-    const long slot = b < n_a ? b : off_b + (b - n_a);
-    for (int k = 0; k < kTerms; ++k) t[k] += src[slot * kTerms + k];
-  }
-  __shared__ double out[kTerms];
-  block_terms(t, out);
-  __syncthreads();
-  if (threadIdx.x < kTerms) {
-    const double x = out[threadIdx.x];
-    terms[(long)inst * kTerms + threadIdx.x] = x;
-    if (!isfinite(x)) flag[0] = 1;
-  }
+  final_terms(partials + (long)blockIdx.x * n_part_blocks * kTerms, n_a, off_b, n_b,
+              terms + (long)blockIdx.x * kTerms, flag);
 }
 
 __global__ void metric_kernel(const double *terms, double *r, int batch, double scale) {
@@ -887,7 +882,11 @@ hipError_t launch_colsum(modil_ctx *c, void *g_fine) {
   return hipGetLastError();
 }
 
-hipError_t launch_data(modil_ctx *c, const void *u, void *g, bool want_grad) {
+hipError_t launch_data(modil_ctx *c, const void *u, void *g, bool want_grad, double *terms,
+                       bool &summed) {
+  const long n_fine = (long)((c->lay.fine_cells + kBlock - 1) / kBlock);
+  summed = c->n_data_blocks == 1;
+  if (!summed) terms = nullptr;
   FineFields ff{};
   ff.nf = c->lay.n_fields;
   ff.inst_stride = c->lay.level_stride[0];
@@ -896,11 +895,13 @@ hipError_t launch_data(modil_ctx *c, const void *u, void *g, bool want_grad) {
   if (c->prob.dtype == MODIL_F64)
     data_kernel<double><<<grid, kBlock, 0, c->stream>>>(
         (const double *)u, (double *)g, ff, c->m_inst_ptr, c->m_field, c->m_idx, c->m_term,
-        c->m_val, c->m_w, c->partials, c->n_part_blocks, c->n_fine_blocks, want_grad ? 1 : 0);
+        c->m_val, c->m_w, c->partials, c->n_part_blocks, c->n_fine_blocks, want_grad ? 1 : 0,
+        n_fine, terms, c->flag);
   else
     data_kernel<float><<<grid, kBlock, 0, c->stream>>>(
         (const float *)u, (float *)g, ff, c->m_inst_ptr, c->m_field, c->m_idx, c->m_term,
-        c->m_val, c->m_w, c->partials, c->n_part_blocks, c->n_fine_blocks, want_grad ? 1 : 0);
+        c->m_val, c->m_w, c->partials, c->n_part_blocks, c->n_fine_blocks, want_grad ? 1 : 0,
+        n_fine, terms, c->flag);
   return hipGetLastError();
 }
 
