@@ -134,7 +134,7 @@ int validate(const modil_problem *p, std::string &msg) {
 
 struct Carve {
   size_t w, g, gq, partials, terms, flag, m_idx, m_field, m_term, m_ptr, m_val, m_w, inst_re;
-  size_t fm_ptr, fm_field, fm_idx, fm_term, fm_val, fm_w, end;
+  size_t fm_ptr, fm_rec, end;
   long n_fine_blocks, n_data_blocks, n_keys;
 };
 
@@ -182,11 +182,7 @@ Carve carve(const modil_problem &p, const modil_pack_layout &L) {
   c.inst_re = take((size_t)p.batch * 8);
   const size_t fm = fused_keys ? mm : 0;
   c.fm_ptr = take(fused_keys ? ((size_t)fused_keys + 1) * 4 : 0);
-  c.fm_field = take(fm * 4);
-  c.fm_idx = take(fm * 4);
-  c.fm_term = take(fm * 4);
-  c.fm_val = take(fm * 8);
-  c.fm_w = take(fm * 8);
+  c.fm_rec = take(fm * sizeof(FusedMeas));
   c.end = off;
   return c;
 }
@@ -247,8 +243,8 @@ int upload_measurements(modil_ctx *c) {
                 "upload");
   // buckets of the fused channel-flow kernel: key = (tile, plane within the z-chunk)
   c->fused_ok = false;
-  std::vector<int32_t> fptr, fidx, ffld, ftrm;
-  std::vector<double> fval, fw;
+  std::vector<int32_t> fptr;
+  std::vector<FusedMeas> frec;
   if (c->prob.op == MODIL_OP_NS3D) {
     int tz, nzt, ntx, nty, ox, oy;
     ns3d_tiles(c->prob, tz, nzt, ntx, nty, ox, oy);
@@ -270,22 +266,24 @@ int upload_measurements(modil_ctx *c) {
     fptr.assign(keys + 1, 0);
     for (size_t k = 0; k < n; ++k) {
       const Meas &e = m[order[k].second];
-      fidx.push_back(e.idx);
-      ffld.push_back(e.field);
-      ftrm.push_back(e.term);
-      fval.push_back(e.val);
-      fw.push_back(e.w);
+      FusedMeas r{};
+      r.field = e.field;
+      r.cell = e.idx;
+      r.term = e.term;
+      // position in the tile, whose first column and row are a 2-cell halo
+      r.lx = (int16_t)(e.idx % nx % ox + 2);
+      r.ly = (int16_t)(e.idx / nx % ny % oy + 2);
+      r.val = e.val;
+      r.w = e.w;
+      frec.push_back(r);
       fptr[order[k].first + 1]++;
     }
     for (long k = 0; k < keys; ++k) fptr[k + 1] += fptr[k];
     HIP_OR_RETURN(c, hipMemcpyAsync(c->fm_ptr, fptr.data(), fptr.size() * 4, hipMemcpyHostToDevice, s), "upload");
-    if (n) {
-      HIP_OR_RETURN(c, hipMemcpyAsync(c->fm_idx, fidx.data(), n * 4, hipMemcpyHostToDevice, s), "upload");
-      HIP_OR_RETURN(c, hipMemcpyAsync(c->fm_field, ffld.data(), n * 4, hipMemcpyHostToDevice, s), "upload");
-      HIP_OR_RETURN(c, hipMemcpyAsync(c->fm_term, ftrm.data(), n * 4, hipMemcpyHostToDevice, s), "upload");
-      HIP_OR_RETURN(c, hipMemcpyAsync(c->fm_val, fval.data(), n * 8, hipMemcpyHostToDevice, s), "upload");
-      HIP_OR_RETURN(c, hipMemcpyAsync(c->fm_w, fw.data(), n * 8, hipMemcpyHostToDevice, s), "upload");
-    }
+    if (n)
+      HIP_OR_RETURN(c, hipMemcpyAsync(c->fm_rec, frec.data(), n * sizeof(FusedMeas),
+                                      hipMemcpyHostToDevice, s),
+                    "upload");
     for (double re : c->inst_re_host) ok = ok && re == c->prob.re;
     c->fused_ok = ok;
   }
@@ -489,11 +487,7 @@ int modil_create(const modil_problem *p, void *ws, size_t ws_bytes, void *stream
   c->m_w = (double *)(c->ws + cv.m_w);
   c->inst_re = (double *)(c->ws + cv.inst_re);
   c->fm_ptr = (int32_t *)(c->ws + cv.fm_ptr);
-  c->fm_field = (int32_t *)(c->ws + cv.fm_field);
-  c->fm_idx = (int32_t *)(c->ws + cv.fm_idx);
-  c->fm_term = (int32_t *)(c->ws + cv.fm_term);
-  c->fm_val = (double *)(c->ws + cv.fm_val);
-  c->fm_w = (double *)(c->ws + cv.fm_w);
+  c->fm_rec = (FusedMeas *)(c->ws + cv.fm_rec);
   c->n_fine_blocks = cv.n_fine_blocks;
   c->n_data_blocks = cv.n_data_blocks;
   c->n_part_blocks = cv.n_fine_blocks + cv.n_data_blocks;

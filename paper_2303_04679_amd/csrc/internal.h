@@ -107,6 +107,16 @@ struct AdamArgs {
   T b1, b2, step, isb2, eps;
 };
 
+// A measurement as the fused channel-flow kernel reads it: field, flat cell
+// index (to find repeated cells), loss term, position in its tile (halo
+// included), value and weight.
+struct FusedMeas {
+  int32_t field, cell, term;
+  int16_t lx, ly;
+  double val, w;
+};
+static_assert(sizeof(FusedMeas) == 32, "32-byte records");
+
 struct Meas {
   int32_t inst, field, term, idx;
   double val, w;
@@ -150,8 +160,8 @@ struct modil_ctx {
   double *inst_re = nullptr;
 
   // measurements bucketed per (tile, plane) for the fused channel-flow kernel
-  int32_t *fm_ptr = nullptr, *fm_field = nullptr, *fm_idx = nullptr, *fm_term = nullptr;
-  double *fm_val = nullptr, *fm_w = nullptr;
+  int32_t *fm_ptr = nullptr;
+  modil::FusedMeas *fm_rec = nullptr;
   bool fused_enabled = true;  // MODIL_OPT_FUSED
   bool fused_ok = false;      // measurements admit the fused kernel
   bool march_enabled = true;  // MODIL_OPT_MARCH

@@ -61,8 +61,8 @@ struct NS3DArgs {
   T *g;               // level 0 of the gradient pack
   const T *forcing[4];
   const T *chi;       // fixed chi, [instance][cells]
-  const int32_t *mptr, *mfld, *midx, *mterm;
-  const double *mval, *mw;
+  const int32_t *mptr;      // [key + 1]: measurement records of (tile, plane)
+  const FusedMeas *mrec;
   double *partials;
   int n_part_blocks;
   AdamArgs<T> adam;   // level-0 pointers of theta_in / theta_out / m / v
@@ -101,8 +101,10 @@ __device__ inline void st_at(T *base, uint32_t byte_off, T v) {
   *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off) = v;
 }
 
-// CHI: 1 fixed chi array, 2 unknown chihat (field 4)
-template <typename T, int CHI, bool ADAM>
+// CHI: 1 fixed chi array, 2 unknown chihat (field 4).  FORCING: some equation
+// has a forcing array (compiled out otherwise: its pointers would hold scalar
+// registers through the plane loop).
+template <typename T, int CHI, bool ADAM, bool FORCING>
 __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel(NS3DArgs<T> A) {
   constexpr int NF = (CHI == 2) ? 5 : 4;  // unknown fields
   constexpr int NS = 5;                   // stored per cell: u, v, w, p, chi
@@ -337,7 +339,7 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
       T r[4];
       ns_residual<3, true>(K, L, uc, U2[4], r);
       for (int e = 0; e < 4; ++e) {
-        if (A.forcing[e]) r[e] -= ld_at(A.forcing[e] + inst * A.fsize, fo[0] + pofs(s));
+        if (FORCING && A.forcing[e]) r[e] -= ld_at(A.forcing[e] + inst * A.fsize, fo[0] + pofs(s));
         an[e] = T(2) * wv * r[e];
       }
       if (own_xy && s >= z0 && s < z1)
@@ -348,16 +350,16 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
       const int key = key_base + (q - z0);
       const int e0 = A.mptr[key], e1 = A.mptr[key + 1];
       for (int e = e0 + tid; e < e1; e += NS_THREADS) {
-        const int f = A.mfld[e], k = A.midx[e];
-        const int lx = k % nx - ox, ly = (k / nx) % ny - oy;  // tile coordinates
-        const T uv = Ul[qb][f][ly][lx];
-        const double r = (double)uv - A.mval[e];
-        part[A.mterm[e]] += A.mw[e] * r * r;
-        if (e == e0 || A.mfld[e - 1] != f || A.midx[e - 1] != k) {
+        const FusedMeas me = A.mrec[e];
+        const int f = me.field, k = me.cell;
+        const T uv = Ul[qb][f][me.ly][me.lx];
+        const double r = (double)uv - me.val;
+        part[me.term] += me.w * r * r;
+        if (e == e0 || A.mrec[e - 1].field != f || A.mrec[e - 1].cell != k) {
           double gs = 0.0;
-          for (int j = e; j < e1 && A.mfld[j] == f && A.midx[j] == k; ++j)
-            gs += 2.0 * A.mw[j] * ((double)uv - A.mval[j]);
-          Dl[f][ly][lx] = T(gs);
+          for (int j = e; j < e1 && A.mrec[j].field == f && A.mrec[j].cell == k; ++j)
+            gs += 2.0 * A.mrec[j].w * ((double)uv - A.mrec[j].val);
+          Dl[f][me.ly][me.lx] = T(gs);
         }
       }
     }
@@ -516,8 +518,8 @@ static hipError_t fused_t(modil_ctx *c, const void *theta, void *g, const AdamHo
   A.g = (T *)g;
   for (int e = 0; e < 4; ++e) A.forcing[e] = (const T *)c->forcing[e];
   A.chi = (const T *)c->chi;
-  A.mptr = c->fm_ptr; A.mfld = c->fm_field; A.midx = c->fm_idx; A.mterm = c->fm_term;
-  A.mval = c->fm_val; A.mw = c->fm_w;
+  A.mptr = c->fm_ptr;
+  A.mrec = c->fm_rec;
   A.partials = c->partials;
   A.n_part_blocks = (int)c->n_part_blocks;
   if (ad) {
@@ -528,12 +530,14 @@ static hipError_t fused_t(modil_ctx *c, const void *theta, void *g, const AdamHo
   }
   const dim3 grid(NS_XCD * A.tiles_per_xcd * P.batch), block(NS_THREADS);
   const bool fixed = (P.flags & MODIL_FLAG_CHI_FIXED) != 0;
+  const bool forcing = A.forcing[0] || A.forcing[1] || A.forcing[2] || A.forcing[3];
+  auto go = [&](auto kernel) { kernel<<<grid, block, 0, c->stream>>>(A); };
   if (fixed) {
-    if (ad) ns3d_fused_kernel<T, 1, true><<<grid, block, 0, c->stream>>>(A);
-    else ns3d_fused_kernel<T, 1, false><<<grid, block, 0, c->stream>>>(A);
+    if (ad) forcing ? go(ns3d_fused_kernel<T, 1, true, true>) : go(ns3d_fused_kernel<T, 1, true, false>);
+    else forcing ? go(ns3d_fused_kernel<T, 1, false, true>) : go(ns3d_fused_kernel<T, 1, false, false>);
   } else {
-    if (ad) ns3d_fused_kernel<T, 2, true><<<grid, block, 0, c->stream>>>(A);
-    else ns3d_fused_kernel<T, 2, false><<<grid, block, 0, c->stream>>>(A);
+    if (ad) forcing ? go(ns3d_fused_kernel<T, 2, true, true>) : go(ns3d_fused_kernel<T, 2, true, false>);
+    else forcing ? go(ns3d_fused_kernel<T, 2, false, true>) : go(ns3d_fused_kernel<T, 2, false, false>);
   }
   return hipGetLastError();
 }
