@@ -311,14 +311,24 @@ int evaluate(modil_ctx *c, const void *theta, void *grad, double *terms, const A
       Timed t(c, 0);
       HIP_OR_RETURN(c, launch_ns3d_fused(c, theta, grad, adam, th_out, m, v), "fused kernel");
     }
-    {
-      Timed t(c, 2);
-      HIP_OR_RETURN(c, launch_restrict_chain(c, grad, 0, theta, th_out, m, v, adam), "restrict");
-    }
     long blocks, keys;
     fused_geometry(c->prob, blocks, keys);
-    Timed t(c, 4);
-    HIP_OR_RETURN(c, launch_reduce(c, terms, blocks, 0, 0), "reduce");
+    TermSum sum;
+    sum.partials = c->partials;
+    sum.n_part_blocks = c->n_part_blocks;
+    sum.n_a = blocks;
+    sum.terms = terms;
+    sum.flag = c->flag;
+    bool summed = false;
+    {
+      Timed t(c, 2);
+      HIP_OR_RETURN(c, launch_restrict_chain(c, grad, 0, theta, th_out, m, v, adam, &sum, &summed),
+                    "restrict");
+    }
+    if (!summed) {
+      Timed t(c, 4);
+      HIP_OR_RETURN(c, launch_reduce(c, terms, blocks, 0, 0), "reduce");
+    }
     return MODIL_OK;
   }
   const void *u = theta;

@@ -241,8 +241,21 @@ struct AdamHost {
 hipError_t launch_horner(modil_ctx *c, const void *theta, void *fine_dst, bool skip_fine);
 // g_{l+1} = T^T g_l for l >= from_level (pack layout in g); with adam also
 // Adam on every level it produces.
+// A final sum of loss partials that a later kernel can carry out:
+// final_terms(partials + instance * n_part_blocks * kTerms, n_a, off_b, n_b, ...)
+// for every instance.
+struct TermSum {
+  const double *partials = nullptr;
+  long n_part_blocks = 0, n_a = 0, off_b = 0, n_b = 0;
+  double *terms = nullptr;
+  int32_t *flag = nullptr;
+};
+// Restriction of the gradient from level from_level down, with Adam on every
+// level produced when adam is given.  With sum given, the chain's last kernel
+// also does that sum when it can (summed tells whether it did).
 hipError_t launch_restrict_chain(modil_ctx *c, void *g, int from_level, const void *th_in,
-                                 void *th_out, void *m, void *v, const AdamHost *adam);
+                                 void *th_out, void *m, void *v, const AdamHost *adam,
+                                 const TermSum *sum = nullptr, bool *summed = nullptr);
 // Marching restriction of level l -> l+1 with optional Adam (restrict_march.hip);
 // returns false, launching nothing, when the level's shape does not admit it.
 // tile: 16 * rows + planes per wave, 0 = automatic.

@@ -319,11 +319,19 @@ __global__ __launch_bounds__(kBlock) void restrict_kernel(Levels G, int l, T *g,
 // levels l_lo and l_lo + 1 alternate.
 template <typename T, bool ADAM>
 __global__ __launch_bounds__(1024) void restrict_tail_kernel(Levels G, int l_lo, int cap0, T *g,
-                                                             AdamArgs<T> A) {
+                                                             AdamArgs<T> A, TermSum S) {
   constexpr int kPf = 2;  // outputs per thread of the first level whose Adam state is prefetched
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *cur = reinterpret_cast<T *>(smem_raw);
   T *nxt = cur + cap0;
+  // blocks past the (instance, field) ones sum the loss partials of an
+  // earlier kernel, one instance each
+  if ((int)blockIdx.x >= G.batch * G.nf) {
+    const int i = blockIdx.x - G.batch * G.nf;
+    final_terms(S.partials + (long)i * S.n_part_blocks * kTerms, S.n_a, S.off_b, S.n_b,
+                S.terms + (long)i * kTerms, S.flag);
+    return;
+  }
   const int inst = blockIdx.x / G.nf, f = blockIdx.x % G.nf;
   const int bd = blockDim.x, tid = threadIdx.x;
   const int base1 = G.off[l_lo + 1] + inst * G.stride[l_lo + 1] + G.foff[l_lo + 1][f];
@@ -729,7 +737,9 @@ hipError_t launch_horner(modil_ctx *c, const void *theta, void *fine_dst, bool s
 
 template <typename T>
 static hipError_t restrict_t(modil_ctx *c, void *g_v, int from, const void *th_in, void *th_out,
-                             void *m, void *v, const AdamHost *ad) {
+                             void *m, void *v, const AdamHost *ad, const TermSum *sum,
+                             bool *summed) {
+  if (summed) *summed = false;
   const Levels G = levels_of(c);
   T *g = (T *)g_v;
   AdamArgs<T> A{};
@@ -738,8 +748,9 @@ static hipError_t restrict_t(modil_ctx *c, void *g_v, int from, const void *th_i
     A.b1 = T(ad->b1); A.b2 = T(ad->b2); A.step = T(ad->step); A.isb2 = T(ad->isb2); A.eps = T(ad->eps);
   }
   // levels lt+1 .. L-1 come from one launch of the LDS tail kernel
+  // (less 1 KB of the LDS budget for the kernel's static arrays)
   int lt = c->tail_enabled
-               ? tail_level(G, from, sizeof(T), c->lds_budget, kTailCapRestrict, true)
+               ? tail_level(G, from, sizeof(T), c->lds_budget - 1024, kTailCapRestrict, true)
                : G.L - 1;
   const int cap0 = lt + 1 < G.L ? (int)max_field(G, lt) : 0;
   const size_t bytes = lt + 1 < G.L ? (size_t)(cap0 + max_field(G, lt + 1)) * sizeof(T) : 0;
@@ -757,18 +768,23 @@ static hipError_t restrict_t(modil_ctx *c, void *g_v, int from, const void *th_i
       restrict_kernel<T, false><<<nblk(total), kBlock, 0, c->stream>>>(G, l, g, A);
   }
   if (lt + 1 < G.L) {
+    const TermSum S = sum ? *sum : TermSum{};
+    const int blocks = G.batch * G.nf + (sum ? G.batch : 0);
     if (ad)
-      restrict_tail_kernel<T, true><<<G.batch * G.nf, 1024, bytes, c->stream>>>(G, lt, cap0, g, A);
+      restrict_tail_kernel<T, true><<<blocks, 1024, bytes, c->stream>>>(G, lt, cap0, g, A, S);
     else
-      restrict_tail_kernel<T, false><<<G.batch * G.nf, 1024, bytes, c->stream>>>(G, lt, cap0, g, A);
+      restrict_tail_kernel<T, false><<<blocks, 1024, bytes, c->stream>>>(G, lt, cap0, g, A, S);
+    if (summed) *summed = sum != nullptr;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_restrict_chain(modil_ctx *c, void *g, int from, const void *th_in, void *th_out,
-                                 void *m, void *v, const AdamHost *adam) {
-  return c->prob.dtype == MODIL_F64 ? restrict_t<double>(c, g, from, th_in, th_out, m, v, adam)
-                                    : restrict_t<float>(c, g, from, th_in, th_out, m, v, adam);
+                                 void *m, void *v, const AdamHost *adam, const TermSum *sum,
+                                 bool *summed) {
+  return c->prob.dtype == MODIL_F64
+             ? restrict_t<double>(c, g, from, th_in, th_out, m, v, adam, sum, summed)
+             : restrict_t<float>(c, g, from, th_in, th_out, m, v, adam, sum, summed);
 }
 
 hipError_t launch_adam(modil_ctx *c, const void *th_in, void *th_out, void *m, void *v,
