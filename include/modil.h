@@ -261,6 +261,11 @@ int modil_residual_metric(modil_ctx *ctx, const void *theta_pack, double *r);
  * are prolonged, and restricted with Adam, by one launch with one block per
  * instance working in LDS; 0 launches one kernel per level instead.       */
 #define MODIL_OPT_TAIL 3
+/* MODIL_OPT_TILE (default 1): the generic engine on 2-D problems stages tiles
+ * of the fine fields in LDS and forms every cell's residuals once; 0 selects
+ * the per-cell kernel, which forms the residuals of each cell's neighbours
+ * again.  Same results up to the order of the sums.                       */
+#define MODIL_OPT_TILE 4
 int modil_set_option(modil_ctx *ctx, int32_t option, int64_t value);
 /* modil_fused_active: 1 if the next loss / gradient / step of this context
  * runs the fused finest-level kernel (option on and the problem, its

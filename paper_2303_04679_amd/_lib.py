@@ -23,6 +23,7 @@ OPT_FUSED = 0
 OPT_MARCH = 1
 OPT_MARCH_TILE = 2
 OPT_TAIL = 3
+OPT_TILE = 4
 MAX_LEVELS, MAX_FIELDS = 8, 5
 TERM_NAMES = ("pde", "data", "reg", "ic", "bc")
 

@@ -160,7 +160,7 @@ Carve carve(const modil_problem &p, const modil_pack_layout &L) {
   };
   long fused_blocks, fused_keys;
   fused_geometry(p, fused_blocks, fused_keys);
-  c.n_fine_blocks = std::max<long>((long)((L.fine_cells + kBlock - 1) / kBlock), fused_blocks);
+  c.n_fine_blocks = std::max<long>(fine_partial_slots(p), fused_blocks);
   c.n_keys = fused_keys;
   c.n_data_blocks = std::max<long>(1, (p.max_meas + kBlock - 1) / kBlock);
   const long nl = p.n_levels;
@@ -354,8 +354,7 @@ int evaluate(modil_ctx *c, const void *theta, void *grad, double *terms, const A
   }
   if (!summed) {
     Timed t(c, 4);
-    const long generic_blocks = (long)((c->lay.fine_cells + kBlock - 1) / kBlock);
-    HIP_OR_RETURN(c, launch_reduce(c, terms, generic_blocks, c->n_fine_blocks, c->n_data_blocks),
+    HIP_OR_RETURN(c, launch_reduce(c, terms, c->fine_slots, c->n_fine_blocks, c->n_data_blocks),
                   "reduce");
   }
   if (adam) {
@@ -707,6 +706,10 @@ int modil_set_option(modil_ctx *c, int32_t option, int64_t value) {
   }
   if (option == MODIL_OPT_TAIL) {
     c->tail_enabled = value != 0;
+    return MODIL_OK;
+  }
+  if (option == MODIL_OPT_TILE) {
+    c->tile_enabled = value != 0;
     return MODIL_OK;
   }
   if (option == MODIL_OPT_MARCH_TILE) {

@@ -167,9 +167,11 @@ struct modil_ctx {
   bool march_enabled = true;  // MODIL_OPT_MARCH
   int march_tile = 0;         // MODIL_OPT_MARCH_TILE
   bool tail_enabled = true;   // MODIL_OPT_TAIL
+  bool tile_enabled = true;   // MODIL_OPT_TILE
   size_t lds_budget = 64 * 1024;  // LDS bytes one block of the tail kernels may use
 
   long n_fine_blocks = 0;   // partial blocks of the fine kernel per instance
+  long fine_slots = 0;      // partial slots the last generic fine-kernel launch wrote
   long n_data_blocks = 0;   // partial blocks of the data kernel per instance
   long n_part_blocks = 0;   // n_fine_blocks + n_data_blocks
 
@@ -271,6 +273,8 @@ bool launch_prolong_block(const Levels &G, int l, const T *theta, const T *csrc,
 hipError_t launch_adam(modil_ctx *c, const void *theta_in, void *theta_out, void *m, void *v,
                        const void *g, long n, const AdamHost &h);
 hipError_t launch_fine(modil_ctx *c, const void *u, void *g, bool want_grad);
+// most partial slots per instance the generic fine kernels use
+long fine_partial_slots(const modil_problem &P);
 hipError_t launch_colsum(modil_ctx *c, void *g_fine);
 // measurement misfits; with one data block per instance that block also sums
 // the fine and data partials into terms (returns whether it did)

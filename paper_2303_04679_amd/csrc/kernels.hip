@@ -560,6 +560,144 @@ __global__ __launch_bounds__(kBlock) void fine_kernel(FineArgs<T> A) {
   block_terms(part, A.partials + ((long)inst * A.n_part_blocks + blockIdx.x) * kTerms);
 }
 
+// ------------------------------------------------ 2-D stencil engine by tiles
+// A block owns TX x TY cells of one instance.  It stages the fields of its tile
+// with a 2-cell halo in LDS; every cell of the tile plus a 1-cell halo forms
+// its residuals once (loss partials from the owned cells) and writes the
+// sensitivities of its weighted residual to the 7 slots of its star, ghost
+// slots folded back, to LDS; every owned cell then sums the slots that refer
+// to it.  Same adjoint as fine_kernel (which forms each neighbour's residuals
+// again per cell), without atomics.
+template <int TX, int TY>
+struct FineTile {
+  static constexpr int UX = TX + 4, UY = TY + 4;  // staged fields
+  static constexpr int SX = TX + 2, SY = TY + 2;  // cells forming residuals
+};
+
+// block sum of the loss partials for a block of NT threads (a whole number of waves)
+template <int NT>
+__device__ inline void block_terms_n(double (&t)[kTerms], double *out) {
+  static_assert(NT % 64 == 0 && NT <= 1024, "whole waves");
+  __shared__ double sh[NT / 64][kTerms];
+  for (int k = 0; k < kTerms; ++k)
+    for (int off = 32; off >= 1; off >>= 1) t[k] += __shfl_down(t[k], off, 64);
+  if ((threadIdx.x & 63) == 0)
+    for (int k = 0; k < kTerms; ++k) sh[threadIdx.x >> 6][k] = t[k];
+  __syncthreads();
+  if (threadIdx.x < kTerms) {
+    double sum = 0.0;
+    for (int w = 0; w < NT / 64; ++w) sum += sh[w][threadIdx.x];
+    out[threadIdx.x] = sum;
+  }
+}
+
+// star of cell i (2-D) from the staged tile ut ([field][UY][UX], cell at X, Y),
+// ghost values at the domain edges as load_star forms them
+template <class Op, typename T, int UX, int UY>
+__device__ inline void star_from_tile(const OpParams &p, const FineFields &ff, const int (&i)[3],
+                                      const T *ut, int X, int Y, T (&U)[Op::NF][7]) {
+  for (int f = 0; f < Op::NF; ++f) {
+    const T *b = ut + f * UX * UY;
+    const T c = b[Y * UX + X];
+    for (int q = 0; q < 7; ++q) U[f][q] = c;
+    if (!Op::needs_nb(f)) continue;
+    for (int a = 1; a < 3; ++a) {
+      if (ff.stride[f][a] == 0) continue;
+      const int d = a == 2 ? 1 : UX;  // neighbour offset in the tile
+      const int k = Y * UX + X;
+      if (i[a] > 0) {
+        U[f][slot_m(a)] = b[k - d];
+      } else {
+        const GhostRule gr = Op::ghost(p, f, a, 0);
+        U[f][slot_m(a)] = T(gr.b2) + T(gr.c0) * c + T(gr.c1) * b[k + d];
+      }
+      if (i[a] < p.n[a] - 1) {
+        U[f][slot_p(a)] = b[k + d];
+      } else {
+        const GhostRule gr = Op::ghost(p, f, a, 1);
+        U[f][slot_p(a)] = T(gr.b2) + T(gr.c0) * c + T(gr.c1) * b[k - d];
+      }
+    }
+  }
+}
+
+template <class Op, typename T, int TX, int TY>
+__global__ __launch_bounds__(TX * TY) void fine_tile_kernel(FineArgs<T> A, int tiles_x) {
+  using FT = FineTile<TX, TY>;
+  constexpr int NT = TX * TY, NF = Op::NF, NE = Op::NE;
+  __shared__ T Ut[NF][FT::UY][FT::UX];
+  __shared__ T St[NF][7][FT::SY][FT::SX];
+  const int inst = blockIdx.y, tid = threadIdx.x;
+  const int x0 = (blockIdx.x % tiles_x) * TX, y0 = (blockIdx.x / tiles_x) * TY;
+  const int ny = A.p.n[1], nx = A.p.n[2];
+  const T *ub = A.u + (long)inst * A.ff.inst_stride;
+  for (int k = tid; k < FT::UX * FT::UY; k += NT) {
+    const int X = k % FT::UX, Y = k / FT::UX, x = x0 - 2 + X, y = y0 - 2 + Y;
+    const bool in = x >= 0 && x < nx && y >= 0 && y < ny;
+    for (int f = 0; f < NF; ++f)
+      Ut[f][Y][X] = in ? ub[A.ff.off[f] + y * A.ff.stride[f][1] + x * A.ff.stride[f][2]] : T(0);
+  }
+  __syncthreads();
+  double part[kTerms] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int k = tid; k < FT::SX * FT::SY; k += NT) {
+    const int X = k % FT::SX, Y = k / FT::SX, x = x0 - 1 + X, y = y0 - 1 + Y;
+    T s[NF][7];
+    for (int f = 0; f < NF; ++f)
+      for (int q = 0; q < 7; ++q) s[f][q] = T(0);
+    if (x >= 0 && x < nx && y >= 0 && y < ny) {
+      const int i[3] = {0, y, x};
+      T U[NF][7];
+      star_from_tile<Op, T, FT::UX, FT::UY>(A.p, A.ff, i, &Ut[0][0][0], X + 1, Y + 1, U);
+      const long lin = (long)y * nx + x;
+      const T chi = A.chi ? A.chi[(long)inst * A.ncell + lin] : T(0);
+      T r[NE], wv[NE];
+      int term[NE];
+      Op::eval(A.p, i, inst, U, chi, r, wv, term);
+      for (int e = 0; e < NE && e < 4; ++e)
+        if (A.forcing[e] && wv[e] != T(0) && (!Op::kForcePdeOnly || term[e] == MODIL_TERM_PDE))
+          r[e] -= A.forcing[e][(long)inst * A.ncell + lin];
+      if (X >= 1 && X <= TX && Y >= 1 && Y <= TY)
+        for (int e = 0; e < NE; ++e) part[term[e]] += (double)wv[e] * (double)r[e] * (double)r[e];
+      if (A.want_grad) {
+        T a[NE];
+        for (int e = 0; e < NE; ++e) a[e] = T(2) * wv[e] * r[e];
+        Op::vjp(A.p, i, inst, U, chi, a, s);
+        fold_ghosts<Op>(A.p, A.ff, i, s);
+      }
+    }
+    if (A.want_grad)
+      for (int f = 0; f < NF; ++f)
+        for (int q = 0; q < 7; ++q) St[f][q][Y][X] = s[f][q];
+  }
+  if (A.want_grad) {
+    __syncthreads();
+    const int cx = tid % TX, cy = tid / TX, x = x0 + cx, y = y0 + cy;
+    if (x < nx && y < ny) {
+      T gacc[NF];
+      for (int f = 0; f < NF; ++f) gacc[f] = T(0);
+      for (int o = 0; o < 7; ++o) {
+        int X = cx + 1, Y = cy + 1, jx = x, jy = y;
+        if (o > 0) {
+          // slot o of cell j refers to this cell: j = this cell - offset(o)
+          const int a = (o - 1) >> 1, d = (o & 1) ? 1 : -1;
+          if (a == 0) continue;
+          if (a == 1) { jy += d; Y += d; } else { jx += d; X += d; }
+          if (jy < 0 || jy >= ny || jx < 0 || jx >= nx) continue;
+        }
+        for (int f = 0; f < NF; ++f) gacc[f] += St[f][o][Y][X];
+      }
+      const long c = (long)y * nx + x;
+      for (int f = 0; f < NF; ++f) {
+        if (f == A.xonly_field)
+          A.gq[(long)inst * A.ncell + c] = gacc[f];
+        else
+          A.g[(long)inst * A.ff.inst_stride + A.ff.off[f] + c] = gacc[f];
+      }
+    }
+  }
+  block_terms_n<NT>(part, A.partials + ((long)inst * A.n_part_blocks + blockIdx.x) * kTerms);
+}
+
 // column sums of the x-only field's per-cell contributions (rows = t)
 // Column sums of the per-cell contributions of the x-only field: a block
 // takes 64 columns of one instance; 16 row groups sum every 16th row, then the
@@ -842,11 +980,67 @@ static FineArgs<T> fine_args(modil_ctx *c, const void *u, void *g, bool want_gra
   return A;
 }
 
+// cells per axis of the fine grid of a 2-D problem (y, x)
+static void fine_2d(const modil_problem &P, int &ny, int &nx) {
+  const int extra = P.centering == MODIL_NODE ? 1 : 0;
+  ny = P.dims[0] + extra;
+  nx = P.dims[1] + extra;
+}
+
+static bool fine_is_2d(const modil_problem &P) {
+  return P.op == MODIL_OP_BURGERS || P.op == MODIL_OP_HEAT_KX || P.op == MODIL_OP_CAVITY ||
+         (P.op == MODIL_OP_POISSON && P.ndim == 2);
+}
+
+long fine_partial_slots(const modil_problem &P) {
+  long cells = 1;
+  for (int k = 0; k < P.ndim; ++k) cells *= P.dims[k] + (P.centering == MODIL_NODE ? 1 : 0);
+  long slots = (cells + kBlock - 1) / kBlock;
+  if (fine_is_2d(P)) {
+    int ny, nx;
+    fine_2d(P, ny, nx);
+    slots = std::max(slots, (long)((nx + 15) / 16) * ((ny + 3) / 4));  // the smaller tile
+  }
+  return slots;
+}
+
+// the tiled engine for one operator: 32 x 8 tiles when they give every
+// compute unit a block, else 16 x 4
+template <class Op, typename T>
+static void launch_fine_tile(modil_ctx *c, const FineArgs<T> &A) {
+  int ny, nx;
+  fine_2d(c->prob, ny, nx);
+  int tx = (nx + 31) / 32, ty = (ny + 7) / 8;
+  if ((long)tx * ty * c->prob.batch >= 256) {
+    c->fine_slots = (long)tx * ty;
+    fine_tile_kernel<Op, T, 32, 8><<<dim3(tx * ty, c->prob.batch), 256, 0, c->stream>>>(A, tx);
+  } else {
+    tx = (nx + 15) / 16;
+    ty = (ny + 3) / 4;
+    c->fine_slots = (long)tx * ty;
+    fine_tile_kernel<Op, T, 16, 4><<<dim3(tx * ty, c->prob.batch), 64, 0, c->stream>>>(A, tx);
+  }
+}
+
 template <typename T>
 static hipError_t launch_fine_t(modil_ctx *c, const void *u, void *g, bool want_grad) {
   const FineArgs<T> A = fine_args<T>(c, u, g, want_grad);
   const dim3 grid(nblk(A.ncell), c->prob.batch);
   const modil_problem &P = c->prob;
+  c->fine_slots = nblk(A.ncell);
+  if (c->tile_enabled && fine_is_2d(P)) {
+    switch (P.op) {
+      case MODIL_OP_POISSON:
+        if (P.centering == MODIL_NODE) launch_fine_tile<OpPoissonNode, T>(c, A);
+        else launch_fine_tile<OpPoisson, T>(c, A);
+        break;
+      case MODIL_OP_BURGERS: launch_fine_tile<OpBurgers, T>(c, A); break;
+      case MODIL_OP_HEAT_KX: launch_fine_tile<OpHeat, T>(c, A); break;
+      case MODIL_OP_CAVITY: launch_fine_tile<OpNS<2, 0>, T>(c, A); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   switch (P.op) {
     case MODIL_OP_POISSON:
       if (P.centering == MODIL_NODE)
@@ -900,7 +1094,7 @@ hipError_t launch_colsum(modil_ctx *c, void *g_fine) {
 
 hipError_t launch_data(modil_ctx *c, const void *u, void *g, bool want_grad, double *terms,
                        bool &summed) {
-  const long n_fine = (long)((c->lay.fine_cells + kBlock - 1) / kBlock);
+  const long n_fine = c->fine_slots;
   summed = c->n_data_blocks == 1;
   if (!summed) terms = nullptr;
   FineFields ff{};

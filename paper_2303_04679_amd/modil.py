@@ -269,6 +269,11 @@ class Context:
         """Do the small coarse levels of each instance in one LDS launch (default)."""
         L.check(L.lib().modil_set_option(self.h, L.OPT_TAIL, 1 if enabled else 0), self.h)
 
+    def set_tile(self, enabled: bool):
+        """Generic engine on 2-D problems: LDS tiles forming every residual
+        once (default), or the per-cell kernel."""
+        L.check(L.lib().modil_set_option(self.h, L.OPT_TILE, 1 if enabled else 0), self.h)
+
     def set_march_tile(self, rows: int = 0, planes: int = 0):
         """Coarse rows and planes per wave of the marching kernel (0, 0: automatic)."""
         L.check(L.lib().modil_set_option(self.h, L.OPT_MARCH_TILE, 16 * rows + planes), self.h)

@@ -212,6 +212,39 @@ def test_nonfinite_is_reported():
     ctx.check()   # the flag is cleared
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("op,dims,L,batch", [("heat", (40, 72), 3, 1), ("cavity", (32, 48), 4, 1),
+                                             ("burgers", (24, 40), 3, 1), ("poisson", (32, 48), 4, 1),
+                                             ("poisson_node", (16, 24), 3, 1),
+                                             ("heat", (64, 96), 3, 12), ("cavity", (48, 64), 3, 16)])
+def test_tiled_engine(op, dims, L, batch, dtype):
+    """The 2-D tiled engine (16 x 4 tiles; 32 x 8 when the batch fills the
+    chip) against the per-cell kernel for every instance and the oracle for
+    the first and last; ragged tiles, node-based values, an x-only field."""
+    need_gpu()
+    print(f"\n[parity] tiled {op} {dims} L={L} batch={batch} {dtype}", flush=True)
+    forcing = op not in ("poisson", "poisson_node")
+    specs = [case(op, dims, L, seed=60 + b, with_forcing=forcing) for b in range(batch)]
+    ctx = context_of(specs[0], dtype, batch=batch, specs=specs)
+    lvs = [rounded(_levels(s, 70 + b), dtype) for b, s in enumerate(specs)]
+    theta = pack_of(ctx, lvs)
+    tt, gt = ctx.loss_grad(theta)
+    lt = ctx.loss(theta)
+    ctx.set_tile(False)
+    tc, gc = ctx.loss_grad(theta)
+    torch.cuda.synchronize()
+    tol = TOL[dtype]
+    for b in range(batch):
+        ref = {t: float(tc[b, k]) for k, t in enumerate(TERMS)}
+        assert_terms(tt[b].cpu().numpy(), ref, tol, ("per-cell", b))
+        assert_terms(lt[b].cpu().numpy(), ref, tol, ("per-cell loss", b))
+        assert_levels(levels_of(ctx, gt, b), levels_of(ctx, gc, b), tol, ("per-cell", b))
+    for b in sorted({0, batch - 1}):
+        rt, rg = ops.loss_and_grad(specs[b], lvs[b])
+        assert_terms(tt[b].cpu().numpy(), rt, tol, ("oracle", b))
+        assert_levels(levels_of(ctx, gt, b), rg, tol, ("oracle", b))
+
+
 def test_theta_pingpong_required():
     need_gpu()
     from paper_2303_04679_amd import _lib as L
