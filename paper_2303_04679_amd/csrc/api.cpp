@@ -134,7 +134,7 @@ int validate(const modil_problem *p, std::string &msg) {
 
 struct Carve {
   size_t w, g, gq, partials, terms, flag, m_idx, m_field, m_term, m_ptr, m_val, m_w, inst_re;
-  size_t fm_ptr, fm_rec, end;
+  size_t fm_ptr, fm_rec, tm_ptr, tm_rec, end;
   long n_fine_blocks, n_data_blocks, n_keys;
 };
 
@@ -147,6 +147,14 @@ void fused_geometry(const modil_problem &p, long &blocks, long &keys) {
   ns3d_tiles(p, tz, nzt, ntx, nty, ox, oy);
   blocks = (long)nzt * ntx * nty;
   keys = (long)p.batch * blocks * tz;
+}
+
+// (instance, tile) buckets of the 2-D tiled engine (0 for other problems)
+long tile_keys(const modil_problem &p) {
+  if (!fine_is_2d(p)) return 0;
+  int tx, ty, nbx, nby;
+  fine_tile_shape(p, tx, ty, nbx, nby);
+  return (long)p.batch * nbx * nby;
 }
 
 Carve carve(const modil_problem &p, const modil_pack_layout &L) {
@@ -183,6 +191,9 @@ Carve carve(const modil_problem &p, const modil_pack_layout &L) {
   const size_t fm = fused_keys ? mm : 0;
   c.fm_ptr = take(fused_keys ? ((size_t)fused_keys + 1) * 4 : 0);
   c.fm_rec = take(fm * sizeof(FusedMeas));
+  const long tkeys = tile_keys(p);
+  c.tm_ptr = take(tkeys ? ((size_t)tkeys + 1) * 4 : 0);
+  c.tm_rec = take(tkeys ? mm * sizeof(FusedMeas) : 0);
   c.end = off;
   return c;
 }
@@ -287,6 +298,46 @@ int upload_measurements(modil_ctx *c) {
     for (double re : c->inst_re_host) ok = ok && re == c->prob.re;
     c->fused_ok = ok;
   }
+  // buckets of the 2-D tiled engine: key = (instance, tile); within a key the
+  // order of the list (field, cell, term) is kept
+  if (fine_is_2d(c->prob)) {
+    int tx, ty, nbx, nby, ny, nx;
+    fine_tile_shape(c->prob, tx, ty, nbx, nby);
+    fine_2d(c->prob, ny, nx);
+    const long keys = (long)c->prob.batch * nbx * nby;
+    std::vector<std::pair<long, size_t>> order(n);
+    for (size_t k = 0; k < n; ++k) {
+      const int x = m[k].idx % nx, y = m[k].idx / nx;
+      order[k] = {((long)m[k].inst * nby + y / ty) * nbx + x / tx, k};
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [](const std::pair<long, size_t> &a, const std::pair<long, size_t> &b) {
+                       return a.first < b.first;
+                     });
+    std::vector<int32_t> tptr(keys + 1, 0);
+    std::vector<FusedMeas> trec;
+    trec.reserve(n);
+    for (size_t k = 0; k < n; ++k) {
+      const Meas &e = m[order[k].second];
+      FusedMeas r{};
+      r.field = e.field;
+      r.cell = e.idx;
+      r.term = e.term;
+      r.lx = (int16_t)(e.idx % nx % tx);
+      r.ly = (int16_t)(e.idx / nx % ty);
+      r.val = e.val;
+      r.w = e.w;
+      trec.push_back(r);
+      tptr[order[k].first + 1]++;
+    }
+    for (long k = 0; k < keys; ++k) tptr[k + 1] += tptr[k];
+    HIP_OR_RETURN(c, hipMemcpyAsync(c->tm_ptr, tptr.data(), tptr.size() * 4, hipMemcpyHostToDevice, s),
+                  "upload");
+    if (n)
+      HIP_OR_RETURN(c, hipMemcpyAsync(c->tm_rec, trec.data(), n * sizeof(FusedMeas),
+                                      hipMemcpyHostToDevice, s),
+                    "upload");
+  }
   HIP_OR_RETURN(c, hipStreamSynchronize(s), "upload");
   c->n_meas_dev = (int)n;
   return MODIL_OK;
@@ -337,6 +388,37 @@ int evaluate(modil_ctx *c, const void *theta, void *grad, double *terms, const A
     Timed t(c, 1);
     HIP_OR_RETURN(c, launch_horner(c, theta, nullptr, false), "prolong");
     u = c->w_buf;
+  }
+  if (fine_uses_tiles(c)) {
+    // 2-D tiled engine: the tile kernel also forms the data terms and, with
+    // Adam, updates level 0; the restriction kernels update the coarse levels
+    // and the restriction tail sums the loss partials
+    {
+      Timed t(c, 0);
+      HIP_OR_RETURN(c, launch_fine(c, u, grad, want, adam, theta, th_out, m, v), "fine kernel");
+    }
+    TermSum sum;
+    sum.partials = c->partials;
+    sum.n_part_blocks = c->n_part_blocks;
+    sum.n_a = c->fine_slots;
+    sum.terms = terms;
+    sum.flag = c->flag;
+    if (want) {
+      bool xonly = false;
+      for (int f = 0; f < c->lay.n_fields; ++f) xonly |= field_is_x_only(c->prob, f);
+      if (xonly) {
+        Timed t(c, 4);
+        HIP_OR_RETURN(c, launch_colsum(c, grad, adam, theta, th_out, m, v), "column sum");
+      }
+      Timed t(c, 2);
+      HIP_OR_RETURN(c, launch_restrict_chain(c, grad, 0, theta, th_out, m, v, adam, &sum, &summed),
+                    "restrict");
+    }
+    if (!summed) {
+      Timed t(c, 4);
+      HIP_OR_RETURN(c, launch_reduce(c, terms, c->fine_slots, 0, 0), "reduce");
+    }
+    return MODIL_OK;
   }
   {
     Timed t(c, 0);
@@ -497,6 +579,8 @@ int modil_create(const modil_problem *p, void *ws, size_t ws_bytes, void *stream
   c->inst_re = (double *)(c->ws + cv.inst_re);
   c->fm_ptr = (int32_t *)(c->ws + cv.fm_ptr);
   c->fm_rec = (FusedMeas *)(c->ws + cv.fm_rec);
+  c->tm_ptr = (int32_t *)(c->ws + cv.tm_ptr);
+  c->tm_rec = (FusedMeas *)(c->ws + cv.tm_rec);
   c->n_fine_blocks = cv.n_fine_blocks;
   c->n_data_blocks = cv.n_data_blocks;
   c->n_part_blocks = cv.n_fine_blocks + cv.n_data_blocks;

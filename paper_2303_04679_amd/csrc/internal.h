@@ -162,6 +162,9 @@ struct modil_ctx {
   // measurements bucketed per (tile, plane) for the fused channel-flow kernel
   int32_t *fm_ptr = nullptr;
   modil::FusedMeas *fm_rec = nullptr;
+  // measurements bucketed per (instance, tile) for the 2-D tiled engine
+  int32_t *tm_ptr = nullptr;
+  modil::FusedMeas *tm_rec = nullptr;
   bool fused_enabled = true;  // MODIL_OPT_FUSED
   bool fused_ok = false;      // measurements admit the fused kernel
   bool march_enabled = true;  // MODIL_OPT_MARCH
@@ -272,10 +275,23 @@ bool launch_prolong_block(const Levels &G, int l, const T *theta, const T *csrc,
                           hipStream_t s);
 hipError_t launch_adam(modil_ctx *c, const void *theta_in, void *theta_out, void *m, void *v,
                        const void *g, long n, const AdamHost &h);
-hipError_t launch_fine(modil_ctx *c, const void *u, void *g, bool want_grad);
+// generic finest-level kernel (tiled on 2-D problems); with adam given (tiled
+// engine only) also Adam on level 0 of the fields spanning the grid
+hipError_t launch_fine(modil_ctx *c, const void *u, void *g, bool want_grad,
+                       const AdamHost *adam = nullptr, const void *th_in = nullptr,
+                       void *th_out = nullptr, void *m = nullptr, void *v = nullptr);
+// the 2-D engine by tiles: the problems it takes, their fine grid, tile shape
+bool fine_is_2d(const modil_problem &P);
+void fine_2d(const modil_problem &P, int &ny, int &nx);
+void fine_tile_shape(const modil_problem &P, int &tx, int &ty, int &tiles_x, int &tiles_y);
+bool fine_uses_tiles(const modil_ctx *c);
 // most partial slots per instance the generic fine kernels use
 long fine_partial_slots(const modil_problem &P);
-hipError_t launch_colsum(modil_ctx *c, void *g_fine);
+// column sums of the x-only field's contributions; with adam given also Adam
+// on that field's level 0
+hipError_t launch_colsum(modil_ctx *c, void *g_fine, const AdamHost *adam = nullptr,
+                         const void *th_in = nullptr, void *th_out = nullptr, void *m = nullptr,
+                         void *v = nullptr);
 // measurement misfits; with one data block per instance that block also sums
 // the fine and data partials into terms (returns whether it did)
 hipError_t launch_data(modil_ctx *c, const void *u, void *g, bool want_grad, double *terms,

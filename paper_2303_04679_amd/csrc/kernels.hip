@@ -401,12 +401,9 @@ __global__ __launch_bounds__(kBlock) void adam_kernel(const T *__restrict__ th_i
                                                       T eps) {
   const long e = (long)blockIdx.x * kBlock + threadIdx.x;
   if (e >= n) return;
-  const T gg = g[e];
-  const T mm = b1 * m[e] + (T(1) - b1) * gg;
-  const T vv = b2 * v[e] + (T(1) - b2) * gg * gg;
-  m[e] = mm;
-  v[e] = vv;
-  th_out[e] = adam_theta(th_in[e], mm, vv, step, inv_sqrt_bc2, eps);
+  // the same update, in the same form, as Adam fused into the other kernels
+  const AdamArgs<T> A{th_in, th_out, m, v, b1, b2, step, inv_sqrt_bc2, eps};
+  adam_elem(A, (int)e, g[e]);
 }
 
 // ------------------------------------------------------- block-sum of terms
@@ -621,16 +618,28 @@ __device__ inline void star_from_tile(const OpParams &p, const FineFields &ff, c
   }
 }
 
-template <class Op, typename T, int TX, int TY>
-__global__ __launch_bounds__(TX * TY) void fine_tile_kernel(FineArgs<T> A, int tiles_x) {
+// measurements bucketed per (instance, tile): ptr[key] .. ptr[key + 1] index
+// rec; lx, ly are the cell's position among the tile's owned cells
+struct TileMeas {
+  const int32_t *ptr;
+  const FusedMeas *rec;
+};
+
+// ADAM: also Adam on level 0 of every field spanning the grid (A0: level-0
+// pointers of theta_in / theta_out / m / v, the pack layout)
+template <class Op, typename T, int TX, int TY, bool ADAM>
+__global__ __launch_bounds__(TX * TY) void fine_tile_kernel(FineArgs<T> A, int tiles_x, TileMeas M,
+                                                            AdamArgs<T> A0) {
   using FT = FineTile<TX, TY>;
   constexpr int NT = TX * TY, NF = Op::NF, NE = Op::NE;
   __shared__ T Ut[NF][FT::UY][FT::UX];
   __shared__ T St[NF][7][FT::SY][FT::SX];
+  __shared__ T Dt[NF][TY][TX];  // gradient of the data terms at the owned cells
   const int inst = blockIdx.y, tid = threadIdx.x;
   const int x0 = (blockIdx.x % tiles_x) * TX, y0 = (blockIdx.x / tiles_x) * TY;
   const int ny = A.p.n[1], nx = A.p.n[2];
   const T *ub = A.u + (long)inst * A.ff.inst_stride;
+  for (int f = 0; f < NF; ++f) Dt[f][tid / TX][tid % TX] = T(0);
   for (int k = tid; k < FT::UX * FT::UY; k += NT) {
     const int X = k % FT::UX, Y = k / FT::UX, x = x0 - 2 + X, y = y0 - 2 + Y;
     const bool in = x >= 0 && x < nx && y >= 0 && y < ny;
@@ -669,6 +678,25 @@ __global__ __launch_bounds__(TX * TY) void fine_tile_kernel(FineArgs<T> A, int t
       for (int f = 0; f < NF; ++f)
         for (int q = 0; q < 7; ++q) St[f][q][Y][X] = s[f][q];
   }
+  // measurement misfits of the tile's cells (entries of one (field, cell) are
+  // adjacent; the first of a run writes their summed gradient)
+  {
+    const long key = (long)inst * gridDim.x + blockIdx.x;
+    const int e0 = M.ptr[key], e1 = M.ptr[key + 1];
+    for (int e = e0 + tid; e < e1; e += NT) {
+      const FusedMeas me = M.rec[e];
+      const T uv = Ut[me.field][me.ly + 2][me.lx + 2];
+      const double r = (double)uv - me.val;
+      part[me.term] += me.w * r * r;
+      if (A.want_grad &&
+          (e == e0 || M.rec[e - 1].field != me.field || M.rec[e - 1].cell != me.cell)) {
+        double gs = 0.0;
+        for (int j = e; j < e1 && M.rec[j].field == me.field && M.rec[j].cell == me.cell; ++j)
+          gs += 2.0 * M.rec[j].w * ((double)uv - M.rec[j].val);
+        Dt[me.field][me.ly][me.lx] = T(gs);
+      }
+    }
+  }
   if (A.want_grad) {
     __syncthreads();
     const int cx = tid % TX, cy = tid / TX, x = x0 + cx, y = y0 + cy;
@@ -688,10 +716,14 @@ __global__ __launch_bounds__(TX * TY) void fine_tile_kernel(FineArgs<T> A, int t
       }
       const long c = (long)y * nx + x;
       for (int f = 0; f < NF; ++f) {
-        if (f == A.xonly_field)
-          A.gq[(long)inst * A.ncell + c] = gacc[f];
-        else
-          A.g[(long)inst * A.ff.inst_stride + A.ff.off[f] + c] = gacc[f];
+        const T gf = gacc[f] + Dt[f][cy][cx];
+        if (f == A.xonly_field) {
+          A.gq[(long)inst * A.ncell + c] = gf;
+        } else {
+          const long k = (long)inst * A.ff.inst_stride + A.ff.off[f] + c;
+          A.g[k] = gf;
+          if (ADAM) adam_elem(A0, (int)k, gf);
+        }
       }
     }
   }
@@ -704,10 +736,11 @@ __global__ __launch_bounds__(TX * TY) void fine_tile_kernel(FineArgs<T> A, int t
 // group sums are added in group order (fixed order: deterministic).
 constexpr int kColX = 64, kColY = 16;
 
-template <typename T>
+template <typename T, bool ADAM>
 __global__ __launch_bounds__(kColX * kColY) void colsum_kernel(const T *__restrict__ gq,
                                                                T *__restrict__ g, long inst_stride,
-                                                               long foff, int nt, int nx) {
+                                                               long foff, int nt, int nx,
+                                                               AdamArgs<T> A0) {
   __shared__ T sh[kColY][kColX];
   const int inst = blockIdx.y;
   const int ix = blockIdx.x * kColX + threadIdx.x;
@@ -722,7 +755,9 @@ __global__ __launch_bounds__(kColX * kColY) void colsum_kernel(const T *__restri
   if (threadIdx.y == 0 && ix < nx) {
     T s = T(0);
     for (int k = 0; k < kColY; ++k) s += sh[k][threadIdx.x];
-    g[(long)inst * inst_stride + foff + ix] = s;
+    const long e = (long)inst * inst_stride + foff + ix;
+    g[e] = s;
+    if (ADAM) adam_elem(A0, (int)e, s);  // level 0 of the x-only field
   }
 }
 
@@ -980,16 +1015,30 @@ static FineArgs<T> fine_args(modil_ctx *c, const void *u, void *g, bool want_gra
   return A;
 }
 
-// cells per axis of the fine grid of a 2-D problem (y, x)
-static void fine_2d(const modil_problem &P, int &ny, int &nx) {
+void fine_2d(const modil_problem &P, int &ny, int &nx) {
   const int extra = P.centering == MODIL_NODE ? 1 : 0;
   ny = P.dims[0] + extra;
   nx = P.dims[1] + extra;
 }
 
-static bool fine_is_2d(const modil_problem &P) {
+bool fine_is_2d(const modil_problem &P) {
   return P.op == MODIL_OP_BURGERS || P.op == MODIL_OP_HEAT_KX || P.op == MODIL_OP_CAVITY ||
          (P.op == MODIL_OP_POISSON && P.ndim == 2);
+}
+
+void fine_tile_shape(const modil_problem &P, int &tx, int &ty, int &tiles_x, int &tiles_y) {
+  int ny, nx;
+  fine_2d(P, ny, nx);
+  tx = 32;
+  ty = 8;
+  tiles_x = (nx + tx - 1) / tx;
+  tiles_y = (ny + ty - 1) / ty;
+  if ((long)tiles_x * tiles_y * P.batch < 256) {
+    tx = 16;
+    ty = 4;
+    tiles_x = (nx + tx - 1) / tx;
+    tiles_y = (ny + ty - 1) / ty;
+  }
 }
 
 long fine_partial_slots(const modil_problem &P) {
@@ -1004,43 +1053,57 @@ long fine_partial_slots(const modil_problem &P) {
   return slots;
 }
 
-// the tiled engine for one operator: 32 x 8 tiles when they give every
-// compute unit a block, else 16 x 4
+template <typename T>
+static AdamArgs<T> adam_args(const AdamHost *ad, const void *th_in, void *th_out, void *m, void *v) {
+  AdamArgs<T> A{};
+  if (ad) {
+    A.th_in = (const T *)th_in; A.th_out = (T *)th_out; A.m = (T *)m; A.v = (T *)v;
+    A.b1 = T(ad->b1); A.b2 = T(ad->b2); A.step = T(ad->step); A.isb2 = T(ad->isb2); A.eps = T(ad->eps);
+  }
+  return A;
+}
+
+// the tiled engine for one operator (tile shape from fine_tile_shape)
 template <class Op, typename T>
-static void launch_fine_tile(modil_ctx *c, const FineArgs<T> &A) {
-  int ny, nx;
-  fine_2d(c->prob, ny, nx);
-  int tx = (nx + 31) / 32, ty = (ny + 7) / 8;
-  if ((long)tx * ty * c->prob.batch >= 256) {
-    c->fine_slots = (long)tx * ty;
-    fine_tile_kernel<Op, T, 32, 8><<<dim3(tx * ty, c->prob.batch), 256, 0, c->stream>>>(A, tx);
+static void launch_fine_tile(modil_ctx *c, const FineArgs<T> &A, const AdamArgs<T> &A0, bool adam) {
+  int tx, ty, nbx, nby;
+  fine_tile_shape(c->prob, tx, ty, nbx, nby);
+  c->fine_slots = (long)nbx * nby;
+  const TileMeas M{c->tm_ptr, c->tm_rec};
+  const dim3 grid(nbx * nby, c->prob.batch);
+  if (tx == 32) {
+    if (adam) fine_tile_kernel<Op, T, 32, 8, true><<<grid, 256, 0, c->stream>>>(A, nbx, M, A0);
+    else fine_tile_kernel<Op, T, 32, 8, false><<<grid, 256, 0, c->stream>>>(A, nbx, M, A0);
   } else {
-    tx = (nx + 15) / 16;
-    ty = (ny + 3) / 4;
-    c->fine_slots = (long)tx * ty;
-    fine_tile_kernel<Op, T, 16, 4><<<dim3(tx * ty, c->prob.batch), 64, 0, c->stream>>>(A, tx);
+    if (adam) fine_tile_kernel<Op, T, 16, 4, true><<<grid, 64, 0, c->stream>>>(A, nbx, M, A0);
+    else fine_tile_kernel<Op, T, 16, 4, false><<<grid, 64, 0, c->stream>>>(A, nbx, M, A0);
   }
 }
 
 template <typename T>
-static hipError_t launch_fine_t(modil_ctx *c, const void *u, void *g, bool want_grad) {
+static hipError_t launch_fine_t(modil_ctx *c, const void *u, void *g, bool want_grad,
+                                const AdamHost *adam, const void *th_in, void *th_out, void *m,
+                                void *v) {
   const FineArgs<T> A = fine_args<T>(c, u, g, want_grad);
+  const AdamArgs<T> A0 = adam_args<T>(adam, th_in, th_out, m, v);
+  const bool ad = adam != nullptr;
   const dim3 grid(nblk(A.ncell), c->prob.batch);
   const modil_problem &P = c->prob;
   c->fine_slots = nblk(A.ncell);
-  if (c->tile_enabled && fine_is_2d(P)) {
+  if (fine_uses_tiles(c)) {
     switch (P.op) {
       case MODIL_OP_POISSON:
-        if (P.centering == MODIL_NODE) launch_fine_tile<OpPoissonNode, T>(c, A);
-        else launch_fine_tile<OpPoisson, T>(c, A);
+        if (P.centering == MODIL_NODE) launch_fine_tile<OpPoissonNode, T>(c, A, A0, ad);
+        else launch_fine_tile<OpPoisson, T>(c, A, A0, ad);
         break;
-      case MODIL_OP_BURGERS: launch_fine_tile<OpBurgers, T>(c, A); break;
-      case MODIL_OP_HEAT_KX: launch_fine_tile<OpHeat, T>(c, A); break;
-      case MODIL_OP_CAVITY: launch_fine_tile<OpNS<2, 0>, T>(c, A); break;
+      case MODIL_OP_BURGERS: launch_fine_tile<OpBurgers, T>(c, A, A0, ad); break;
+      case MODIL_OP_HEAT_KX: launch_fine_tile<OpHeat, T>(c, A, A0, ad); break;
+      case MODIL_OP_CAVITY: launch_fine_tile<OpNS<2, 0>, T>(c, A, A0, ad); break;
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
   }
+  if (ad) return hipErrorInvalidValue;  // the per-cell kernel has no Adam
   switch (P.op) {
     case MODIL_OP_POISSON:
       if (P.centering == MODIL_NODE)
@@ -1069,26 +1132,41 @@ static hipError_t launch_fine_t(modil_ctx *c, const void *u, void *g, bool want_
   return hipGetLastError();
 }
 
-hipError_t launch_fine(modil_ctx *c, const void *u, void *g, bool want_grad) {
-  return c->prob.dtype == MODIL_F64 ? launch_fine_t<double>(c, u, g, want_grad)
-                                    : launch_fine_t<float>(c, u, g, want_grad);
+bool fine_uses_tiles(const modil_ctx *c) { return c->tile_enabled && fine_is_2d(c->prob); }
+
+hipError_t launch_fine(modil_ctx *c, const void *u, void *g, bool want_grad, const AdamHost *adam,
+                       const void *th_in, void *th_out, void *m, void *v) {
+  return c->prob.dtype == MODIL_F64
+             ? launch_fine_t<double>(c, u, g, want_grad, adam, th_in, th_out, m, v)
+             : launch_fine_t<float>(c, u, g, want_grad, adam, th_in, th_out, m, v);
 }
 
-hipError_t launch_colsum(modil_ctx *c, void *g_fine) {
+hipError_t launch_colsum(modil_ctx *c, void *g_fine, const AdamHost *adam, const void *th_in,
+                         void *th_out, void *m, void *v) {
   int xf = -1;
   for (int f = 0; f < c->lay.n_fields; ++f)
     if (field_is_x_only(c->prob, f)) xf = f;
   if (xf < 0) return hipSuccess;
   const int nt = c->prob.dims[0], nx = c->prob.dims[1];
   const dim3 grid((nx + kColX - 1) / kColX, c->prob.batch), block(kColX, kColY);
-  if (c->prob.dtype == MODIL_F64)
-    colsum_kernel<double><<<grid, block, 0, c->stream>>>(
-        (const double *)c->gq_buf, (double *)g_fine, c->lay.level_stride[0],
-        c->lay.field_offset[0][xf], nt, nx);
-  else
-    colsum_kernel<float><<<grid, block, 0, c->stream>>>(
-        (const float *)c->gq_buf, (float *)g_fine, c->lay.level_stride[0],
-        c->lay.field_offset[0][xf], nt, nx);
+  const long st = c->lay.level_stride[0], fo = c->lay.field_offset[0][xf];
+  if (c->prob.dtype == MODIL_F64) {
+    const AdamArgs<double> A0 = adam_args<double>(adam, th_in, th_out, m, v);
+    if (adam)
+      colsum_kernel<double, true><<<grid, block, 0, c->stream>>>(
+          (const double *)c->gq_buf, (double *)g_fine, st, fo, nt, nx, A0);
+    else
+      colsum_kernel<double, false><<<grid, block, 0, c->stream>>>(
+          (const double *)c->gq_buf, (double *)g_fine, st, fo, nt, nx, A0);
+  } else {
+    const AdamArgs<float> A0 = adam_args<float>(adam, th_in, th_out, m, v);
+    if (adam)
+      colsum_kernel<float, true><<<grid, block, 0, c->stream>>>(
+          (const float *)c->gq_buf, (float *)g_fine, st, fo, nt, nx, A0);
+    else
+      colsum_kernel<float, false><<<grid, block, 0, c->stream>>>(
+          (const float *)c->gq_buf, (float *)g_fine, st, fo, nt, nx, A0);
+  }
   return hipGetLastError();
 }
 
