@@ -37,12 +37,17 @@ def parse():
                     help="budget of the oracle CPU-baseline sample (0 disables it)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (for counter scaling)")
-    ap.add_argument("--optimizer", choices=("adam", "lbfgs"), default="adam")
+    ap.add_argument("--optimizer", choices=("adam", "lbfgs", "autograd"), default="adam",
+                    help="adam: the library's fused iteration; lbfgs: L-BFGS on the device; autograd: "
+                         "the loss as a torch.autograd.Function (adjoint kernels in backward) with "
+                         "torch.optim.Adam")
+    ap.add_argument("--loop", choices=("run", "step"), default="run",
+                    help="Adam iterations through modil_run (all K in one call) or one modil_step per call")
     ap.add_argument("--history", type=int, default=50, help="L-BFGS pairs")
     return ap.parse_args()
 
 
-def alg_bytes(ctx, spec, fused, adam=True):
+def alg_bytes(ctx, spec, fused, adam=True, tiled=False):
     """Algorithmic bytes of one launch of each kernel class and of one iteration.
 
     Every array a kernel must read or write is counted once; halo re-reads
@@ -53,7 +58,9 @@ def alg_bytes(ctx, spec, fused, adam=True):
     finest level and the prolonged level 1, and writes theta', m', v' and the
     finest gradient; the restriction class reads each gradient level, writes
     the next one and applies Adam to it.  Generic path: the fine kernel reads
-    the prolonged field and writes the finest gradient; Adam is one sweep.
+    the prolonged field and writes the finest gradient; Adam is one sweep, or
+    (2-D tiled engine) Adam of level 0 sits in the fine kernel and that of the
+    coarse levels in the restriction, as in the fused path.
     """
     b = 4 if spec.dtype == "f32" else 8
     lay = ctx.lay
@@ -69,6 +76,11 @@ def alg_bytes(ctx, spec, fused, adam=True):
     elif fused:
         fine = (7 * size[0] + (size[1] if L > 1 else 0)) * b + chi
         horner = sum((2 * size[l] + size[l + 1]) * b for l in range(1, L - 1))
+        restrict = sum((size[l] + 7 * size[l + 1]) * b for l in range(L - 1))
+        adam = 0
+    elif tiled and adam:
+        fine = 8 * size[0] * b + chi
+        horner = sum((2 * size[l] + size[l + 1]) * b for l in range(L - 1))
         restrict = sum((size[l] + 7 * size[l + 1]) * b for l in range(L - 1))
         adam = 0
     else:
@@ -175,6 +187,8 @@ def main():
     ctx, theta = configs.build(wl)
     if args.optimizer == "lbfgs":
         return main_lbfgs(args, wl, ctx, theta)
+    if args.optimizer == "autograd":
+        return main_autograd(args, wl, ctx, theta)
     a, b = theta, ctx.new_pack()
     m, v = ctx.new_pack(), ctx.new_pack()
     terms = torch.empty((spec.batch, 5), dtype=torch.float64, device=ctx.device)
@@ -182,7 +196,13 @@ def main():
 
     def run(n):
         nonlocal a, b, step
-        for _ in range(n):
+        if args.loop == "run":  # n iterations in one library call
+            out = ctx.run(a, b, m, v, step + 1, n, lr=wl.lr, terms=terms)
+            if out is b:
+                a, b = b, a
+            step += n
+            return
+        for _ in range(n):  # one library call per iteration
             step += 1
             ctx.step(a, b, m, v, step, lr=wl.lr, terms=terms)
             a, b = b, a
@@ -214,7 +234,7 @@ def main():
         kern[name] = {"total_ms": tot, "launches": cnt, "avg_ms": tot / max(cnt, 1)}
     ctx.profile(False)
     fused = ctx.fused_active()
-    ab = alg_bytes(ctx, spec, fused)
+    ab = alg_bytes(ctx, spec, fused, tiled=ctx.tiled_active())
     dom = max(CLASSES, key=lambda n: kern[n]["total_ms"])
     avg_s = kern[dom]["avg_ms"] * 1e-3
     achieved = ab[dom] / avg_s / 1e9 if avg_s > 0 else 0.0
@@ -248,7 +268,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "grid": "x".join(str(d) for d in spec.dims),
                    "levels": spec.n_levels, "fields": len(spec.fields), "params": int(ctx.lay.total),
-                   "batch": spec.batch, "optimizer": "adam", "loss_reduction": "f64"},
+                   "batch": spec.batch, "optimizer": "adam", "loss_reduction": "f64",
+                   "loop": "modil_run" if args.loop == "run" else "modil_step"},
         "hbm_gbs_algorithmic": it_gbs,
         "iteration_roofline_frac": it_gbs / HBM_PEAK_GBS,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
@@ -328,6 +349,60 @@ def main_lbfgs(args, wl, ctx, theta):
         "cpu_baseline": None,
     }
     lb.close()
+    print(json.dumps(out), flush=True)
+
+
+def main_autograd(args, wl, ctx, theta):
+    """One step = loss forward (loss kernels), backward (the adjoint kernels,
+    prolonged field recomputed) and torch.optim.Adam over the pack: the
+    unfused differentiation pattern, timed apart from the fused iteration."""
+    import torch
+
+    from paper_2303_04679_amd.autograd import modil_loss
+    spec = wl.spec
+    th = torch.nn.Parameter(theta.clone())
+    opt = torch.optim.Adam([th], lr=wl.lr)
+
+    def run(n):
+        for _ in range(n):
+            opt.zero_grad(set_to_none=False)
+            loss = modil_loss(th, ctx)
+            loss.backward()
+            opt.step()
+        return loss
+
+    run(args.warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    loss = run(args.steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ctx.check()
+    ms = e0.elapsed_time(e1)
+    b = 4 if spec.dtype == "f32" else 8
+    S = int(ctx.lay.total)
+    out = {
+        "metric": "fine-grid cell-iters/s",
+        "value": spec.fine_cells * spec.batch * args.steps / (ms * 1e-3),
+        "unit": "cell-iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": spec.dtype,
+        "data": "synthetic",
+        "config": {"workload": wl.name, "grid": "x".join(str(d) for d in spec.dims),
+                   "levels": spec.n_levels, "fields": len(spec.fields), "params": S,
+                   "batch": spec.batch, "optimizer": "autograd.Function + torch.optim.Adam",
+                   "loss_reduction": "f64"},
+        "unfused_bytes_per_step": 9 * b * S,
+        "final_loss": float(loss),
+        "cpu_baseline": None,
+    }
     print(json.dumps(out), flush=True)
 
 

@@ -226,6 +226,13 @@ int modil_set_instance_scalar(modil_ctx *ctx, int32_t instance, int32_t which, d
  *   if not NULL), gradient, and Adam into theta_out.  theta_out must differ
  *   from theta_in (tiles read neighbours of theta_in while theta_out is
  *   written) -> MODIL_ERR_INVALID_ARG.
+ * modil_run: n_steps >= 1 iterations of modil_step with steps
+ *   step0 .. step0 + n_steps - 1, theta alternating between the two packs:
+ *   step step0 + k reads theta_a and writes theta_b for even k, the reverse
+ *   for odd k, so the result is in theta_b if n_steps is odd, else theta_a.
+ *   Loss terms of the last iteration go to terms (if not NULL).  The same
+ *   arithmetic as calling modil_step n_steps times, without a host round
+ *   trip per iteration.  theta_a must differ from theta_b.
  * modil_residual_metric: r[instance] = RMS over cells and PDE equations of
  *   the cell-integrated residual, sqrt(sum (V R)^2 / (n_eq * n_cells)),
  *   evaluated in double from the PDE term.                               */
@@ -237,6 +244,8 @@ int modil_adam(modil_ctx *ctx, const void *theta_in, void *theta_out, void *m, v
                const void *grad, const modil_adam_hp *hp, int64_t step);
 int modil_step(modil_ctx *ctx, const void *theta_in, void *theta_out, void *m, void *v,
                const modil_adam_hp *hp, int64_t step, double *terms);
+int modil_run(modil_ctx *ctx, void *theta_a, void *theta_b, void *m, void *v,
+              const modil_adam_hp *hp, int64_t step0, int32_t n_steps, double *terms);
 int modil_residual_metric(modil_ctx *ctx, const void *theta_pack, double *r);
 
 /* ---- options --------------------------------------------------------------

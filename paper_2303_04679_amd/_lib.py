@@ -120,6 +120,8 @@ _SIGS = {
     "modil_loss_grad": (_I, [_P, _P, _P, _P]),
     "modil_adam": (_I, [_P, _P, _P, _P, _P, _P, ctypes.POINTER(AdamHP), ctypes.c_int64]),
     "modil_step": (_I, [_P, _P, _P, _P, _P, ctypes.POINTER(AdamHP), ctypes.c_int64, _P]),
+    "modil_run": (_I, [_P, _P, _P, _P, _P, ctypes.POINTER(AdamHP), ctypes.c_int64, ctypes.c_int32,
+                       _P]),
     "modil_residual_metric": (_I, [_P, _P, _P]),
     "modil_check": (_I, [_P]),
     "modil_set_option": (_I, [_P, ctypes.c_int32, ctypes.c_int64]),

@@ -350,13 +350,18 @@ bool use_fused(const modil_ctx *c) {
 
 // Loss terms at theta; with grad the gradient of every level; with adam
 // also one Adam step theta -> th_out on every level.
+// carry_in: w_buf already holds the Horner tail for theta (carried by the
+// previous iteration); carry_out: have the restriction tail also form the
+// Horner tail for th_out (carried reports whether it did).
 int evaluate(modil_ctx *c, const void *theta, void *grad, double *terms, const AdamHost *adam = nullptr,
-             void *th_out = nullptr, void *m = nullptr, void *v = nullptr) {
+             void *th_out = nullptr, void *m = nullptr, void *v = nullptr, bool carry_in = false,
+             bool carry_out = false, bool *carried = nullptr) {
   const bool want = grad != nullptr;
+  if (carried) *carried = false;
   if (use_fused(c) && want) {
     {
       Timed t(c, 1);
-      HIP_OR_RETURN(c, launch_horner(c, theta, nullptr, true), "prolong");
+      HIP_OR_RETURN(c, launch_horner(c, theta, nullptr, true, carry_in), "prolong");
     }
     {
       Timed t(c, 0);
@@ -373,7 +378,8 @@ int evaluate(modil_ctx *c, const void *theta, void *grad, double *terms, const A
     bool summed = false;
     {
       Timed t(c, 2);
-      HIP_OR_RETURN(c, launch_restrict_chain(c, grad, 0, theta, th_out, m, v, adam, &sum, &summed),
+      HIP_OR_RETURN(c, launch_restrict_chain(c, grad, 0, theta, th_out, m, v, adam, &sum, &summed,
+                                             carry_out, carried),
                     "restrict");
     }
     if (!summed) {
@@ -384,12 +390,13 @@ int evaluate(modil_ctx *c, const void *theta, void *grad, double *terms, const A
   }
   const void *u = theta;
   bool summed = false;  // the data kernel summed the partials
+  const bool tiled = fine_uses_tiles(c);
   if (c->prob.n_levels > 1) {
     Timed t(c, 1);
-    HIP_OR_RETURN(c, launch_horner(c, theta, nullptr, false), "prolong");
+    HIP_OR_RETURN(c, launch_horner(c, theta, nullptr, false, tiled && carry_in), "prolong");
     u = c->w_buf;
   }
-  if (fine_uses_tiles(c)) {
+  if (tiled) {
     // 2-D tiled engine: the tile kernel also forms the data terms and, with
     // Adam, updates level 0; the restriction kernels update the coarse levels
     // and the restriction tail sums the loss partials
@@ -411,7 +418,8 @@ int evaluate(modil_ctx *c, const void *theta, void *grad, double *terms, const A
         HIP_OR_RETURN(c, launch_colsum(c, grad, adam, theta, th_out, m, v), "column sum");
       }
       Timed t(c, 2);
-      HIP_OR_RETURN(c, launch_restrict_chain(c, grad, 0, theta, th_out, m, v, adam, &sum, &summed),
+      HIP_OR_RETURN(c, launch_restrict_chain(c, grad, 0, theta, th_out, m, v, adam, &sum, &summed,
+                                             carry_out, carried),
                     "restrict");
     }
     if (!summed) {
@@ -766,6 +774,30 @@ int modil_step(modil_ctx *c, const void *th_in, void *th_out, void *m, void *v,
   if (th_in == th_out) return fail(c, MODIL_ERR_INVALID_ARG, "theta_out must differ from theta_in");
   const AdamHost ah = adam_host(hp, step);
   return evaluate(c, th_in, c->g_buf, terms ? terms : c->terms_tmp, &ah, th_out, m, v);
+}
+
+int modil_run(modil_ctx *c, void *th_a, void *th_b, void *m, void *v, const modil_adam_hp *hp,
+              int64_t step0, int32_t n_steps, double *terms) {
+  int st = ready(c);
+  if (st) return st;
+  if (n_steps < 1) return fail(c, MODIL_ERR_INVALID_ARG, "n_steps must be >= 1");
+  st = check_hp(c, hp, step0);
+  if (st) return st;
+  if (!th_a || !th_b || !m || !v) return fail(c, MODIL_ERR_INVALID_ARG, "NULL pointer");
+  if (th_a == th_b) return fail(c, MODIL_ERR_INVALID_ARG, "theta_b must differ from theta_a");
+  // each iteration but the last has its restriction tail form the next
+  // iteration's Horner tail (same values, one launch fewer)
+  bool carried = false;
+  for (int32_t k = 0; k < n_steps; ++k) {
+    const AdamHost ah = adam_host(hp, step0 + k);
+    void *in = (k & 1) ? th_b : th_a, *out = (k & 1) ? th_a : th_b;
+    double *t = (k == n_steps - 1 && terms) ? terms : c->terms_tmp;
+    bool next = false;
+    st = evaluate(c, in, c->g_buf, t, &ah, out, m, v, carried, k + 1 < n_steps, &next);
+    if (st) return st;
+    carried = next;
+  }
+  return MODIL_OK;
 }
 
 int modil_residual_metric(modil_ctx *c, const void *theta, double *r) {

@@ -243,7 +243,9 @@ struct AdamHost {
 // and return hipSuccess or the launch error.
 // Horner chain: w_l for every coarse level into w_buf and the finest field
 // into fine_dst (w_buf level 0 if null); stops at level 1 when skip_fine.
-hipError_t launch_horner(modil_ctx *c, const void *theta, void *fine_dst, bool skip_fine);
+// skip_tail: the small levels' w are in w_buf already (carried)
+hipError_t launch_horner(modil_ctx *c, const void *theta, void *fine_dst, bool skip_fine,
+                         bool skip_tail = false);
 // g_{l+1} = T^T g_l for l >= from_level (pack layout in g); with adam also
 // Adam on every level it produces.
 // A final sum of loss partials that a later kernel can carry out:
@@ -260,7 +262,8 @@ struct TermSum {
 // also does that sum when it can (summed tells whether it did).
 hipError_t launch_restrict_chain(modil_ctx *c, void *g, int from_level, const void *th_in,
                                  void *th_out, void *m, void *v, const AdamHost *adam,
-                                 const TermSum *sum = nullptr, bool *summed = nullptr);
+                                 const TermSum *sum = nullptr, bool *summed = nullptr,
+                                 bool carry = false, bool *carried = nullptr);
 // Marching restriction of level l -> l+1 with optional Adam (restrict_march.hip);
 // returns false, launching nothing, when the level's shape does not admit it.
 // tile: 16 * rows + planes per wave, 0 = automatic.

@@ -238,13 +238,12 @@ __device__ inline void field_index(const Levels &G, int l, int f, int e, int (&i
 // w_{L-1} = theta_{L-1}, then w_l = theta_l + T w_{l+1} for l = L-2 .. l_stop;
 // every w_l it produces is also written to w (pack layout).  Level l sits in
 // LDS buffer (l - l_stop) % 2, sized for levels l_stop and l_stop + 1.
+// The block's part: field f of instance inst, LDS at smem.
 template <typename T>
-__global__ __launch_bounds__(1024) void horner_tail_kernel(Levels G, int l_stop, int cap0,
-                                                           const T *__restrict__ theta, T *w) {
+__device__ inline void horner_tail_block(const Levels &G, int l_stop, int cap0, const T *theta, T *w,
+                                         int inst, int f, T *smem) {
   constexpr int kPf = 4;  // theta values per thread of the last (largest) level, loaded first
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T *buf[2] = {reinterpret_cast<T *>(smem_raw), reinterpret_cast<T *>(smem_raw) + cap0};
-  const int inst = blockIdx.x / G.nf, f = blockIdx.x % G.nf;
+  T *buf[2] = {smem, smem + cap0};
   const int bd = blockDim.x, tid = threadIdx.x;
   const int bstop = G.off[l_stop] + inst * G.stride[l_stop] + G.foff[l_stop][f];
   const int nstop = field_cells(G, l_stop, f);
@@ -292,6 +291,14 @@ __global__ __launch_bounds__(1024) void horner_tail_kernel(Levels G, int l_stop,
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(1024) void horner_tail_kernel(Levels G, int l_stop, int cap0,
+                                                           const T *__restrict__ theta, T *w) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  horner_tail_block(G, l_stop, cap0, theta, w, (int)(blockIdx.x / G.nf), (int)(blockIdx.x % G.nf),
+                    reinterpret_cast<T *>(smem_raw));
+}
+
 // --------------------------------------------------------------- restriction
 // g_{l+1} = T^T g_l (pack layout in g); with ADAM also Adam on level l+1
 template <typename T, bool ADAM>
@@ -317,9 +324,19 @@ __global__ __launch_bounds__(kBlock) void restrict_kernel(Levels G, int l, T *g,
 // block, in LDS, with Adam on every level produced; level l_lo is read from g,
 // every level produced is written back to g.  Two LDS buffers sized for
 // levels l_lo and l_lo + 1 alternate.
+// With H.w set (and Adam), each block then does the Horner tail of its field
+// for the updated theta (horner_tail_block with theta_out), so the next
+// iteration starts from it.
+template <typename T>
+struct CarryTail {
+  T *w = nullptr;
+  int l_stop = 0, cap0 = 0;
+};
+
 template <typename T, bool ADAM>
 __global__ __launch_bounds__(1024) void restrict_tail_kernel(Levels G, int l_lo, int cap0, T *g,
-                                                             AdamArgs<T> A, TermSum S) {
+                                                             AdamArgs<T> A, TermSum S,
+                                                             CarryTail<T> H) {
   constexpr int kPf = 2;  // outputs per thread of the first level whose Adam state is prefetched
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *cur = reinterpret_cast<T *>(smem_raw);
@@ -390,6 +407,9 @@ __global__ __launch_bounds__(1024) void restrict_tail_kernel(Levels G, int l_lo,
     cur = nxt;
     nxt = t;
   }
+  if (ADAM && H.w)
+    horner_tail_block(G, H.l_stop, H.cap0, (const T *)A.th_out, H.w, inst, f,
+                      reinterpret_cast<T *>(smem_raw));
 }
 
 // ---------------------------------------------------------------------- Adam
@@ -870,26 +890,35 @@ static bool lds_ready(K kernel, size_t bytes) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess;
 }
 
+// The Horner tail: w_{L-2} .. w_lt by one launch in LDS (at least two levels,
+// none below 1; level 0 goes to the finest field).  False if it does not apply.
+static bool horner_tail_plan(const modil_ctx *c, const Levels &G, size_t elem, int &lt, int &cap0,
+                             size_t &bytes) {
+  if (!c->tail_enabled || G.L < 3) return false;
+  lt = tail_level(G, 1, elem, c->lds_budget - 1024, kTailCapProlong, false);
+  if (lt > G.L - 3) return false;
+  cap0 = (int)max_field(G, lt);
+  bytes = (size_t)(cap0 + max_field(G, lt + 1)) * elem;
+  return true;
+}
+
+// skip_tail: the Horner tail for theta is already in w_buf (carried by the
+// previous iteration's restriction tail)
 template <typename T>
-static hipError_t horner_t(modil_ctx *c, const void *theta_v, void *fine_dst_v, bool skip_fine) {
+static hipError_t horner_t(modil_ctx *c, const void *theta_v, void *fine_dst_v, bool skip_fine,
+                           bool skip_tail) {
   const Levels G = levels_of(c);
   const T *theta = (const T *)theta_v;
   T *w = (T *)c->w_buf;
   T *fine_dst = fine_dst_v ? (T *)fine_dst_v : w;
   if (G.L == 1) return hipSuccess;
   int l = G.L - 2;
-  // the tail produces w_{L-2} .. w_lt (at least two levels, none below 1;
-  // level 0 goes to fine_dst)
-  int lt = c->tail_enabled
-               ? tail_level(G, 1, sizeof(T), c->lds_budget, kTailCapProlong, false)
-               : G.L;
-  if (lt <= G.L - 3) {
-    const int cap0 = (int)max_field(G, lt);
-    const size_t bytes = (size_t)(cap0 + max_field(G, lt + 1)) * sizeof(T);
-    if (lds_ready(horner_tail_kernel<T>, bytes)) {
+  int lt, cap0;
+  size_t bytes;
+  if (horner_tail_plan(c, G, sizeof(T), lt, cap0, bytes) && lds_ready(horner_tail_kernel<T>, bytes)) {
+    if (!skip_tail)
       horner_tail_kernel<T><<<G.batch * G.nf, 1024, bytes, c->stream>>>(G, lt, cap0, theta, w);
-      l = lt - 1;
-    }
+    l = lt - 1;
   }
   const int l_end = skip_fine ? 1 : 0;
   for (; l >= l_end; --l) {
@@ -903,16 +932,18 @@ static hipError_t horner_t(modil_ctx *c, const void *theta_v, void *fine_dst_v, 
   return hipGetLastError();
 }
 
-hipError_t launch_horner(modil_ctx *c, const void *theta, void *fine_dst, bool skip_fine) {
-  return c->prob.dtype == MODIL_F64 ? horner_t<double>(c, theta, fine_dst, skip_fine)
-                                    : horner_t<float>(c, theta, fine_dst, skip_fine);
+hipError_t launch_horner(modil_ctx *c, const void *theta, void *fine_dst, bool skip_fine,
+                         bool skip_tail) {
+  return c->prob.dtype == MODIL_F64 ? horner_t<double>(c, theta, fine_dst, skip_fine, skip_tail)
+                                    : horner_t<float>(c, theta, fine_dst, skip_fine, skip_tail);
 }
 
 template <typename T>
 static hipError_t restrict_t(modil_ctx *c, void *g_v, int from, const void *th_in, void *th_out,
                              void *m, void *v, const AdamHost *ad, const TermSum *sum,
-                             bool *summed) {
+                             bool *summed, bool carry, bool *carried) {
   if (summed) *summed = false;
+  if (carried) *carried = false;
   const Levels G = levels_of(c);
   T *g = (T *)g_v;
   AdamArgs<T> A{};
@@ -943,10 +974,24 @@ static hipError_t restrict_t(modil_ctx *c, void *g_v, int from, const void *th_i
   if (lt + 1 < G.L) {
     const TermSum S = sum ? *sum : TermSum{};
     const int blocks = G.batch * G.nf + (sum ? G.batch : 0);
+    // carry the next iteration's Horner tail when its LDS fits beside
+    CarryTail<T> H;
+    size_t lds = bytes;
+    int lth, caph;
+    size_t bytes_h;
+    if (carry && ad && horner_tail_plan(c, G, sizeof(T), lth, caph, bytes_h) &&
+        lds_ready(horner_tail_kernel<T>, bytes_h) &&
+        lds_ready(restrict_tail_kernel<T, true>, std::max(bytes, bytes_h))) {
+      H.w = (T *)c->w_buf;
+      H.l_stop = lth;
+      H.cap0 = caph;
+      lds = std::max(bytes, bytes_h);
+      if (carried) *carried = true;
+    }
     if (ad)
-      restrict_tail_kernel<T, true><<<blocks, 1024, bytes, c->stream>>>(G, lt, cap0, g, A, S);
+      restrict_tail_kernel<T, true><<<blocks, 1024, lds, c->stream>>>(G, lt, cap0, g, A, S, H);
     else
-      restrict_tail_kernel<T, false><<<blocks, 1024, bytes, c->stream>>>(G, lt, cap0, g, A, S);
+      restrict_tail_kernel<T, false><<<blocks, 1024, lds, c->stream>>>(G, lt, cap0, g, A, S, H);
     if (summed) *summed = sum != nullptr;
   }
   return hipGetLastError();
@@ -954,10 +999,10 @@ static hipError_t restrict_t(modil_ctx *c, void *g_v, int from, const void *th_i
 
 hipError_t launch_restrict_chain(modil_ctx *c, void *g, int from, const void *th_in, void *th_out,
                                  void *m, void *v, const AdamHost *adam, const TermSum *sum,
-                                 bool *summed) {
+                                 bool *summed, bool carry, bool *carried) {
   return c->prob.dtype == MODIL_F64
-             ? restrict_t<double>(c, g, from, th_in, th_out, m, v, adam, sum, summed)
-             : restrict_t<float>(c, g, from, th_in, th_out, m, v, adam, sum, summed);
+             ? restrict_t<double>(c, g, from, th_in, th_out, m, v, adam, sum, summed, carry, carried)
+             : restrict_t<float>(c, g, from, th_in, th_out, m, v, adam, sum, summed, carry, carried);
 }
 
 hipError_t launch_adam(modil_ctx *c, const void *th_in, void *th_out, void *m, void *v,

@@ -108,6 +108,7 @@ class Context:
 
     def __init__(self, spec: ProblemSpec, device="cuda", stream: Optional[torch.cuda.Stream] = None):
         self.spec = spec
+        self._tile = True  # MODIL_OPT_TILE
         self.device = torch.device(device)
         if self.device.type == "cuda" and self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
@@ -242,6 +243,18 @@ class Context:
                                    ctypes.byref(hp), int(step), _ptr(terms)), self.h)
         return terms
 
+    def run(self, theta_a, theta_b, m, v, step0, n_steps, lr=1e-3, beta1=0.9, beta2=0.999,
+            eps=1e-8, terms=None):
+        """n_steps iterations (steps step0 ..) alternating theta_a -> theta_b ->
+        theta_a ...; returns the pack holding the result (theta_b if n_steps
+        is odd).  Loss terms of the last iteration go to terms if given."""
+        hp = L.AdamHP(lr, beta1, beta2, eps)
+        for t, n in ((theta_a, "theta_a"), (theta_b, "theta_b"), (m, "m"), (v, "v")):
+            self._check_pack(t, n)
+        L.check(L.lib().modil_run(self.h, _ptr(theta_a), _ptr(theta_b), _ptr(m), _ptr(v),
+                                  ctypes.byref(hp), int(step0), int(n_steps), _ptr(terms)), self.h)
+        return theta_b if n_steps % 2 else theta_a
+
     def residual_metric(self, theta, out=None):
         self._check_pack(theta, "theta")
         out = torch.empty((self.spec.batch,), dtype=torch.float64, device=self.device) if out is None else out
@@ -259,6 +272,10 @@ class Context:
         L.check(min(r, 0), self.h)
         return r == 1
 
+    def tiled_active(self) -> bool:
+        """True if the generic engine runs by LDS tiles (2-D problems, option on)."""
+        return self.spec.ndim == 2 and self._tile
+
     def set_march(self, enabled: bool):
         """Transfer levels with the lane-shuffle kernels (marching restriction,
         block prolongation) where a level admits them (default), or with the
@@ -273,6 +290,7 @@ class Context:
         """Generic engine on 2-D problems: LDS tiles forming every residual
         once (default), or the per-cell kernel."""
         L.check(L.lib().modil_set_option(self.h, L.OPT_TILE, 1 if enabled else 0), self.h)
+        self._tile = bool(enabled)
 
     def set_march_tile(self, rows: int = 0, planes: int = 0):
         """Coarse rows and planes per wave of the marching kernel (0, 0: automatic)."""

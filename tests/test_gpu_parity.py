@@ -162,6 +162,18 @@ def test_step_is_loss_grad_then_adam_f32(op, dims, L):
     assert_terms(terms[0].cpu().numpy(), rterms, 1e-5, op)
 
 
+def test_run_argument_errors():
+    need_gpu()
+    from paper_2303_04679_amd import _lib as L
+    spec = case("poisson", (16, 16), 2, seed=1)
+    ctx = context_of(spec, "f64")
+    a, b, m, v = ctx.new_pack(), ctx.new_pack(), ctx.new_pack(), ctx.new_pack()
+    for args in ((a, a, m, v, 1, 3), (a, b, m, v, 1, 0), (a, b, m, v, 0, 2)):
+        with pytest.raises(L.ModilError) as ei:
+            ctx.run(*args)
+        assert ei.value.status == L.ERR_INVALID_ARG
+
+
 def test_deterministic():
     need_gpu()
     spec = case("ns3d", (16, 16, 16), 3, seed=9, with_forcing=True)
@@ -346,3 +358,28 @@ def test_fused_channel_batch():
         rt, rg = ops.loss_and_grad(s, lvs[b])
         assert_terms(terms[b].cpu().numpy(), rt, TOL["f32"], b)
         assert_levels(levels_of(ctx, grad, b), rg, TOL["f32"], b)
+
+
+@pytest.mark.parametrize("op,dims,L,dtype", [("cavity", (32, 48), 4, "f32"), ("heat", (32, 64), 4, "f64"),
+                                             ("ns3d", (16, 16, 32), 3, "f32")])
+@pytest.mark.parametrize("n", [1, 4, 5])
+def test_run_equals_steps(op, dims, L, dtype, n):
+    """modil_run of n iterations equals n modil_step calls bit for bit
+    (packs, moments and the last loss terms)."""
+    need_gpu()
+    spec = case(op, dims, L, seed=21, with_forcing=op != "poisson")
+    lv = rounded(_levels(spec, 22), dtype)
+    ctx = context_of(spec, dtype)
+    th0 = pack_of(ctx, [lv])
+    a, b, m, v = th0.clone(), ctx.new_pack(), ctx.new_pack(), ctx.new_pack()
+    t_run = torch.empty((1, 5), dtype=torch.float64, device="cuda")
+    res = ctx.run(a, b, m, v, 3, n, lr=1e-3, terms=t_run)
+    assert res is (b if n % 2 else a)
+    a2, b2, m2, v2 = th0.clone(), ctx.new_pack(), ctx.new_pack(), ctx.new_pack()
+    t_step = torch.empty((1, 5), dtype=torch.float64, device="cuda")
+    for k in range(n):
+        ctx.step(a2, b2, m2, v2, 3 + k, lr=1e-3, terms=t_step)
+        a2, b2 = b2, a2
+    torch.cuda.synchronize()
+    assert torch.equal(res, a2) and torch.equal(m, m2) and torch.equal(v, v2)
+    assert torch.equal(t_run, t_step)
