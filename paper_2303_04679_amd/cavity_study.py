@@ -1,0 +1,100 @@
+"""The lid-driven cavity of Section 3.3 on the GPU: convergence of mODIL with
+L-BFGS against the number of multigrid levels.
+
+    python -m paper_2303_04679_amd.cavity_study --out cavity_study.json
+
+Unit square, no-slip walls, the lid moving with unit velocity, Re = 100;
+64 x 64 cells (cell-based; levels 64, 32, 16, 8, 4), FP64 fields.  The
+reference is the discrete solution: L-BFGS with five levels run until the
+loss stops decreasing.  For L = 1 .. 5 levels, L-BFGS (50 pairs) starts from
+zero; the RMS difference of the velocity u from the reference is recorded
+every `--check-every` iterations, and with it the first check at which it is
+at most 1e-3.
+"""
+import argparse
+import json
+import time
+
+import torch
+
+from .modil import LBFGS, Context, ProblemSpec
+
+
+def problem(n, L):
+    return Context(ProblemSpec("cavity", (n, n), (1.0, 1.0), L, dtype="f64", re=100.0,
+                               tau_coef=0.5, u_ref=1.0, w_pde=1.0))
+
+
+def solve(ctx, iters, history, check_every, observe):
+    th = ctx.new_pack()
+    lb = LBFGS(ctx, history=history)
+    hist = [observe(th, 0)]
+    evals, status, it = 0, 0, 0
+    t0 = time.perf_counter()
+    for it in range(1, iters + 1):
+        info = lb.step(th)
+        evals += info["evals"]
+        status = info["status"]
+        if it % check_every == 0 or status == 2:
+            hist.append(observe(th, it))
+            if hist[-1].get("stop"):
+                break
+        if status == 2:
+            break
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    lb.close()
+    return th, hist, evals, secs, it, status
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--n", type=int, default=64)
+    ap.add_argument("--iters", type=int, default=10000)
+    ap.add_argument("--reference-iters", type=int, default=30000)
+    ap.add_argument("--history", type=int, default=50)
+    ap.add_argument("--check-every", type=int, default=10)
+    ap.add_argument("--target", type=float, default=1e-3)
+    args = ap.parse_args()
+    n = args.n
+    # reference: the discrete solution
+    rctx = problem(n, 5)
+
+    def observe_ref(th, it):
+        loss = float(rctx.loss(th).sum())
+        if it % 1000 == 0:
+            print(f"[cavity] reference it {it}: loss {loss:.3e}", flush=True)
+        return {"it": it, "loss": loss}
+
+    th, rh, rev, rsec, rit, rstatus = solve(rctx, args.reference_iters, args.history, 100, observe_ref)
+    u_ref = rctx.fine_views(rctx.prolong(th))[0].clone()
+    print(f"[cavity] reference: {rit} iterations, loss {rh[-1]['loss']:.3e}, status {rstatus}", flush=True)
+    rctx.close()
+    out = {"n": n, "re": 100.0, "target": args.target,
+           "reference": {"iterations": rit, "loss": rh[-1]["loss"], "status": rstatus, "seconds": rsec},
+           "runs": []}
+    for L in range(1, 6):
+        ctx = problem(n, L)
+        first = [None]
+
+        def observe(th, it):
+            u = ctx.fine_views(ctx.prolong(th))[0]
+            e = float(torch.sqrt(((u - u_ref) ** 2).mean()))
+            if first[0] is None and e <= args.target:
+                first[0] = it
+            return {"it": it, "error": e, "stop": first[0] is not None and it >= 2 * first[0] + 200}
+
+        _, hist, ev, secs, it, status = solve(ctx, args.iters, args.history, args.check_every, observe)
+        print(f"[cavity] L={L}: error <= {args.target:g} at iteration {first[0]}; "
+              f"{it} iterations, {ev} evaluations, {secs:.2f} s, final error {hist[-1]['error']:.2e}",
+              flush=True)
+        out["runs"].append({"L": L, "iterations_to_target": first[0], "iterations": it,
+                            "evaluations": ev, "seconds": secs,
+                            "history": [(h["it"], h["error"]) for h in hist]})
+        ctx.close()
+    json.dump(out, open(args.out, "w"))
+
+
+if __name__ == "__main__":
+    main()
