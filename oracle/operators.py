@@ -27,7 +27,9 @@ the one the whole project uses (every reading is listed in the design notes):
            compact pressure-stabilised continuity equation, body fraction
            chi = sigmoid(chihat - shift), inlet/outlet/free-slip ghost rules.
   cavity   steady 2-D Navier-Stokes in the lid-driven cavity (Section 3.3),
-           same discretisation as ns3d, no-slip walls, unit lid velocity.
+           same discretisation as ns3d, no-slip walls, unit lid velocity;
+           cell-based, or node-based with the wall velocity imposed on the
+           wall nodes.
 
 Optional per-equation forcing arrays (fine grid) are subtracted from the
 residuals; they let a test manufacture a state whose residual is zero.
@@ -401,11 +403,66 @@ def cavity_residual(spec, fields):
                           0.0, P.get("tau_coef", 0.5))
 
 
+def cavity_node_residual(spec, fields):
+    """Lid-driven cavity on node-based values (Sections 2.2, 3.3).
+
+    Nodes x_i = i h, i = 0..N on both axes.  The no-slip condition is imposed
+    on the wall nodes directly: their velocity is zero, except u = u_ref on the
+    lid's nodes (y = 1, the two corners excluded), whatever the fine field
+    holds there.  The wall pressure is that of the interior node next to it
+    (zero normal derivative).  Continuity and momentum hold at the interior
+    nodes, with central differences and the stabilised continuity equation of
+    the cell-based form.  Returns [continuity, momentum u, momentum v] on the
+    interior nodes."""
+    u, v, p = fields
+    lid = spec.params.get("u_ref", 1.0)
+    inside = poisson_node_interior(u.shape)
+    top = torch.zeros_like(u)
+    top[-1, 1:-1] = lid  # axis 0 = y: the last row is the lid
+    u = u * inside + top
+    v = v * inside
+    p = p.clone()
+    p[0, :] = p[1, :]
+    p[-1, :] = p[-2, :]
+    p[:, 0] = p[:, 1]
+    p[:, -1] = p[:, -2]
+    hy, hx = spec.h
+    P = spec.params
+    nu = 1.0 / P["re"]
+    tau = P.get("tau_coef", 0.5)
+    inner = (slice(1, -1), slice(1, -1))
+
+    def dx(f):
+        return (f[1:-1, 2:] - f[1:-1, :-2]) / (2.0 * hx)
+
+    def dy(f):
+        return (f[2:, 1:-1] - f[:-2, 1:-1]) / (2.0 * hy)
+
+    def lap_x(f):
+        return (f[1:-1, 2:] - 2.0 * f[inner] + f[1:-1, :-2]) / hx ** 2
+
+    def lap_y(f):
+        return (f[2:, 1:-1] - 2.0 * f[inner] + f[:-2, 1:-1]) / hy ** 2
+
+    uc, vc = u[inner], v[inner]
+    cont = dx(u) + dy(v) - (tau * hx * lap_x(p) + tau * hy * lap_y(p))
+    mom_u = uc * dx(u) + vc * dy(u) + dx(p) - nu * (lap_x(u) + lap_y(u))
+    mom_v = uc * dx(v) + vc * dy(v) + dy(p) - nu * (lap_x(v) + lap_y(v))
+    res = [cont, mom_u, mom_v]
+    for e in range(3):
+        f = spec.forcing.get(e)
+        if f is not None:
+            res[e] = res[e] - torch.as_tensor(f, dtype=DT)[inner]
+    return res
+
+
 def residuals(spec, fine):
     """PDE residual arrays of the problem for the list of fine fields."""
     op = spec.op
     if op == "poisson" and spec.centering == "node":
         return poisson_node_residual(spec, fine[0])
+    if op == "cavity" and spec.centering == "node":
+        return cavity_node_residual(spec, fine)
     if op == "poisson":
         return poisson_residual(spec, fine[0])
     if op == "burgers":

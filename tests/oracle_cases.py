@@ -51,19 +51,25 @@ def case(op, dims, n_levels, seed=0, with_forcing=False):
         spec.meas = [(c, "data", plane, g.uniform(-1, 1, size=n), 1.0 / n) for c in range(3)]
         if op == "ns3d_fixed":
             spec.chi = synth.rng(seed + 31).uniform(0, 1, size=dims)
-    elif op == "cavity":
+    elif op in ("cavity", "cavity_node"):
+        node = op == "cavity_node"
         spec = ops.Spec("cavity", dims, (1.0, 1.0), n_levels,
-                        params={"re": 400.0, "tau_coef": 0.5}, weights={"pde": 1.0, "data": 1.0})
+                        params={"re": 400.0, "tau_coef": 0.5, "u_ref": 1.0},
+                        weights={"pde": 1.0, "data": 1.0}, centering="node" if node else "cell")
+        shape = tuple(d + 1 for d in dims) if node else dims
         n = max(2, min(64, dims[0] * dims[1] // 8))
-        idx = synth.unique_cells(seed + 41, dims, n=n)
+        # node-based: measure interior nodes only (the wall nodes carry imposed values)
+        lo, hi = ((1,) * 2, dims) if node else (None, None)
+        idx = synth.unique_cells(seed + 41, shape, lo=lo, hi=hi, n=n)
         g = synth.rng(seed + 42)
         spec.meas = [(c, "data", idx, g.uniform(-1, 1, size=n), 1.0 / n) for c in range(2)]
     else:
         raise ValueError(op)
     if with_forcing:
-        neq = {"burgers": 1, "heat": 1, "ns3d": 4, "ns3d_fixed": 4, "cavity": 3}[op]
+        neq = {"burgers": 1, "heat": 1, "ns3d": 4, "ns3d_fixed": 4, "cavity": 3, "cavity_node": 3}[op]
         g = synth.rng(seed + 51)
-        spec.forcing = {e: g.uniform(-1, 1, size=dims) for e in range(neq)}
+        shape = tuple(d + 1 for d in dims) if spec.centering == "node" else dims
+        spec.forcing = {e: g.uniform(-1, 1, size=shape) for e in range(neq)}
     return spec
 
 

@@ -27,6 +27,8 @@ CASES = [
     ("ns3d", (4, 4, 4), 2),
     ("ns3d_fixed", (4, 4, 4), 2),
     ("cavity", (8, 8), 3),
+    ("cavity_node", (8, 8), 3),
+    ("cavity_node", (8, 4), 2),
 ]
 
 

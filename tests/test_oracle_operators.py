@@ -321,6 +321,104 @@ def test_cavity_pressure_gauge_invariance():
     assert abs(a - b) <= 1e-13 * a
 
 
+# ------------------------------------------------------ node-based cavity
+def _cavity_node_spec(n, re=100.0, tau=0.5, lid=0.0, forcing=None, ny=None):
+    ny = ny or n
+    return ops.Spec("cavity", (ny, n), (1.0, 1.0), 1,
+                    params={"re": re, "tau_coef": tau, "u_ref": lid},
+                    weights={"pde": 1.0}, centering="node", forcing=forcing or {})
+
+
+def test_cavity_node_exact_for_products_of_quadratics():
+    """With a resting lid, u = q(x) q(y) and v = q(x) q(y) / 2 (q(s) = s (1 - s))
+    vanish on the walls and are quadratic along each axis, where central
+    differences are exact; with constant pressure the node residuals are the
+    continuous Navier-Stokes operators evaluated at the nodes."""
+    n, ny = 8, 6
+    nu = 1.0 / 100.0
+    y, x = np.arange(ny + 1) / ny, np.arange(n + 1) / n
+    Y, X = np.meshgrid(y, x, indexing="ij")
+    qx, qy, dqx, dqy = X * (1 - X), Y * (1 - Y), 1 - 2 * X, 1 - 2 * Y
+    u, v = qx * qy, 0.5 * qx * qy
+    ux, uy = dqx * qy, qx * dqy
+    lap_u = -2.0 * qy - 2.0 * qx
+    f = {0: ux + 0.5 * uy,
+         1: u * ux + v * uy - nu * lap_u,
+         2: 0.5 * (u * ux + v * uy - nu * lap_u)}
+    spec = _cavity_node_spec(n, ny=ny, forcing=f)
+    R = ops.cavity_node_residual(spec, [torch.tensor(u), torch.tensor(v), torch.full_like(torch.tensor(u), 2.5)])
+    for r in R:
+        assert r.shape == (ny - 1, n - 1)
+        assert float(r.abs().max()) < 1e-13
+
+
+def test_cavity_node_lid_row():
+    """u = y with the lid at u = 1: the imposed lid (last row) and bottom wall
+    (u = 0) agree with u = y, so away from the side walls every residual is zero."""
+    n = 8
+    y = np.arange(n + 1) / n
+    Y = np.tile(y[:, None], (1, n + 1))
+    z = np.zeros_like(Y)
+    rng = np.random.default_rng(5)
+    U = Y + 9.0 * (1 - ops.poisson_node_interior(Y.shape).numpy()) * rng.standard_normal(Y.shape)
+    R = ops.cavity_node_residual(_cavity_node_spec(n, lid=1.0), [torch.tensor(U), torch.tensor(z), torch.tensor(z)])
+    for r in R:
+        assert float(r[:, 1:-1].abs().max()) < 1e-13
+    # next to the left wall u drops to 0: u_x = (y - 0) / 2h, u_xx = (y - 2 y + 0) / h^2
+    h, yi = 1.0 / n, y[1:-1]
+    np.testing.assert_allclose(R[1][:, 0].numpy(), yi * yi / (2 * h) + (1 / 100.0) * yi / h ** 2,
+                               rtol=1e-12)
+
+
+def test_cavity_node_pressure_neumann_wall():
+    """p = s x at rest: a zero normal derivative at the wall makes the wall
+    pressure equal its neighbour's, so the node next to the wall sees half the
+    slope in the momentum equation and a one-sided stabilisation term in
+    continuity; elsewhere p_x = s exactly and the stabilisation vanishes."""
+    n, s, tau = 8, 3.0, 0.5
+    x = np.arange(n + 1) / n
+    P = np.tile(s * x[None, :], (n + 1, 1))
+    z = np.zeros_like(P)
+    R = ops.cavity_node_residual(_cavity_node_spec(n, tau=tau), [torch.tensor(z), torch.tensor(z), torch.tensor(P)])
+    cont, mu, mv = (r.numpy() for r in R)
+    np.testing.assert_allclose(mu[:, 1:-1], s, rtol=1e-13)
+    np.testing.assert_allclose(mu[:, 0], s / 2, rtol=1e-13)
+    np.testing.assert_allclose(mu[:, -1], s / 2, rtol=1e-13)
+    np.testing.assert_allclose(cont[:, 1:-1], 0.0, atol=1e-12)
+    np.testing.assert_allclose(cont[:, 0], -tau * s, rtol=1e-12)
+    np.testing.assert_allclose(cont[:, -1], tau * s, rtol=1e-12)
+    assert float(np.abs(mv).max()) == 0.0
+
+
+def test_cavity_node_wall_values_do_not_matter():
+    """Every wall node's value is replaced (velocity imposed, pressure copied):
+    the loss does not depend on the fine field there and its gradient is zero."""
+    spec = _cavity_node_spec(8, re=400.0, lid=1.0)
+    spec.forcing = {}
+    rng = np.random.default_rng(11)
+    f = [rng.standard_normal((9, 9)) for _ in range(3)]
+    mask = ops.poisson_node_interior((9, 9)).numpy()
+    g = [x * mask + 5.0 * (1 - mask) * rng.standard_normal((9, 9)) for x in f]
+    assert ops.loss_value(spec, [f])["pde"] == ops.loss_value(spec, [g])["pde"]
+    _, gr = ops.loss_and_grad(spec, [f])
+    for c in range(3):
+        assert np.all(gr[0][c][mask == 0] == 0.0)
+        assert np.linalg.norm(gr[0][c]) > 0
+
+
+def test_cavity_node_pressure_gauge_invariance():
+    spec = _cavity_node_spec(8, re=400.0, lid=1.0)
+    rng = np.random.default_rng(3)
+    f = [rng.standard_normal((9, 9)) for _ in range(3)]
+    a = ops.loss_value(spec, [f])["pde"]
+    b = ops.loss_value(spec, [[f[0], f[1], f[2] + 3.25]])["pde"]
+    assert abs(a - b) <= 1e-13 * a
+
+
+def test_cavity_node_level_shapes():
+    assert ops.level_shapes("cavity", (64, 64), 5, "node") == [[(n, n)] * 3 for n in (65, 33, 17, 9, 5)]
+
+
 # ------------------------------------------------------- node-based Poisson
 def _node_grid(n, d):
     x = np.arange(n + 1) / n
