@@ -62,7 +62,7 @@ extern "C" {
 #define MODIL_F64 1
 
 #define MODIL_CELL 0 /* values at cell centres                           */
-#define MODIL_NODE 1 /* values at grid nodes, MODIL_OP_POISSON only      */
+#define MODIL_NODE 1 /* values at grid nodes, POISSON and CAVITY only   */
 
 /* Residual operators (the discretised PDEs of Sections 3.1-3.5).
  *   POISSON   d = 1,2,3; Laplacian u = f, Dirichlet u = 0 by quadratic
@@ -115,15 +115,21 @@ extern "C" {
  * Validation: ndim matches the operator, dims[a] divisible by
  * 2^(n_levels-1) with at least 2 coarsest cells per axis (cell-based
  * extrapolation needs two), lengths > 0, batch >= 1, 1 <= n_levels <= 8.
- * MODIL_NODE (POISSON only; Section 3.1, node-based variant): dims are cells
+ * MODIL_NODE (POISSON and CAVITY; Sections 2.2, 3.1, 3.3): dims are cells
  * per axis and a field holds (dims[a] >> l) + 1 nodes per axis on level l,
  * boundary nodes included; T is the node-based interpolation of Section 2.2
- * (even fine nodes copy the coarse node, odd ones average two).  Interior
- * nodes carry the finite-difference Laplacian (weight w_pde h^d).  The zero
- * Dirichlet condition is imposed on the boundary nodes directly: they carry no
- * equation, enter their neighbours' stencils as zero whatever the prolonged
- * field holds there, and get a zero gradient.  Forcing arrays and
- * measurement indices address nodes; the forcing enters interior rows only. */
+ * (even fine nodes copy the coarse node, odd ones average two).  Boundary
+ * nodes carry no equation and get a zero gradient; forcing arrays and
+ * measurement indices address nodes; the forcing enters interior rows only.
+ *   POISSON: interior nodes carry the finite-difference Laplacian (weight
+ *   w_pde h^d); the zero Dirichlet value is imposed on the boundary nodes,
+ *   which enter their neighbours' stencils as zero whatever the prolonged
+ *   field holds there.
+ *   CAVITY: interior nodes carry the three cell-based cavity equations
+ *   (central differences, stabilised continuity); on the wall nodes the
+ *   velocity is imposed (zero, u = u_ref on the lid row y = 1 without its
+ *   corners) and the pressure is that of the interior neighbour across the
+ *   wall (zero normal derivative), whatever the prolonged fields hold there. */
 typedef struct {
   int32_t ndim;
   int32_t dims[3];

@@ -69,8 +69,9 @@ int validate(const modil_problem *p, std::string &msg) {
     msg = "dtype must be MODIL_F32 or MODIL_F64";
     return MODIL_ERR_DTYPE;
   }
-  if (p->centering != MODIL_CELL && !(p->centering == MODIL_NODE && p->op == MODIL_OP_POISSON)) {
-    msg = "node-based values are implemented for MODIL_OP_POISSON only";
+  if (p->centering != MODIL_CELL &&
+      !(p->centering == MODIL_NODE && (p->op == MODIL_OP_POISSON || p->op == MODIL_OP_CAVITY))) {
+    msg = "node-based values are implemented for MODIL_OP_POISSON and MODIL_OP_CAVITY only";
     return MODIL_ERR_DTYPE;
   }
   const int want = expected_ndim(p->op);

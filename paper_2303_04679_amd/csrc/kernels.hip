@@ -1143,7 +1143,10 @@ static hipError_t launch_fine_t(modil_ctx *c, const void *u, void *g, bool want_
         break;
       case MODIL_OP_BURGERS: launch_fine_tile<OpBurgers, T>(c, A, A0, ad); break;
       case MODIL_OP_HEAT_KX: launch_fine_tile<OpHeat, T>(c, A, A0, ad); break;
-      case MODIL_OP_CAVITY: launch_fine_tile<OpNS<2, 0>, T>(c, A, A0, ad); break;
+      case MODIL_OP_CAVITY:
+        if (P.centering == MODIL_NODE) launch_fine_tile<OpCavityNode, T>(c, A, A0, ad);
+        else launch_fine_tile<OpNS<2, 0>, T>(c, A, A0, ad);
+        break;
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1169,7 +1172,10 @@ static hipError_t launch_fine_t(modil_ctx *c, const void *u, void *g, bool want_
         fine_kernel<OpNS<3, 2>, T><<<grid, kBlock, 0, c->stream>>>(A);
       break;
     case MODIL_OP_CAVITY:
-      fine_kernel<OpNS<2, 0>, T><<<grid, kBlock, 0, c->stream>>>(A);
+      if (P.centering == MODIL_NODE)
+        fine_kernel<OpCavityNode, T><<<grid, kBlock, 0, c->stream>>>(A);
+      else
+        fine_kernel<OpNS<2, 0>, T><<<grid, kBlock, 0, c->stream>>>(A);
       break;
     default:
       return hipErrorInvalidValue;

@@ -471,4 +471,86 @@ struct OpNS {
   }
 };
 
+// Node-based lid-driven cavity (Sections 2.2, 3.3): values at the nodes
+// x_i = i h.  The no-slip condition is imposed on the wall nodes: their
+// velocity is zero, except u = u_ref on the lid (axis 1, last row), whatever
+// the prolonged field holds there.  The wall pressure equals that of the
+// interior node next to it across the wall (zero normal derivative); for an
+// interior node that neighbour is the node itself.  Wall nodes carry no
+// equation; interior nodes carry the equations of OpNS<2, 0> evaluated on the
+// star with these substitutions, so the adjoint drops the velocity wall slots
+// and moves the pressure wall slots onto the centre.
+struct OpCavityNode {
+  using Base = OpNS<2, 0>;
+  static constexpr bool kForcePdeOnly = false;
+  static constexpr int NF = 3, NE = 3;
+
+  __device__ static bool needs_nb(int) { return true; }
+  __device__ static GhostRule ghost(const OpParams &, int, int, int) {
+    return GhostRule{0.0, 0.0, 0.0};  // never used by an equation
+  }
+  __device__ static bool on_boundary(const OpParams &p, const int *j) {
+    return j[1] == 0 || j[1] == p.n[1] - 1 || j[2] == 0 || j[2] == p.n[2] - 1;
+  }
+  // bit (2 a + side) set when the star's neighbour along axis a (1, 2) on that side is a wall node
+  __device__ static int wall_mask(const OpParams &p, const int *j) {
+    int m = 0;
+    for (int a = 1; a < 3; ++a) {
+      if (j[a] - 1 == 0) m |= 1 << (2 * a);
+      if (j[a] + 1 == p.n[a] - 1) m |= 1 << (2 * a + 1);
+    }
+    return m;
+  }
+  template <typename T>
+  __device__ static void impose(const OpParams &p, int m, const T (&U)[NF][7], T (&W)[NF][7]) {
+    for (int f = 0; f < NF; ++f)
+      for (int k = 0; k < 7; ++k) W[f][k] = U[f][k];
+    for (int a = 1; a < 3; ++a)
+      for (int side = 0; side < 2; ++side) {
+        if (!(m >> (2 * a + side) & 1)) continue;
+        const int k = side ? slot_p(a) : slot_m(a);
+        W[0][k] = (a == 1 && side == 1) ? T(p.u_ref) : T(0);
+        W[1][k] = T(0);
+        W[2][k] = U[2][S_C];
+      }
+  }
+  template <typename T>
+  __device__ static void eval(const OpParams &p, const int *j, int inst, const T (&U)[NF][7],
+                              T chi_fixed, T *r, T *wv, int *term) {
+    if (on_boundary(p, j)) {
+      for (int e = 0; e < NE; ++e) {
+        r[e] = T(0);
+        wv[e] = T(0);
+        term[e] = MODIL_TERM_PDE;
+      }
+      return;
+    }
+    T W[NF][7];
+    impose(p, wall_mask(p, j), U, W);
+    Base::eval(p, j, inst, W, chi_fixed, r, wv, term);
+  }
+  template <typename T>
+  __device__ static void vjp(const OpParams &p, const int *j, int inst, const T (&U)[NF][7],
+                             T chi_fixed, const T *a, T (&s)[NF][7]) {
+    if (on_boundary(p, j)) return;
+    const int m = wall_mask(p, j);
+    T W[NF][7], t[NF][7];
+    impose(p, m, U, W);
+    for (int f = 0; f < NF; ++f)
+      for (int k = 0; k < 7; ++k) t[f][k] = T(0);
+    Base::vjp(p, j, inst, W, chi_fixed, a, t);
+    for (int ax = 1; ax < 3; ++ax)
+      for (int side = 0; side < 2; ++side) {
+        if (!(m >> (2 * ax + side) & 1)) continue;
+        const int k = side ? slot_p(ax) : slot_m(ax);
+        t[0][k] = T(0);
+        t[1][k] = T(0);
+        t[2][S_C] += t[2][k];
+        t[2][k] = T(0);
+      }
+    for (int f = 0; f < NF; ++f)
+      for (int k = 0; k < 7; ++k) s[f][k] += t[f][k];
+  }
+};
+
 }  // namespace modil

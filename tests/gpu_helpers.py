@@ -23,7 +23,7 @@ def problem_of(spec, dtype, batch=1):
         max_meas=batch * sum(len(m[2]) for m in spec.meas) + 1,
         chi_fixed=spec.op == "ns3d_fixed", re=P.get("re", 100.0), diam=P.get("diam", 0.4),
         lam=P.get("lam", 1.0), chi_shift=P.get("chi_shift", 5.0), tau_coef=P.get("tau_coef", 0.5),
-        u_ref=1.0, w_pde=spec.weights["pde"], w_reg=spec.weights["reg"], w_bc=spec.weights["bc"],
+        u_ref=P.get("u_ref", 1.0), w_pde=spec.weights["pde"], w_reg=spec.weights["reg"], w_bc=spec.weights["bc"],
         centering=spec.centering)
 
 

@@ -77,11 +77,23 @@ def test_validation_errors(kw, status):
     assert L.lib().modil_last_error(None)
 
 
-def test_node_centering_only_for_poisson():
-    p = ProblemSpec("cavity", (16, 16), (1.0, 1.0), 2).to_c()
+@pytest.mark.parametrize("op,dims,lengths", [("burgers", (16, 16), (1.0, 2.0)),
+                                             ("heat", (16, 16), (0.02, 1.0)),
+                                             ("ns3d", (8, 8, 16), (1.0, 1.0, 2.0))])
+def test_node_centering_only_for_poisson_and_cavity(op, dims, lengths):
+    p = ProblemSpec(op, dims, lengths, 2).to_c()
     p.centering = L.NODE
     out = L.PackLayout()
     assert L.lib().modil_layout(ctypes.byref(p), ctypes.byref(out)) == L.ERR_DTYPE
+
+
+def test_node_cavity_layout():
+    """Node-based cavity: three fields of (dims >> l) + 1 values per axis."""
+    lay = layout(ProblemSpec("cavity", (64, 64), (1.0, 1.0), 5, centering="node"))
+    for l, n in enumerate((65, 33, 17, 9, 5)):
+        assert [tuple(lay.field_dims[l][f])[1:] for f in range(3)] == [(n, n)] * 3
+    assert lay.fine_cells == 65 * 65
+    assert lay.total == 3 * sum(n * n for n in (65, 33, 17, 9, 5))
 
 
 def test_node_layout():

@@ -47,7 +47,8 @@ def _oracle_fg(spec):
 
 
 PARITY = [("poisson", (32, 48), 4), ("burgers", (24, 40), 3), ("heat", (40, 72), 3),
-          ("ns3d", (8, 16, 8), 3), ("cavity", (32, 48), 4), ("poisson_node", (32, 48), 4)]
+          ("ns3d", (8, 16, 8), 3), ("cavity", (32, 48), 4), ("poisson_node", (32, 48), 4),
+          ("cavity_node", (32, 48), 4)]
 
 
 @pytest.mark.parametrize("op,dims,L", PARITY)

@@ -34,6 +34,8 @@ CASES = [
     ("poisson_node", (64,), 4),
     ("poisson_node", (16, 24), 3),
     ("poisson_node", (8, 16, 8), 2),
+    ("cavity_node", (32, 48), 4),
+    ("cavity_node", (24, 16), 3),
 ]
 
 
@@ -115,7 +117,7 @@ def test_adam(dtype):
 
 @pytest.mark.parametrize("op,dims,L", [("burgers", (32, 32), 4), ("heat", (32, 32), 4),
                                        ("ns3d", (8, 8, 16), 3), ("cavity", (32, 32), 4),
-                                       ("poisson_node", (32, 32), 4)])
+                                       ("poisson_node", (32, 32), 4), ("cavity_node", (32, 32), 4)])
 def test_step_sequence_f64(op, dims, L):
     """Three modil_step calls (ping-pong theta) follow the oracle's loss, gradient and Adam."""
     need_gpu()
@@ -227,7 +229,8 @@ def test_nonfinite_is_reported():
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("op,dims,L,batch", [("heat", (40, 72), 3, 1), ("cavity", (32, 48), 4, 1),
                                              ("burgers", (24, 40), 3, 1), ("poisson", (32, 48), 4, 1),
-                                             ("poisson_node", (16, 24), 3, 1),
+                                             ("poisson_node", (16, 24), 3, 1), ("cavity_node", (32, 48), 4, 1),
+                                             ("cavity_node", (48, 64), 3, 12),
                                              ("heat", (64, 96), 3, 12), ("cavity", (48, 64), 3, 16)])
 def test_tiled_engine(op, dims, L, batch, dtype):
     """The 2-D tiled engine (16 x 4 tiles; 32 x 8 when the batch fills the
@@ -361,6 +364,7 @@ def test_fused_channel_batch():
 
 
 @pytest.mark.parametrize("op,dims,L,dtype", [("cavity", (32, 48), 4, "f32"), ("heat", (32, 64), 4, "f64"),
+                                             ("cavity_node", (32, 48), 4, "f64"),
                                              ("ns3d", (16, 16, 32), 3, "f32")])
 @pytest.mark.parametrize("n", [1, 4, 5])
 def test_run_equals_steps(op, dims, L, dtype, n):
