@@ -101,23 +101,46 @@ __device__ inline void st_at(T *base, uint32_t byte_off, T v) {
   *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off) = v;
 }
 
+// Adjoint of the residuals of a neighbour j across one face, added to g.
+// at = {a_0, a_1 (1 - chi), a_2 (1 - chi), a_3 (1 - chi)} are j's residual
+// seeds (continuity, then momentum scaled by 1 - chi: the momentum residual is
+// (1 - chi) times the flow operator plus the body term), ukc is j's velocity
+// component along the axis, sgi2h = side / (2 h) with side the direction from j
+// to the cell receiving the sensitivity.  Convection u_kc d/da u_c, the
+// viscous term, the pressure gradient and the stabilised continuity are the
+// terms of j's residuals that read a neighbour along the axis.
+template <typename T>
+__device__ inline void face_add(const NSCoef<T> &K, int axis, T sgi2h, const T (&at)[4], T ukc,
+                                T (&g)[4]) {
+  const int kc = 2 - axis;  // velocity component along this axis
+  const T coef = sgi2h * ukc - K.nu * K.ih2[axis];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) g[c] += at[1 + c] * coef;
+  g[kc] += sgi2h * at[0];
+  g[3] += sgi2h * at[1 + kc] - K.tauh[axis] * at[0];
+}
+
 // CHI: 1 fixed chi array, 2 unknown chihat (field 4).  FORCING: some equation
 // has a forcing array (compiled out otherwise: its pointers would hold scalar
 // registers through the plane loop).
+//
+// Walls in x and y: a cell next to a wall writes into the halo slot across
+// the wall (outside the grid, so no other cell owns it) the ghost values of
+// its (u, v, w, p), which its stencil then reads like any neighbour, and, for
+// the gather, seeds that make the neighbour formula give the ghost map's
+// adjoint: with c_f the ghost rule's coefficient of field f (ghost = b + c_f
+// u_f), the slot holds a_0 -c_k, a_c c_c (k the component normal to the
+// wall) and normal velocity -u_k.  This relies on c_k = -c_p, which the host
+// checks.  Walls in z are uniform over a plane and take a branch.
 template <typename T, int CHI, bool ADAM, bool FORCING>
 __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel(NS3DArgs<T> A) {
   constexpr int NF = (CHI == 2) ? 5 : 4;  // unknown fields
-  constexpr int NS = 5;                   // stored per cell: u, v, w, p, chi
-  __shared__ T Ul[2][NS][NST_Y][NST_X];
-  __shared__ T Al[2][4][NST_Y][NST_X];
+  constexpr int NA = 5;                   // per cell: seeds a_0, a_c (1 - chi), and u for x faces
+  __shared__ T Ul[2][4][NST_Y][NST_X];
+  __shared__ T Al[2][NA][NST_Y][NST_X];
   __shared__ T Dl[4][NST_Y][NST_X];
   __shared__ double red[NS_THREADS / 64][kTerms];
   static_assert(sizeof(T) == 4, "FP32 fields");
-  // the derivatives and body terms of a cell (12 values) are kept from its
-  // seed pass for its gradient pass one plane later, instead of being formed
-  // again
-  constexpr int NLS = 12;
-  __shared__ T Ls[2][NLS][NS_THREADS];
   // two coarse planes (coarse plane K in slot K & 1): the one a fine plane
   // interpolates from and the next; the next one is loaded a plane ahead
   static_assert(NF_MAX_COARSE * NCT <= 2 * NS_THREADS, "two coarse values per thread");
@@ -153,6 +176,9 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
   const bool in_xy = active && x >= 0 && x < nx && y >= 0 && y < ny;
   const bool seed_xy = in_xy && X >= 1 && X <= NST_X - 2 && Y >= 1 && Y <= NST_Y - 2;
   const bool own_xy = in_xy && X >= 2 && X <= NST_X - 3 && Y >= 2 && Y <= NST_Y - 3;
+  // walls next to a seed cell (its halo slot across the wall is in the tile)
+  const bool wxm = seed_xy && x == 0, wxp = seed_xy && x == nx - 1;
+  const bool wym = seed_xy && y == 0, wyp = seed_xy && y == ny - 1;
   const int plane = nx * ny;
   const int col = y * nx + x;
   const NSCoef<T> &K = A.K;
@@ -161,8 +187,8 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
   // byte offset of this column in field f of plane 0 from the instance's
   // level-0 base (the host checks the largest offset used fits in 32 bits)
   const uint32_t plane_b = (uint32_t)plane * (uint32_t)sizeof(T);
-  uint32_t fo[NS];
-  for (int f = 0; f < NS; ++f)
+  uint32_t fo[NF];
+  for (int f = 0; f < NF; ++f)
     fo[f] = ((uint32_t)f * (uint32_t)A.fsize + (uint32_t)(in_xy ? col : 0)) * (uint32_t)sizeof(T);
   // byte offset of plane z (uniform); planes before the grid map to plane 0
   auto pofs = [&](int z) { return (uint32_t)max(z, 0) * plane_b; };
@@ -226,15 +252,21 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
     __syncthreads();
   }
 
-  T U0[NS], U1[NS], U2[NS], U3[NS];  // planes pz-3 .. pz
-  T A0[4], A1[4], A2[4];             // seeds at planes pz-3 .. pz-1
-  for (int f = 0; f < NS; ++f) U0[f] = U1[f] = U2[f] = U3[f] = T(0);
+  // planes pz-3 .. pz of this column: U0w is w at pz-3 (the gather's lower
+  // z face), U1 (u, v, w, p) at pz-2, U2 and U3 all five values
+  T U0w = T(0), U1[4], U2[5], U3[5];
+  for (int f = 0; f < 4; ++f) U1[f] = T(0);
+  for (int f = 0; f < 5; ++f) U2[f] = U3[f] = T(0);
+  T A0[4], A1[4], A2[4];  // scaled seeds at planes pz-3 .. pz-1
   for (int e = 0; e < 4; ++e) A0[e] = A1[e] = A2[e] = T(0);
+  // centre sensitivity of the cell at the gather plane, formed in its seed pass
+  T Cq[5] = {T(0), T(0), T(0), T(0), T(0)};
   double part[kTerms] = {0.0, 0.0, 0.0, 0.0, 0.0};
 
   // ghost value of field f across face (axis a, side s) of a cell with value c
-#define GV(f, a, s, c) (T(ns_ghost<3>(p, f, a, s).b2) + T(ns_ghost<3>(p, f, a, s).c0) * (c))
+#define GB(f, a, s) T(ns_ghost<3>(p, f, a, s).b2)
 #define GC0(f, a, s) T(ns_ghost<3>(p, f, a, s).c0)
+#define GV(f, a, s, c) (GB(f, a, s) + GC0(f, a, s) * (c))
 
   const int key_base = (inst * A.nzt * A.ntx * A.nty + tile) * A.tz;
 
@@ -279,7 +311,7 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
       }
     }
     // ---- 1. prolong plane pz of this column
-    T un[NS];
+    T un[5];
     if (in_xy && pz >= 0 && pz < nz) {
       if (A.has_coarse) {
         int km;
@@ -305,18 +337,27 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
       if (CHI == 2) un[4] = sigmoid_stable(un[4] - T(p.chi_shift));
       else un[4] = chi_pz;
     } else {
-      for (int f = 0; f < NS; ++f) un[f] = T(0);
+      for (int f = 0; f < 5; ++f) un[f] = T(0);
     }
-    for (int f = 0; f < NS; ++f) { U0[f] = U1[f]; U1[f] = U2[f]; U2[f] = U3[f]; U3[f] = un[f]; }
+    U0w = U1[2];
+    for (int f = 0; f < 4; ++f) U1[f] = U2[f];
+    for (int f = 0; f < 5; ++f) { U2[f] = U3[f]; U3[f] = un[f]; }
 
-    // ---- 2. stage plane pz-1 for the xy neighbours; clear the data seeds
+    // ---- 2. stage plane pz-1 for the xy neighbours, with the wall ghosts;
+    // clear the data seeds
     const int s = pz - 1, sb = s & 1;
-    for (int f = 0; f < NS; ++f) Ul[sb][f][Y][X] = U2[f];
+    if (in_xy)
+      for (int f = 0; f < 4; ++f) Ul[sb][f][Y][X] = U2[f];
+    if (wxm) for (int f = 0; f < 4; ++f) Ul[sb][f][Y][X - 1] = GV(f, 2, 0, U2[f]);
+    if (wxp) for (int f = 0; f < 4; ++f) Ul[sb][f][Y][X + 1] = GV(f, 2, 1, U2[f]);
+    if (wym) for (int f = 0; f < 4; ++f) Ul[sb][f][Y - 1][X] = GV(f, 1, 0, U2[f]);
+    if (wyp) for (int f = 0; f < 4; ++f) Ul[sb][f][Y + 1][X] = GV(f, 1, 1, U2[f]);
     for (int f = 0; f < 4; ++f) Dl[f][Y][X] = T(0);
     __syncthreads();
 
     // ---- 3. residual seeds at plane s; measurement seeds at plane q = pz-2
     T an[4] = {T(0), T(0), T(0), T(0)};
+    T Cs[5] = {T(0), T(0), T(0), T(0), T(0)};
     if (seed_xy && s >= 0 && s < nz && s >= z0 - 1 && s <= z1) {
       T Us[4][7];
       for (int f = 0; f < 4; ++f) {
@@ -324,28 +365,57 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
         Us[f][S_C] = c;
         Us[f][S_ZM] = s > 0 ? U1[f] : GV(f, 0, 0, c);
         Us[f][S_ZP] = s < nz - 1 ? U3[f] : GV(f, 0, 1, c);
-        Us[f][S_YM] = y > 0 ? Ul[sb][f][Y - 1][X] : GV(f, 1, 0, c);
-        Us[f][S_YP] = y < ny - 1 ? Ul[sb][f][Y + 1][X] : GV(f, 1, 1, c);
-        Us[f][S_XM] = x > 0 ? Ul[sb][f][Y][X - 1] : GV(f, 2, 0, c);
-        Us[f][S_XP] = x < nx - 1 ? Ul[sb][f][Y][X + 1] : GV(f, 2, 1, c);
+        Us[f][S_YM] = Ul[sb][f][Y - 1][X];
+        Us[f][S_YP] = Ul[sb][f][Y + 1][X];
+        Us[f][S_XM] = Ul[sb][f][Y][X - 1];
+        Us[f][S_XP] = Ul[sb][f][Y][X + 1];
       }
       NSLocal<3, T> L;
       ns_local<3>(K, Us, L);
-      for (int c = 0; c < 3; ++c) {
-        for (int k = 0; k < 3; ++k) Ls[sb][3 * c + k][tid] = L.du[c][k];
-        Ls[sb][9 + c][tid] = L.body[c];
-      }
       const T uc[3] = {U2[0], U2[1], U2[2]};
+      const T chi = U2[4], omc = T(1) - chi;
       T r[4];
-      ns_residual<3, true>(K, L, uc, U2[4], r);
+      ns_residual<3, true>(K, L, uc, chi, r);
+      T a[4];
       for (int e = 0; e < 4; ++e) {
         if (FORCING && A.forcing[e]) r[e] -= ld_at(A.forcing[e] + inst * A.fsize, fo[0] + pofs(s));
-        an[e] = T(2) * wv * r[e];
+        a[e] = T(2) * wv * r[e];
       }
-      if (own_xy && s >= z0 && s < z1)
+      an[0] = a[0];
+      for (int c = 0; c < 3; ++c) an[1 + c] = a[1 + c] * omc;
+      for (int e = 0; e < 4; ++e) Al[sb][e][Y][X] = an[e];
+      Al[sb][4][Y][X] = uc[0];
+      // wall slots: seeds whose neighbour adjoint is the ghost map's
+#define NS_WALL_SLOT(cond, axis, side, SY, SX)                                              \
+      if (cond) {                                                                           \
+        const int k = 2 - (axis);                                                           \
+        Al[sb][0][SY][SX] = -GC0(k, axis, side) * an[0];                                    \
+        for (int c = 0; c < 3; ++c) Al[sb][1 + c][SY][SX] = GC0(c, axis, side) * an[1 + c]; \
+        if ((axis) == 2) Al[sb][4][SY][SX] = -uc[0];                                        \
+      }
+      NS_WALL_SLOT(wxm, 2, 0, Y, X - 1)
+      NS_WALL_SLOT(wxp, 2, 1, Y, X + 1)
+      NS_WALL_SLOT(wym, 1, 0, Y - 1, X)
+      NS_WALL_SLOT(wyp, 1, 1, Y + 1, X)
+#undef NS_WALL_SLOT
+      if (own_xy && s >= z0 && s < z1) {
         for (int e = 0; e < 4; ++e) part[MODIL_TERM_PDE] += (double)wv * (double)r[e] * (double)r[e];
+        // the cell's own sensitivity (centre of its stencil), used by its
+        // gather one plane later
+        for (int f = 0; f < 3; ++f) {
+          T v = T(2) * K.nu * K.ssum * an[1 + f] + K.lam * chi * a[1 + f];
+          for (int c = 0; c < 3; ++c) v += an[1 + c] * L.du[c][f];
+          Cs[f] = v;
+        }
+        Cs[3] = T(2) * K.tsum * a[0];
+        if (CHI == 2) {
+          T dchi = T(0);
+          for (int c = 0; c < 3; ++c) dchi += a[1 + c] * (K.lam * uc[c] - L.body[c]);
+          Cs[4] = dchi * chi * omc;
+        }
+      }
     }
-    for (int e = 0; e < 4; ++e) { A0[e] = A1[e]; A1[e] = A2[e]; A2[e] = an[e]; Al[sb][e][Y][X] = an[e]; }
+    for (int e = 0; e < 4; ++e) { A0[e] = A1[e]; A1[e] = A2[e]; A2[e] = an[e]; }
     if (q >= z0 && q < z1) {
       const int key = key_base + (q - z0);
       const int e0 = A.mptr[key], e1 = A.mptr[key + 1];
@@ -367,59 +437,43 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
 
     // ---- 4. gradient, and Adam, at plane q
     if (gather) {
-      // ns_centre_sens reads the derivatives and body terms only
-      NSLocal<3, T> L;
-      for (int c = 0; c < 3; ++c) {
-        for (int k = 0; k < 3; ++k) L.du[c][k] = Ls[qb][3 * c + k][tid];
-        L.body[c] = Ls[qb][9 + c][tid];
-      }
-      const T uc[3] = {U1[0], U1[1], U1[2]};
-      const T chic = U1[4];
-      T g[5], cs[4], dchi, fs[4];
-      ns_centre_sens<3, true>(K, L, A1, uc, chic, cs, dchi);
-      for (int f = 0; f < 4; ++f) g[f] = cs[f];
-      g[4] = dchi * chic * (T(1) - chic);
-      // neighbours j whose star holds this cell: the face of j pointing here
+      T g[4] = {Cq[0], Cq[1], Cq[2], Cq[3]};
+      // z faces: the neighbours below and above, or the wall's ghost map
       if (q > 0) {
-        const T uj[3] = {U0[0], U0[1], U0[2]};
-        ns_face_sens<3, true>(K, 0, 1, A0, uj, U0[4], fs);
-        for (int f = 0; f < 4; ++f) g[f] += fs[f];
+        face_add(K, 0, K.i2h[0], A0, U0w, g);
       } else {
-        ns_face_sens<3, true>(K, 0, -1, A1, uc, chic, fs);
+        T fs[4] = {T(0), T(0), T(0), T(0)};
+        face_add(K, 0, -K.i2h[0], A1, U1[2], fs);
         for (int f = 0; f < 4; ++f) g[f] += GC0(f, 0, 0) * fs[f];
       }
       if (q < nz - 1) {
-        const T uj[3] = {U2[0], U2[1], U2[2]};
-        ns_face_sens<3, true>(K, 0, -1, A2, uj, U2[4], fs);
-        for (int f = 0; f < 4; ++f) g[f] += fs[f];
+        face_add(K, 0, -K.i2h[0], A2, U2[2], g);
       } else {
-        ns_face_sens<3, true>(K, 0, 1, A1, uc, chic, fs);
+        T fs[4] = {T(0), T(0), T(0), T(0)};
+        face_add(K, 0, K.i2h[0], A1, U1[2], fs);
         for (int f = 0; f < 4; ++f) g[f] += GC0(f, 0, 1) * fs[f];
       }
-#define NS_XY_NEIGHBOUR(cond, axis, side_lo, DY, DX, sideface)                          \
-      if (cond) {                                                                       \
-        const T aj[4] = {Al[qb][0][Y + DY][X + DX], Al[qb][1][Y + DY][X + DX],     \
-                         Al[qb][2][Y + DY][X + DX], Al[qb][3][Y + DY][X + DX]};    \
-        const T uj[3] = {Ul[qb][0][Y + DY][X + DX], Ul[qb][1][Y + DY][X + DX],     \
-                         Ul[qb][2][Y + DY][X + DX]};                                  \
-        ns_face_sens<3, true>(K, axis, sideface, aj, uj, Ul[qb][4][Y + DY][X + DX], fs); \
-        for (int f = 0; f < 4; ++f) g[f] += fs[f];                                      \
-      } else {                                                                          \
-        ns_face_sens<3, true>(K, axis, -(sideface), A1, uc, chic, fs);              \
-        for (int f = 0; f < 4; ++f) g[f] += GC0(f, axis, side_lo) * fs[f];        \
+      // y and x faces: neighbours or wall slots alike
+#define NS_XY_FACE(axis, sgn, SY, SX, UKC)                                                   \
+      {                                                                                      \
+        const T aj[4] = {Al[qb][0][SY][SX], Al[qb][1][SY][SX], Al[qb][2][SY][SX],           \
+                         Al[qb][3][SY][SX]};                                                 \
+        face_add(K, axis, (sgn) * K.i2h[axis], aj, UKC, g);                                  \
       }
-      NS_XY_NEIGHBOUR(y > 0, 1, 0, -1, 0, 1)
-      NS_XY_NEIGHBOUR(y < ny - 1, 1, 1, 1, 0, -1)
-      NS_XY_NEIGHBOUR(x > 0, 2, 0, 0, -1, 1)
-      NS_XY_NEIGHBOUR(x < nx - 1, 2, 1, 0, 1, -1)
-#undef NS_XY_NEIGHBOUR
-      for (int f = 0; f < 4; ++f) g[f] += Dl[f][Y][X];
+      NS_XY_FACE(1, T(1), Y - 1, X, Ul[qb][1][Y - 1][X])
+      NS_XY_FACE(1, T(-1), Y + 1, X, Ul[qb][1][Y + 1][X])
+      NS_XY_FACE(2, T(1), Y, X - 1, Al[qb][4][Y][X - 1])
+      NS_XY_FACE(2, T(-1), Y, X + 1, Al[qb][4][Y][X + 1])
+#undef NS_XY_FACE
+      T gg[5];
+      for (int f = 0; f < 4; ++f) gg[f] = g[f] + Dl[f][Y][X];
+      gg[4] = Cq[4];
       const int base = inst * A.th_inst;
       for (int f = 0; f < NF; ++f) {
-        st_at(A.g + base, fo[f] + qofs, g[f]);
+        st_at(A.g + base, fo[f] + qofs, gg[f]);
         if (ADAM) {
-          const T mm = A.adam.b1 * mq[f] + (T(1) - A.adam.b1) * g[f];
-          const T vv = A.adam.b2 * vq[f] + (T(1) - A.adam.b2) * g[f] * g[f];
+          const T mm = A.adam.b1 * mq[f] + (T(1) - A.adam.b1) * gg[f];
+          const T vv = A.adam.b2 * vq[f] + (T(1) - A.adam.b2) * gg[f] * gg[f];
           st_at(A.adam.m + base, fo[f] + qofs, mm);
           st_at(A.adam.v + base, fo[f] + qofs, vv);
           st_at(A.adam.th_out + base, fo[f] + qofs,
@@ -427,6 +481,7 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
         }
       }
     }
+    for (int f = 0; f < 5; ++f) Cq[f] = Cs[f];
     // the slot taken by the next coarse plane held the one below this fine
     // plane's pair, which nobody reads after step 1
     if (cnext >= 0) {
@@ -438,6 +493,7 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
 
 #undef GV
 #undef GC0
+#undef GB
   // ---- block sum of the loss partials (fixed order)
   for (int k = 0; k < kTerms; ++k) {
     double v = part[k];
@@ -492,6 +548,16 @@ static hipError_t fused_t(modil_ctx *c, const void *theta, void *g, const AdamHo
   p.re = P.re; p.diam = P.diam; p.lam = P.lambda_; p.chi_shift = P.chi_shift;
   p.tau_coef = P.tau_coef; p.u_ref = P.u_ref;
   p.inst_re = c->inst_re;
+  // the kernel's wall slots rely on two properties of the x and y wall rules:
+  // the normal velocity's ghost coefficient is minus the pressure's, and the
+  // normal velocity at a y wall is mirrored (ghost -v)
+  for (int side = 0; side < 2; ++side) {
+    for (int axis = 1; axis <= 2; ++axis)
+      if (ns_ghost<3>(p, 2 - axis, axis, side).c0 != -ns_ghost<3>(p, 3, axis, side).c0)
+        return hipErrorInvalidValue;
+    const GhostRule v = ns_ghost<3>(p, 1, 1, side);
+    if (v.b2 != 0.0 || v.c0 != -1.0) return hipErrorInvalidValue;
+  }
   int tox, toy;
   ns3d_tiles(P, A.tz, A.nzt, A.ntx, A.nty, tox, toy);
   A.tiles_per_xcd = (A.nzt * A.ntx * A.nty + NS_XCD - 1) / NS_XCD;

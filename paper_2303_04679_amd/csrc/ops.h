@@ -386,6 +386,14 @@ template <typename T>
 __device__ inline T sigmoid_stable(T z) {
   return z >= T(0) ? T(1) / (T(1) + exp(-z)) : exp(z) / (T(1) + exp(z));
 }
+// FP32: the hardware exponential and reciprocal (a few ulp, far inside the
+// FP32 tolerance) instead of the correctly rounded library calls
+template <>
+__device__ inline float sigmoid_stable<float>(float z) {
+  const float e = __expf(-fabsf(z));  // in (0, 1]
+  const float r = __builtin_amdgcn_rcpf(1.0f + e);
+  return z >= 0.0f ? r : e * r;
+}
 
 // Ghost rules of the channel (D = 3) and of the cavity (D = 2) for (velocity, p).
 template <int D>
