@@ -69,6 +69,12 @@ __device__ inline float adam_theta<float>(float th, float m, float v, float step
   return th - step * m * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(v) * isb2 + eps);
 }
 
+// Barrier for data exchanged through LDS only: it waits for the wave's own
+// LDS accesses, not for its global stores as __syncthreads does, so blocks
+// that write results level after level do not wait for each level's stores.
+// The memory clobber keeps the compiler from moving memory accesses across it.
+__device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 // Fixed-order final sum of one instance's FP64 loss partials: slots [0, n_a)
 // and [off_b, off_b + n_b) of src.  The first kBlock threads of the calling
 // block add kBlock-strided slots, then each wave's lanes by shuffles, then the

@@ -226,12 +226,28 @@ __global__ __launch_bounds__(kBlock) void prolong_kernel(Levels G, int l, const 
 __device__ inline int field_cells(const Levels &G, int l, int f) {
   return G.n[l][f][0] * G.n[l][f][1] * G.n[l][f][2];
 }
+// e / m for 0 <= e < 2^22 and 1 <= m < 2^12 with rcp = 1 / m: the float
+// quotient is within one of the exact one, which one correction step fixes
+// (the LDS tail kernels index arrays of at most 2^22 elements this way,
+// several times cheaper than an integer division)
+__device__ inline int small_div(int e, int m, float rcp) {
+  int q = (int)((float)e * rcp);
+  const int r = e - q * m;
+  q += (r >= m ? 1 : 0) - (r < 0 ? 1 : 0);
+  return q;
+}
+
+// 3-D index (z, y, x) of element e < 2^22 of an array with dims (., n1, n2)
+__device__ inline void small_index(int e, int n1, int n2, float r1, float r2, int (&i)[3]) {
+  const int q = small_div(e, n2, r2);
+  i[2] = e - q * n2;
+  i[0] = small_div(q, n1, r1);
+  i[1] = q - i[0] * n1;
+}
+
 __device__ inline void field_index(const Levels &G, int l, int f, int e, int (&i)[3]) {
   const int nx = G.n[l][f][2], ny = G.n[l][f][1];
-  i[2] = e % nx;
-  e /= nx;
-  i[1] = e % ny;
-  i[0] = e / ny;
+  small_index(e, ny, nx, 1.0f / (float)ny, 1.0f / (float)nx, i);
 }
 
 // The small coarse levels of one field of one instance per block, in LDS:
@@ -320,27 +336,75 @@ __global__ __launch_bounds__(kBlock) void restrict_kernel(Levels G, int l, T *g,
   if (ADAM) adam_elem_loaded(A, k, val, th, m, v);
 }
 
+// One pass of T^T along axis a (0 z, 1 y, 2 x) over an array in LDS: src has
+// dims n (z, y, x), dst the same dims with n[a] replaced by the coarse extent
+// c.  Cell-based T^T gathers fine 2J-1 .. 2J+2 with 1/4, 3/4, 3/4, 1/4 and the
+// end rows' 5/4, -1/4; node-based fine 2J-1, 2J, 2J+1 with 1/2, 1, 1/2.
+// Applied once per spanned axis it is the tensor-product T^T of one level.
+template <typename T>
+__device__ inline void tail_restrict_pass(const T *__restrict__ src, T *__restrict__ dst,
+                                          const int (&n)[3], int a, int c, bool node) {
+  int m[3] = {n[0], n[1], n[2]};
+  m[a] = c;
+  const int total = m[0] * m[1] * m[2];
+  const float r1 = 1.0f / (float)m[1], r2 = 1.0f / (float)m[2];
+  const int sa = a == 2 ? 1 : (a == 1 ? n[2] : n[1] * n[2]);  // stride of axis a in src
+  const int nf = n[a];
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    int i[3];
+    small_index(e, m[1], m[2], r1, r2, i);
+    const int J = i[a];
+    i[a] = 0;
+    const T *s = src + (i[0] * n[1] + i[1]) * n[2] + i[2];
+    T acc;
+    if (node) {
+      acc = s[2 * J * sa];
+      if (J > 0) acc += T(0.5) * s[(2 * J - 1) * sa];
+      if (2 * J + 1 < nf) acc += T(0.5) * s[(2 * J + 1) * sa];
+    } else {
+      acc = (J == 0 ? T(1.25) : T(0.75)) * s[2 * J * sa] +
+            (J == c - 1 ? T(1.25) : T(0.75)) * s[(2 * J + 1) * sa];
+      if (J >= 1) acc += T(0.25) * s[(2 * J - 1) * sa];
+      if (J <= c - 2) acc += T(0.25) * s[(2 * J + 2) * sa];
+      if (J == 1) acc -= T(0.25) * s[0];
+      if (J == c - 2) acc -= T(0.25) * s[(nf - 1) * sa];
+    }
+    dst[e] = acc;
+  }
+}
+
 // g_{l+1} = T^T g_l for l = l_lo .. L-2 of one field of one instance per
 // block, in LDS, with Adam on every level produced; level l_lo is read from g,
-// every level produced is written back to g.  Two LDS buffers sized for
-// levels l_lo and l_lo + 1 alternate.
+// every level produced is written back to g.  T^T is applied one axis at a
+// time between two LDS regions of cap0 elements each (level l_lo and the
+// passes' outputs).
 // With H.w set (and Adam), each block then does the Horner tail of its field
-// for the updated theta (horner_tail_block with theta_out), so the next
-// iteration starts from it.
+// for the updated theta, w_{L-1} = theta'_{L-1}, w_l = theta'_l + T w_{l+1}
+// down to level H.l_stop, so the next iteration starts from it.  The updated
+// theta of levels l_stop .. L-1 is kept in LDS at element H.toff, level after
+// level: the levels this block produces are stored there by their Adam
+// update, the others (final before the launch) are loaded there at the start.
+// Reads of global memory are issued early: level l_lo of g and the carried
+// theta at the start, each level's Adam state before its passes.
 template <typename T>
 struct CarryTail {
   T *w = nullptr;
-  int l_stop = 0, cap0 = 0;
+  int l_stop = 0, toff = 0;
 };
 
+constexpr int kTailThreads = 1024;
+constexpr int kTailR = 2;  // restricted values per thread per level (cap / kTailThreads)
+
+__device__ inline int field_base(const Levels &G, int l, int inst, int f) {
+  return G.off[l] + inst * G.stride[l] + G.foff[l][f];
+}
+
 template <typename T, bool ADAM>
-__global__ __launch_bounds__(1024) void restrict_tail_kernel(Levels G, int l_lo, int cap0, T *g,
-                                                             AdamArgs<T> A, TermSum S,
-                                                             CarryTail<T> H) {
-  constexpr int kPf = 2;  // outputs per thread of the first level whose Adam state is prefetched
+__global__ __launch_bounds__(kTailThreads) void restrict_tail_kernel(Levels G, int l_lo, int cap0, T *g,
+                                                                     AdamArgs<T> A, TermSum S,
+                                                                     CarryTail<T> H) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T *cur = reinterpret_cast<T *>(smem_raw);
-  T *nxt = cur + cap0;
+  T *const sm = reinterpret_cast<T *>(smem_raw);
   // blocks past the (instance, field) ones sum the loss partials of an
   // earlier kernel, one instance each
   if ((int)blockIdx.x >= G.batch * G.nf) {
@@ -351,65 +415,102 @@ __global__ __launch_bounds__(1024) void restrict_tail_kernel(Levels G, int l_lo,
   }
   const int inst = blockIdx.x / G.nf, f = blockIdx.x % G.nf;
   const int bd = blockDim.x, tid = threadIdx.x;
-  const int base1 = G.off[l_lo + 1] + inst * G.stride[l_lo + 1] + G.foff[l_lo + 1][f];
-  const int n1 = field_cells(G, l_lo + 1, f);
-  T pth[kPf], pm[kPf], pv[kPf];
+  const bool carry = ADAM && H.w != nullptr;
+  T *const tl = sm + H.toff;  // updated theta of levels l_stop .. L-1 (carry)
+
+  // Adam state of the first level produced
+  T th[kTailR], mo[kTailR], vo[kTailR];
+  auto adam_load = [&](int l) {
+    const int base = field_base(G, l, inst, f), n = field_cells(G, l, f);
 #pragma unroll
-  for (int u = 0; u < kPf; ++u) {
-    const int e = tid + u * bd;
-    pth[u] = pm[u] = pv[u] = T(0);
-    if (ADAM && e < n1) {
-      pth[u] = A.th_in[base1 + e];
-      pm[u] = A.m[base1 + e];
-      pv[u] = A.v[base1 + e];
+    for (int u = 0; u < kTailR; ++u) {
+      const int e = tid + u * bd;
+      th[u] = mo[u] = vo[u] = T(0);
+      if (ADAM && e < n) {
+        th[u] = A.th_in[base + e];
+        mo[u] = A.m[base + e];
+        vo[u] = A.v[base + e];
+      }
     }
-  }
+  };
+  adam_load(l_lo + 1);
+  // level l_lo of g, and the theta of the carried levels l_stop .. l_lo
   {
-    const T *src = g + G.off[l_lo] + inst * G.stride[l_lo] + G.foff[l_lo][f];
-    for (int e = tid; e < field_cells(G, l_lo, f); e += bd) cur[e] = src[e];
+    const T *src = g + field_base(G, l_lo, inst, f);
+    const int n = field_cells(G, l_lo, f);
+    for (int e = tid; e < n; e += bd) sm[e] = src[e];
   }
-  __syncthreads();
+  int toff = 0;  // offset in tl of the next level
+  if (carry)
+    for (int j = H.l_stop; j <= l_lo && j < G.L; ++j) {
+      const T *src = A.th_out + field_base(G, j, inst, f);
+      const int n = field_cells(G, j, f);
+      for (int e = tid; e < n; e += bd) tl[toff + e] = src[e];
+      toff += n;
+    }
+  lds_barrier();
+  T *cur = sm, *oth = sm + cap0;
   for (int l = l_lo; l + 1 < G.L; ++l) {
-    const int base = G.off[l + 1] + inst * G.stride[l + 1] + G.foff[l + 1][f];
-    const int n = field_cells(G, l + 1, f);
-    int e0 = tid;
-    if (l == l_lo) {
+    if (l > l_lo) adam_load(l + 1);
+    int n[3] = {G.n[l][f][0], G.n[l][f][1], G.n[l][f][2]};
+    for (int a = 2; a >= 0; --a) {
+      const int c = G.n[l + 1][f][a];
+      if (c == n[a]) continue;  // the field does not span this axis
+      tail_restrict_pass(cur, oth, n, a, c, G.node != 0);
+      n[a] = c;
+      T *t = cur;
+      cur = oth;
+      oth = t;
+      lds_barrier();
+    }
+    // cur holds g_{l+1}
+    const int base = field_base(G, l + 1, inst, f), nl = field_cells(G, l + 1, f);
+    const bool keep = carry && l + 1 >= H.l_stop;
 #pragma unroll
-      for (int u = 0; u < kPf; ++u) {
-        const int e = tid + u * bd;
-        if (e < n) {
-          int I[3];
-          field_index(G, l + 1, f, e, I);
-          const T val = restrict_value_at(G, l, f, I, cur);
-          nxt[e] = val;
-          g[base + e] = val;
-          if (ADAM) adam_elem_loaded(A, base + e, val, pth[u], pm[u], pv[u]);
-        }
-      }
-      e0 = tid + kPf * bd;
-    }
-    for (int e = e0; e < n; e += bd) {
-      T th = T(0), m = T(0), v = T(0);
-      if (ADAM) {
-        th = A.th_in[base + e];
-        m = A.m[base + e];
-        v = A.v[base + e];
-      }
-      int I[3];
-      field_index(G, l + 1, f, e, I);
-      const T val = restrict_value_at(G, l, f, I, cur);
-      nxt[e] = val;
+    for (int u = 0; u < kTailR; ++u) {
+      const int e = tid + u * bd;
+      if (e >= nl) continue;
+      const T val = cur[e];
       g[base + e] = val;
-      if (ADAM) adam_elem_loaded(A, base + e, val, th, m, v);
+      if (ADAM) {
+        const T mm = A.b1 * mo[u] + (T(1) - A.b1) * val;
+        const T vv = A.b2 * vo[u] + (T(1) - A.b2) * val * val;
+        A.m[base + e] = mm;
+        A.v[base + e] = vv;
+        const T tn = adam_theta(th[u], mm, vv, A.step, A.isb2, A.eps);
+        A.th_out[base + e] = tn;
+        if (keep) tl[toff + e] = tn;
+      }
     }
-    __syncthreads();
-    T *t = cur;
-    cur = nxt;
-    nxt = t;
+    if (keep) toff += nl;
+    // the next level's first pass writes oth, which no thread reads any more
   }
-  if (ADAM && H.w)
-    horner_tail_block(G, H.l_stop, H.cap0, (const T *)A.th_out, H.w, inst, f,
-                      reinterpret_cast<T *>(smem_raw));
+  if (!carry) return;
+  lds_barrier();
+  // Horner tail; level l sits in LDS buffer (l - l_stop) & 1 at the start of
+  // the LDS, the restriction's buffers being free
+  T *hb[2] = {sm, sm + field_cells(G, H.l_stop, f)};
+  for (int l = G.L - 1; l >= H.l_stop; --l) {
+    const int n = field_cells(G, l, f);
+    toff -= n;  // now the offset of level l in tl
+    T *dst = hb[(l - H.l_stop) & 1];
+    const T *cs = hb[(l + 1 - H.l_stop) & 1];
+    const int base = field_base(G, l, inst, f);
+    const bool top = l == G.L - 1;
+    const int n1 = G.n[l][f][1], n2 = G.n[l][f][2];
+    const float r1 = 1.0f / (float)n1, r2 = 1.0f / (float)n2;
+    for (int e = tid; e < n; e += bd) {
+      T val = tl[toff + e];
+      if (!top) {
+        int i[3];
+        small_index(e, n1, n2, r1, r2, i);
+        val += prolong_value_at(G, l, f, i, cs);
+        H.w[base + e] = val;
+      }
+      dst[e] = val;
+    }
+    lds_barrier();
+  }
 }
 
 // ---------------------------------------------------------------------- Adam
@@ -875,7 +976,8 @@ static int tail_level(const Levels &G, int lo, size_t elem, size_t budget, long 
       for (int j = from_next ? l + 1 : l; j < G.L; ++j) wf += field_size(G, j, f);
       work = std::max(work, wf);
     }
-    if ((size_t)(max_field(G, l) + max_field(G, l + 1)) * elem <= budget && work <= cap) return l;
+    const long lds = from_next ? 2 * max_field(G, l) : max_field(G, l) + max_field(G, l + 1);
+    if ((size_t)lds * elem <= budget && work <= cap) return l;
   }
   return G.L - 1;
 }
@@ -957,7 +1059,7 @@ static hipError_t restrict_t(modil_ctx *c, void *g_v, int from, const void *th_i
                ? tail_level(G, from, sizeof(T), c->lds_budget - 1024, kTailCapRestrict, true)
                : G.L - 1;
   const int cap0 = lt + 1 < G.L ? (int)max_field(G, lt) : 0;
-  const size_t bytes = lt + 1 < G.L ? (size_t)(cap0 + max_field(G, lt + 1)) * sizeof(T) : 0;
+  const size_t bytes = (size_t)2 * cap0 * sizeof(T);
   if (lt + 1 < G.L && !(ad ? lds_ready(restrict_tail_kernel<T, true>, bytes)
                           : lds_ready(restrict_tail_kernel<T, false>, bytes)))
     lt = G.L - 1;
@@ -980,18 +1082,29 @@ static hipError_t restrict_t(modil_ctx *c, void *g_v, int from, const void *th_i
     int lth, caph;
     size_t bytes_h;
     if (carry && ad && horner_tail_plan(c, G, sizeof(T), lth, caph, bytes_h) &&
-        lds_ready(horner_tail_kernel<T>, bytes_h) &&
-        lds_ready(restrict_tail_kernel<T, true>, std::max(bytes, bytes_h))) {
-      H.w = (T *)c->w_buf;
-      H.l_stop = lth;
-      H.cap0 = caph;
-      lds = std::max(bytes, bytes_h);
-      if (carried) *carried = true;
+        lds_ready(horner_tail_kernel<T>, bytes_h)) {
+      // LDS: the restriction or Horner buffers, then the updated theta of
+      // levels l_stop .. L-1 (the Horner plan caps their count)
+      const size_t toff = (std::max(bytes, bytes_h) + 15) / 16 * 16 / sizeof(T);
+      long nth = 0;
+      for (int f = 0; f < G.nf; ++f) {
+        long n = 0;
+        for (int j = lth; j < G.L; ++j) n += field_size(G, j, f);
+        nth = std::max(nth, n);
+      }
+      const size_t lds_c = (toff + (size_t)nth) * sizeof(T);
+      if (lds_c + 1024 <= c->lds_budget && lds_ready(restrict_tail_kernel<T, true>, lds_c)) {
+        H.w = (T *)c->w_buf;
+        H.l_stop = lth;
+        H.toff = (int)toff;
+        lds = lds_c;
+        if (carried) *carried = true;
+      }
     }
     if (ad)
-      restrict_tail_kernel<T, true><<<blocks, 1024, lds, c->stream>>>(G, lt, cap0, g, A, S, H);
+      restrict_tail_kernel<T, true><<<blocks, kTailThreads, lds, c->stream>>>(G, lt, cap0, g, A, S, H);
     else
-      restrict_tail_kernel<T, false><<<blocks, 1024, lds, c->stream>>>(G, lt, cap0, g, A, S, H);
+      restrict_tail_kernel<T, false><<<blocks, kTailThreads, lds, c->stream>>>(G, lt, cap0, g, A, S, H);
     if (summed) *summed = sum != nullptr;
   }
   return hipGetLastError();

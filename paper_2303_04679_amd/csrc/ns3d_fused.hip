@@ -270,9 +270,10 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
 
   const int key_base = (inst * A.nzt * A.ntx * A.nty + tile) * A.tz;
 
-  // theta (and chi) of the next plane are loaded one iteration ahead
-  T thn[NF], chin = T(0);
-  for (int f = 0; f < NF; ++f) thn[f] = T(0);
+  // theta (and chi) of the next plane are loaded one iteration ahead; theta
+  // of the two planes before is kept for the Adam update of the gather plane
+  T thn[NF], chin = T(0), tA[NF], tB[NF];
+  for (int f = 0; f < NF; ++f) thn[f] = tA[f] = tB[f] = T(0);
   if (in_xy && z0 - 2 >= 0) {
     const uint32_t zb = pofs(z0 - 2);
     for (int f = 0; f < NF; ++f) thn[f] = ld_at(th_base, fo[f] + zb);
@@ -299,7 +300,7 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
       for (int f = 0; f < NF; ++f) thn[f] = ld_at(th_base, fo[f] + zb);
       if (CHI == 1) chin = ld_at(chi_base, fo[0] + zb);
     }
-    T mq[NF], vq[NF], tq[NF];
+    T mq[NF], vq[NF];
     const int q = pz - 2, qb = q & 1;
     const bool gather = own_xy && q >= z0 && q < z1;
     const uint32_t qofs = pofs(q);
@@ -307,7 +308,6 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
       for (int f = 0; f < NF; ++f) {
         mq[f] = ld_at(A.adam.m + inst * A.th_inst, fo[f] + qofs);
         vq[f] = ld_at(A.adam.v + inst * A.th_inst, fo[f] + qofs);
-        tq[f] = ld_at(th_base, fo[f] + qofs);
       }
     }
     // ---- 1. prolong plane pz of this column
@@ -477,10 +477,11 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
           st_at(A.adam.m + base, fo[f] + qofs, mm);
           st_at(A.adam.v + base, fo[f] + qofs, vv);
           st_at(A.adam.th_out + base, fo[f] + qofs,
-                adam_theta(tq[f], mm, vv, A.adam.step, A.adam.isb2, A.adam.eps));
+                adam_theta(tB[f], mm, vv, A.adam.step, A.adam.isb2, A.adam.eps));
         }
       }
     }
+    for (int f = 0; f < NF; ++f) { tB[f] = tA[f]; tA[f] = th[f]; }
     for (int f = 0; f < 5; ++f) Cq[f] = Cs[f];
     // the slot taken by the next coarse plane held the one below this fine
     // plane's pair, which nobody reads after step 1
