@@ -386,10 +386,13 @@ __device__ inline void tail_restrict_pass(const T *__restrict__ src, T *__restri
 // update, the others (final before the launch) are loaded there at the start.
 // Reads of global memory are issued early: level l_lo of g and the carried
 // theta at the start, each level's Adam state before its passes.
+// With H.parts > 1 the Horner tail's last (largest) level is split over that
+// many blocks per field: every part does the (small) restriction and the
+// coarser Horner levels identically, part 0 alone writes what they share.
 template <typename T>
 struct CarryTail {
   T *w = nullptr;
-  int l_stop = 0, toff = 0;
+  int l_stop = 0, toff = 0, parts = 1;
 };
 
 constexpr int kTailThreads = 1024;
@@ -397,6 +400,25 @@ constexpr int kTailR = 2;  // restricted values per thread per level (cap / kTai
 
 __device__ inline int field_base(const Levels &G, int l, int inst, int f) {
   return G.off[l] + inst * G.stride[l] + G.foff[l][f];
+}
+
+// dst[e] = src[e] for e < n, global -> LDS, eight values in flight per thread
+template <typename T>
+__device__ inline void tail_copy_in(T *dst, const T *__restrict__ src, int lo, int hi) {
+  constexpr int kU = 8;
+  for (int e0 = lo + (int)threadIdx.x; e0 < hi; e0 += kU * (int)blockDim.x) {
+    T v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int e = e0 + u * (int)blockDim.x;
+      v[u] = e < hi ? src[e] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int e = e0 + u * (int)blockDim.x;
+      if (e < hi) dst[e] = v[u];
+    }
+  }
 }
 
 template <typename T, bool ADAM>
@@ -407,16 +429,23 @@ __global__ __launch_bounds__(kTailThreads) void restrict_tail_kernel(Levels G, i
   T *const sm = reinterpret_cast<T *>(smem_raw);
   // blocks past the (instance, field) ones sum the loss partials of an
   // earlier kernel, one instance each
-  if ((int)blockIdx.x >= G.batch * G.nf) {
-    const int i = blockIdx.x - G.batch * G.nf;
+  const int nfb = G.batch * G.nf * H.parts;
+  if ((int)blockIdx.x >= nfb) {
+    const int i = blockIdx.x - nfb;
     final_terms(S.partials + (long)i * S.n_part_blocks * kTerms, S.n_a, S.off_b, S.n_b,
                 S.terms + (long)i * kTerms, S.flag);
     return;
   }
-  const int inst = blockIdx.x / G.nf, f = blockIdx.x % G.nf;
+  const int part = blockIdx.x % H.parts, fi = blockIdx.x / H.parts;
+  const int inst = fi / G.nf, f = fi % G.nf;
+  const bool lead = part == 0;  // writes what the parts share
   const int bd = blockDim.x, tid = threadIdx.x;
   const bool carry = ADAM && H.w != nullptr;
   T *const tl = sm + H.toff;  // updated theta of levels l_stop .. L-1 (carry)
+  // this part's slice of the largest Horner level
+  const int n_stop = carry ? field_cells(G, H.l_stop, f) : 0;
+  const int h_lo = (int)((long)n_stop * part / H.parts);
+  const int h_hi = (int)((long)n_stop * (part + 1) / H.parts);
 
   // Adam state of the first level produced
   T th[kTailR], mo[kTailR], vo[kTailR];
@@ -435,17 +464,13 @@ __global__ __launch_bounds__(kTailThreads) void restrict_tail_kernel(Levels G, i
   };
   adam_load(l_lo + 1);
   // level l_lo of g, and the theta of the carried levels l_stop .. l_lo
-  {
-    const T *src = g + field_base(G, l_lo, inst, f);
-    const int n = field_cells(G, l_lo, f);
-    for (int e = tid; e < n; e += bd) sm[e] = src[e];
-  }
+  tail_copy_in(sm, g + field_base(G, l_lo, inst, f), 0, field_cells(G, l_lo, f));
   int toff = 0;  // offset in tl of the next level
   if (carry)
     for (int j = H.l_stop; j <= l_lo && j < G.L; ++j) {
-      const T *src = A.th_out + field_base(G, j, inst, f);
       const int n = field_cells(G, j, f);
-      for (int e = tid; e < n; e += bd) tl[toff + e] = src[e];
+      tail_copy_in(tl + toff, A.th_out + field_base(G, j, inst, f), j == H.l_stop ? h_lo : 0,
+                   j == H.l_stop ? h_hi : n);
       toff += n;
     }
   lds_barrier();
@@ -471,14 +496,16 @@ __global__ __launch_bounds__(kTailThreads) void restrict_tail_kernel(Levels G, i
       const int e = tid + u * bd;
       if (e >= nl) continue;
       const T val = cur[e];
-      g[base + e] = val;
+      if (lead) g[base + e] = val;
       if (ADAM) {
         const T mm = A.b1 * mo[u] + (T(1) - A.b1) * val;
         const T vv = A.b2 * vo[u] + (T(1) - A.b2) * val * val;
-        A.m[base + e] = mm;
-        A.v[base + e] = vv;
         const T tn = adam_theta(th[u], mm, vv, A.step, A.isb2, A.eps);
-        A.th_out[base + e] = tn;
+        if (lead) {
+          A.m[base + e] = mm;
+          A.v[base + e] = vv;
+          A.th_out[base + e] = tn;
+        }
         if (keep) tl[toff + e] = tn;
       }
     }
@@ -499,16 +526,19 @@ __global__ __launch_bounds__(kTailThreads) void restrict_tail_kernel(Levels G, i
     const bool top = l == G.L - 1;
     const int n1 = G.n[l][f][1], n2 = G.n[l][f][2];
     const float r1 = 1.0f / (float)n1, r2 = 1.0f / (float)n2;
-    for (int e = tid; e < n; e += bd) {
+    const bool last = l == H.l_stop;
+    const bool write = last || lead;
+    for (int e = tid + (last ? h_lo : 0); e < (last ? h_hi : n); e += bd) {
       T val = tl[toff + e];
       if (!top) {
         int i[3];
         small_index(e, n1, n2, r1, r2, i);
         val += prolong_value_at(G, l, f, i, cs);
-        H.w[base + e] = val;
+        if (write) H.w[base + e] = val;
       }
       dst[e] = val;
     }
+    if (last) break;
     lds_barrier();
   }
 }
@@ -1075,7 +1105,6 @@ static hipError_t restrict_t(modil_ctx *c, void *g_v, int from, const void *th_i
   }
   if (lt + 1 < G.L) {
     const TermSum S = sum ? *sum : TermSum{};
-    const int blocks = G.batch * G.nf + (sum ? G.batch : 0);
     // carry the next iteration's Horner tail when its LDS fits beside
     CarryTail<T> H;
     size_t lds = bytes;
@@ -1097,10 +1126,13 @@ static hipError_t restrict_t(modil_ctx *c, void *g_v, int from, const void *th_i
         H.w = (T *)c->w_buf;
         H.l_stop = lth;
         H.toff = (int)toff;
+        // split the largest Horner level so a part has about 512 values
+        H.parts = (int)std::min<long>(8, std::max<long>(1, max_field(G, lth) / 512));
         lds = lds_c;
         if (carried) *carried = true;
       }
     }
+    const int blocks = G.batch * G.nf * H.parts + (sum ? G.batch : 0);
     if (ad)
       restrict_tail_kernel<T, true><<<blocks, kTailThreads, lds, c->stream>>>(G, lt, cap0, g, A, S, H);
     else
