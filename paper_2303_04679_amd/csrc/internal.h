@@ -176,6 +176,7 @@ struct modil_ctx {
   bool march_enabled = true;  // MODIL_OPT_MARCH
   int march_tile = 0;         // MODIL_OPT_MARCH_TILE
   bool tail_enabled = true;   // MODIL_OPT_TAIL
+  int carry_stop = 0;  // lowest level of the Horner tail the last restriction tail carried
   bool tile_enabled = true;   // MODIL_OPT_TILE
   size_t lds_budget = 64 * 1024;  // LDS bytes one block of the tail kernels may use
 

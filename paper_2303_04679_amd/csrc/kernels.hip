@@ -250,69 +250,93 @@ __device__ inline void field_index(const Levels &G, int l, int f, int e, int (&i
   small_index(e, ny, nx, 1.0f / (float)ny, 1.0f / (float)nx, i);
 }
 
-// The small coarse levels of one field of one instance per block, in LDS:
-// w_{L-1} = theta_{L-1}, then w_l = theta_l + T w_{l+1} for l = L-2 .. l_stop;
-// every w_l it produces is also written to w (pack layout).  Level l sits in
-// LDS buffer (l - l_stop) % 2, sized for levels l_stop and l_stop + 1.
-// The block's part: field f of instance inst, LDS at smem.
+// dst[e] = src[e] for e < n, global -> LDS, eight values in flight per thread
 template <typename T>
-__device__ inline void horner_tail_block(const Levels &G, int l_stop, int cap0, const T *theta, T *w,
-                                         int inst, int f, T *smem) {
-  constexpr int kPf = 4;  // theta values per thread of the last (largest) level, loaded first
-  T *buf[2] = {smem, smem + cap0};
-  const int bd = blockDim.x, tid = threadIdx.x;
-  const int bstop = G.off[l_stop] + inst * G.stride[l_stop] + G.foff[l_stop][f];
-  const int nstop = field_cells(G, l_stop, f);
-  T pth[kPf];
+__device__ inline void tail_copy_in(T *dst, const T *__restrict__ src, int lo, int hi) {
+  constexpr int kU = 8;
+  for (int e0 = lo + (int)threadIdx.x; e0 < hi; e0 += kU * (int)blockDim.x) {
+    T v[kU];
 #pragma unroll
-  for (int u = 0; u < kPf; ++u) {
-    const int e = tid + u * bd;
-    pth[u] = e < nstop ? theta[bstop + e] : T(0);
-  }
-  {
-    const int l = G.L - 1;
-    T *dst = buf[(l - l_stop) & 1];
-    const T *src = theta + G.off[l] + inst * G.stride[l] + G.foff[l][f];
-    for (int e = tid; e < field_cells(G, l, f); e += bd) dst[e] = src[e];
-  }
-  __syncthreads();
-  for (int l = G.L - 2; l >= l_stop; --l) {
-    T *dst = buf[(l - l_stop) & 1];
-    const T *cs = buf[(l + 1 - l_stop) & 1];
-    const int base = G.off[l] + inst * G.stride[l] + G.foff[l][f];
-    const int n = field_cells(G, l, f);
-    int e0 = tid;
-    if (l == l_stop) {
+    for (int u = 0; u < kU; ++u) {
+      const int e = e0 + u * (int)blockDim.x;
+      v[u] = e < hi ? src[e] : T(0);
+    }
 #pragma unroll
-      for (int u = 0; u < kPf; ++u) {
-        const int e = tid + u * bd;
-        if (e < n) {
-          int i[3];
-          field_index(G, l, f, e, i);
-          const T val = pth[u] + prolong_value_at(G, l, f, i, cs);
-          dst[e] = val;
-          w[base + e] = val;
-        }
-      }
-      e0 = tid + kPf * bd;
+    for (int u = 0; u < kU; ++u) {
+      const int e = e0 + u * (int)blockDim.x;
+      if (e < hi) dst[e] = v[u];
     }
-    for (int e = e0; e < n; e += bd) {
-      int i[3];
-      field_index(G, l, f, e, i);
-      const T val = theta[base + e] + prolong_value_at(G, l, f, i, cs);
-      dst[e] = val;
-      w[base + e] = val;
-    }
-    __syncthreads();
   }
 }
 
+// The Horner tail of the small coarse levels, one field of one instance per
+// `parts` blocks: w_{L-1} = theta_{L-1}, then w_l = theta_l + T w_{l+1} for
+// l = L-2 .. l_stop, every w_l below L-1 written to w (pack layout).  The last
+// (largest) level l_stop is split over the parts; every part computes the
+// levels above it (part 0 writes them).  Levels above l_stop alternate between
+// two LDS buffers of level l_stop + 1's size, level l in buffer
+// (l - l_stop - 1) & 1.  The restriction tail carries the same steps with the
+// same function for the updated theta, so both give the same bits.
 template <typename T>
-__global__ __launch_bounds__(1024) void horner_tail_kernel(Levels G, int l_stop, int cap0,
+__global__ __launch_bounds__(1024) void horner_tail_kernel(Levels G, int l_stop, int parts,
                                                            const T *__restrict__ theta, T *w) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  horner_tail_block(G, l_stop, cap0, theta, w, (int)(blockIdx.x / G.nf), (int)(blockIdx.x % G.nf),
-                    reinterpret_cast<T *>(smem_raw));
+  T *const sm = reinterpret_cast<T *>(smem_raw);
+  constexpr int kPf = 4;  // theta values of the part's slice per thread, loaded first
+  const int part = blockIdx.x % parts, fi = blockIdx.x / parts;
+  const int inst = fi / G.nf, f = fi % G.nf;
+  const bool lead = part == 0;
+  const int bd = blockDim.x, tid = threadIdx.x;
+  const int n_stop = field_cells(G, l_stop, f);
+  const int h_lo = (int)((long)n_stop * part / parts), h_hi = (int)((long)n_stop * (part + 1) / parts);
+  const int bstop = G.off[l_stop] + inst * G.stride[l_stop] + G.foff[l_stop][f];
+  T pth[kPf];
+#pragma unroll
+  for (int u = 0; u < kPf; ++u) {
+    const int e = h_lo + tid + u * bd;
+    pth[u] = e < h_hi ? theta[bstop + e] : T(0);
+  }
+  T *hb[2] = {sm, sm + field_cells(G, l_stop + 1, f)};
+  {
+    const int l = G.L - 1;
+    const T *src = theta + G.off[l] + inst * G.stride[l] + G.foff[l][f];
+    tail_copy_in(hb[(l - l_stop - 1) & 1], src, 0, field_cells(G, l, f));
+  }
+  lds_barrier();
+  for (int l = G.L - 2; l >= l_stop; --l) {
+    const bool last = l == l_stop;
+    T *dst = hb[(l - l_stop - 1) & 1];
+    const T *cs = hb[(l - l_stop) & 1];
+    const int base = G.off[l] + inst * G.stride[l] + G.foff[l][f];
+    const int n1 = G.n[l][f][1], n2 = G.n[l][f][2];
+    const float r1 = 1.0f / (float)n1, r2 = 1.0f / (float)n2;
+    if (last) {
+#pragma unroll
+      for (int u = 0; u < kPf; ++u) {
+        const int e = h_lo + tid + u * bd;
+        if (e < h_hi) {
+          int i[3];
+          small_index(e, n1, n2, r1, r2, i);
+          w[base + e] = pth[u] + prolong_value_at(G, l, f, i, cs);
+        }
+      }
+      for (int e = h_lo + tid + kPf * bd; e < h_hi; e += bd) {
+        int i[3];
+        small_index(e, n1, n2, r1, r2, i);
+        w[base + e] = theta[base + e] + prolong_value_at(G, l, f, i, cs);
+      }
+      break;
+    }
+    const int n = field_cells(G, l, f);
+    for (int e = tid; e < n; e += bd) {
+      int i[3];
+      small_index(e, n1, n2, r1, r2, i);
+      const T val = theta[base + e] + prolong_value_at(G, l, f, i, cs);
+      dst[e] = val;
+      if (lead) w[base + e] = val;
+    }
+    lds_barrier();
+  }
 }
 
 // --------------------------------------------------------------- restriction
@@ -378,17 +402,19 @@ __device__ inline void tail_restrict_pass(const T *__restrict__ src, T *__restri
 // every level produced is written back to g.  T^T is applied one axis at a
 // time between two LDS regions of cap0 elements each (level l_lo and the
 // passes' outputs).
-// With H.w set (and Adam), each block then does the Horner tail of its field
+// With H.w set (and Adam), the blocks then do the Horner tail of their field
 // for the updated theta, w_{L-1} = theta'_{L-1}, w_l = theta'_l + T w_{l+1}
-// down to level H.l_stop, so the next iteration starts from it.  The updated
-// theta of levels l_stop .. L-1 is kept in LDS at element H.toff, level after
-// level: the levels this block produces are stored there by their Adam
-// update, the others (final before the launch) are loaded there at the start.
-// Reads of global memory are issued early: level l_lo of g and the carried
-// theta at the start, each level's Adam state before its passes.
-// With H.parts > 1 the Horner tail's last (largest) level is split over that
-// many blocks per field: every part does the (small) restriction and the
-// coarser Horner levels identically, part 0 alone writes what they share.
+// down to level H.l_stop, so the next iteration starts from it.  The last
+// (largest) level l_stop is split over H.parts blocks per field: every part
+// does the restriction and the Horner levels above l_stop identically (part 0
+// alone writes what they share) and its slice of level l_stop.  Levels above
+// l_stop alternate between two LDS buffers of level l_stop + 1's size.  The
+// updated theta is kept in LDS at element H.toff: the part's slice of level
+// l_stop, then the levels above it in turn; the levels this block produces
+// are stored there by their Adam update, the others (final before the
+// launch) are loaded there at the start.  Reads of global memory are issued
+// early: level l_lo of g and the carried theta at the start, each level's
+// Adam state before its passes.
 template <typename T>
 struct CarryTail {
   T *w = nullptr;
@@ -400,25 +426,6 @@ constexpr int kTailR = 2;  // restricted values per thread per level (cap / kTai
 
 __device__ inline int field_base(const Levels &G, int l, int inst, int f) {
   return G.off[l] + inst * G.stride[l] + G.foff[l][f];
-}
-
-// dst[e] = src[e] for e < n, global -> LDS, eight values in flight per thread
-template <typename T>
-__device__ inline void tail_copy_in(T *dst, const T *__restrict__ src, int lo, int hi) {
-  constexpr int kU = 8;
-  for (int e0 = lo + (int)threadIdx.x; e0 < hi; e0 += kU * (int)blockDim.x) {
-    T v[kU];
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int e = e0 + u * (int)blockDim.x;
-      v[u] = e < hi ? src[e] : T(0);
-    }
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int e = e0 + u * (int)blockDim.x;
-      if (e < hi) dst[e] = v[u];
-    }
-  }
 }
 
 template <typename T, bool ADAM>
@@ -465,13 +472,19 @@ __global__ __launch_bounds__(kTailThreads) void restrict_tail_kernel(Levels G, i
   adam_load(l_lo + 1);
   // level l_lo of g, and the theta of the carried levels l_stop .. l_lo
   tail_copy_in(sm, g + field_base(G, l_lo, inst, f), 0, field_cells(G, l_lo, f));
+  const int slice = h_hi - h_lo;
   int toff = 0;  // offset in tl of the next level
   if (carry)
     for (int j = H.l_stop; j <= l_lo && j < G.L; ++j) {
-      const int n = field_cells(G, j, f);
-      tail_copy_in(tl + toff, A.th_out + field_base(G, j, inst, f), j == H.l_stop ? h_lo : 0,
-                   j == H.l_stop ? h_hi : n);
-      toff += n;
+      const T *src = A.th_out + field_base(G, j, inst, f);
+      if (j == H.l_stop) {
+        tail_copy_in(tl, src + h_lo, 0, slice);
+        toff = slice;
+      } else {
+        const int n = field_cells(G, j, f);
+        tail_copy_in(tl + toff, src, 0, n);
+        toff += n;
+      }
     }
   lds_barrier();
   T *cur = sm, *oth = sm + cap0;
@@ -490,7 +503,7 @@ __global__ __launch_bounds__(kTailThreads) void restrict_tail_kernel(Levels G, i
     }
     // cur holds g_{l+1}
     const int base = field_base(G, l + 1, inst, f), nl = field_cells(G, l + 1, f);
-    const bool keep = carry && l + 1 >= H.l_stop;
+    const bool keep = carry && l + 1 > H.l_stop, keep_slice = carry && l + 1 == H.l_stop;
 #pragma unroll
     for (int u = 0; u < kTailR; ++u) {
       const int e = tid + u * bd;
@@ -507,36 +520,37 @@ __global__ __launch_bounds__(kTailThreads) void restrict_tail_kernel(Levels G, i
           A.th_out[base + e] = tn;
         }
         if (keep) tl[toff + e] = tn;
+        if (keep_slice && e >= h_lo && e < h_hi) tl[e - h_lo] = tn;
       }
     }
     if (keep) toff += nl;
+    if (keep_slice) toff = slice;
     // the next level's first pass writes oth, which no thread reads any more
   }
   if (!carry) return;
   lds_barrier();
-  // Horner tail; level l sits in LDS buffer (l - l_stop) & 1 at the start of
-  // the LDS, the restriction's buffers being free
-  T *hb[2] = {sm, sm + field_cells(G, H.l_stop, f)};
+  // Horner tail; level l > l_stop sits in LDS buffer (l - l_stop - 1) & 1 at
+  // the start of the LDS, the restriction's regions being free
+  T *hb[2] = {sm, sm + field_cells(G, H.l_stop + 1, f)};
   for (int l = G.L - 1; l >= H.l_stop; --l) {
+    const bool last = l == H.l_stop;
     const int n = field_cells(G, l, f);
-    toff -= n;  // now the offset of level l in tl
-    T *dst = hb[(l - H.l_stop) & 1];
-    const T *cs = hb[(l + 1 - H.l_stop) & 1];
+    if (!last) toff -= n;  // now the offset of level l in tl
+    T *dst = hb[(l - H.l_stop - 1) & 1];
+    const T *cs = hb[(l - H.l_stop) & 1];
     const int base = field_base(G, l, inst, f);
     const bool top = l == G.L - 1;
     const int n1 = G.n[l][f][1], n2 = G.n[l][f][2];
     const float r1 = 1.0f / (float)n1, r2 = 1.0f / (float)n2;
-    const bool last = l == H.l_stop;
-    const bool write = last || lead;
     for (int e = tid + (last ? h_lo : 0); e < (last ? h_hi : n); e += bd) {
-      T val = tl[toff + e];
+      T val = last ? tl[e - h_lo] : tl[toff + e];
       if (!top) {
         int i[3];
         small_index(e, n1, n2, r1, r2, i);
         val += prolong_value_at(G, l, f, i, cs);
-        if (write) H.w[base + e] = val;
+        if (last || lead) H.w[base + e] = val;
       }
-      dst[e] = val;
+      if (!last) dst[e] = val;
     }
     if (last) break;
     lds_barrier();
@@ -993,27 +1007,24 @@ static long max_field(const Levels &G, int l) {
   return m;
 }
 
-// The LDS tail kernels give the small coarse levels one block per field and
-// instance.  tail_level returns the smallest level l >= lo whose next level
-// (levels l and l + 1 of a field) fits the LDS budget and below which a block
-// produces at most `cap` values, L - 1 if there is none.  A restriction output
-// gathers up to 96 values, a prolongation output 8, hence separate caps.
-static int tail_level(const Levels &G, int lo, size_t elem, size_t budget, long cap, bool from_next) {
+// The restriction tail gives the small coarse levels one block per field and
+// instance.  tail_level returns the smallest level l >= lo whose two LDS
+// regions (level l's size each, for the one-axis passes) fit the budget and
+// below which a block produces at most `cap` values, L - 1 if there is none.
+static int tail_level(const Levels &G, int lo, size_t elem, size_t budget, long cap) {
   for (int l = lo; l + 1 < G.L; ++l) {
     long work = 0;
     for (int f = 0; f < G.nf; ++f) {
       long wf = 0;
-      for (int j = from_next ? l + 1 : l; j < G.L; ++j) wf += field_size(G, j, f);
+      for (int j = l + 1; j < G.L; ++j) wf += field_size(G, j, f);
       work = std::max(work, wf);
     }
-    const long lds = from_next ? 2 * max_field(G, l) : max_field(G, l) + max_field(G, l + 1);
-    if ((size_t)lds * elem <= budget && work <= cap) return l;
+    if ((size_t)2 * max_field(G, l) * elem <= budget && work <= cap) return l;
   }
   return G.L - 1;
 }
 
-constexpr long kTailCapRestrict = 2048;   // values one block restricts
-constexpr long kTailCapProlong = 16384;   // values one block prolongs
+constexpr long kTailCapRestrict = (long)kTailR * kTailThreads;  // values one block restricts
 
 template <typename K>
 static bool lds_ready(K kernel, size_t bytes) {
@@ -1022,16 +1033,44 @@ static bool lds_ready(K kernel, size_t bytes) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess;
 }
 
-// The Horner tail: w_{L-2} .. w_lt by one launch in LDS (at least two levels,
-// none below 1; level 0 goes to the finest field).  False if it does not apply.
-static bool horner_tail_plan(const modil_ctx *c, const Levels &G, size_t elem, int &lt, int &cap0,
-                             size_t &bytes) {
-  if (!c->tail_enabled || G.L < 3) return false;
-  lt = tail_level(G, 1, elem, c->lds_budget - 1024, kTailCapProlong, false);
-  if (lt > G.L - 3) return false;
-  cap0 = (int)max_field(G, lt);
-  bytes = (size_t)(cap0 + max_field(G, lt + 1)) * elem;
-  return true;
+// The Horner tail of the small levels (horner_tail_kernel, or carried by the
+// restriction tail): levels L-1 .. l_stop, the largest split over `parts`
+// blocks per field.  The lowest level l_stop >= 1 (below L - 1) whose part
+// holds at most kCarrySlice values, with at most kCarryAbove values in the
+// levels above it (every part computes those), whose two LDS buffers of level
+// l_stop + 1 fit.  Both uses take the same plan, so they compute every level
+// with the same function.
+struct HornerPlan {
+  int l_stop = 0, parts = 1;
+  long slice = 0, above = 0;  // per part: values of level l_stop; values above it
+  size_t hbytes = 0;          // LDS of the two buffers
+};
+constexpr long kCarrySlice = 4096;
+constexpr long kCarryAbove = 2048;  // measured: a full 16^3 level in every part costs more than a launch
+constexpr int kCarryParts = 16;
+
+static bool horner_plan(const modil_ctx *c, const Levels &G, size_t elem, HornerPlan &P) {
+  if (!c->tail_enabled) return false;
+  for (int l = 1; l <= G.L - 2; ++l) {
+    const long n_stop = max_field(G, l);
+    const int parts = (int)std::min<long>(kCarryParts, std::max<long>(1, (n_stop + 511) / 512));
+    const long slice = (n_stop + parts - 1) / parts;
+    long above = 0;
+    for (int f = 0; f < G.nf; ++f) {
+      long n = 0;
+      for (int j = l + 1; j < G.L; ++j) n += field_size(G, j, f);
+      above = std::max(above, n);
+    }
+    const size_t hbytes = (size_t)2 * max_field(G, l + 1) * elem;
+    if (slice > kCarrySlice || above > kCarryAbove || hbytes + 1024 > c->lds_budget) continue;
+    P.l_stop = l;
+    P.parts = parts;
+    P.slice = slice;
+    P.above = above;
+    P.hbytes = hbytes;
+    return true;
+  }
+  return false;
 }
 
 // skip_tail: the Horner tail for theta is already in w_buf (carried by the
@@ -1045,12 +1084,13 @@ static hipError_t horner_t(modil_ctx *c, const void *theta_v, void *fine_dst_v, 
   T *fine_dst = fine_dst_v ? (T *)fine_dst_v : w;
   if (G.L == 1) return hipSuccess;
   int l = G.L - 2;
-  int lt, cap0;
-  size_t bytes;
-  if (horner_tail_plan(c, G, sizeof(T), lt, cap0, bytes) && lds_ready(horner_tail_kernel<T>, bytes)) {
-    if (!skip_tail)
-      horner_tail_kernel<T><<<G.batch * G.nf, 1024, bytes, c->stream>>>(G, lt, cap0, theta, w);
-    l = lt - 1;
+  HornerPlan hp;
+  if (skip_tail) {
+    l = c->carry_stop - 1;  // w_{L-2} .. w_{carry_stop} came with the restriction tail
+  } else if (horner_plan(c, G, sizeof(T), hp) && lds_ready(horner_tail_kernel<T>, hp.hbytes)) {
+    horner_tail_kernel<T><<<G.batch * G.nf * hp.parts, 1024, hp.hbytes, c->stream>>>(
+        G, hp.l_stop, hp.parts, theta, w);
+    l = hp.l_stop - 1;
   }
   const int l_end = skip_fine ? 1 : 0;
   for (; l >= l_end; --l) {
@@ -1086,7 +1126,7 @@ static hipError_t restrict_t(modil_ctx *c, void *g_v, int from, const void *th_i
   // levels lt+1 .. L-1 come from one launch of the LDS tail kernel
   // (less 1 KB of the LDS budget for the kernel's static arrays)
   int lt = c->tail_enabled
-               ? tail_level(G, from, sizeof(T), c->lds_budget - 1024, kTailCapRestrict, true)
+               ? tail_level(G, from, sizeof(T), c->lds_budget - 1024, kTailCapRestrict)
                : G.L - 1;
   const int cap0 = lt + 1 < G.L ? (int)max_field(G, lt) : 0;
   const size_t bytes = (size_t)2 * cap0 * sizeof(T);
@@ -1108,27 +1148,19 @@ static hipError_t restrict_t(modil_ctx *c, void *g_v, int from, const void *th_i
     // carry the next iteration's Horner tail when its LDS fits beside
     CarryTail<T> H;
     size_t lds = bytes;
-    int lth, caph;
-    size_t bytes_h;
-    if (carry && ad && horner_tail_plan(c, G, sizeof(T), lth, caph, bytes_h) &&
-        lds_ready(horner_tail_kernel<T>, bytes_h)) {
-      // LDS: the restriction or Horner buffers, then the updated theta of
-      // levels l_stop .. L-1 (the Horner plan caps their count)
-      const size_t toff = (std::max(bytes, bytes_h) + 15) / 16 * 16 / sizeof(T);
-      long nth = 0;
-      for (int f = 0; f < G.nf; ++f) {
-        long n = 0;
-        for (int j = lth; j < G.L; ++j) n += field_size(G, j, f);
-        nth = std::max(nth, n);
-      }
-      const size_t lds_c = (toff + (size_t)nth) * sizeof(T);
+    HornerPlan hp;
+    if (carry && ad && horner_plan(c, G, sizeof(T), hp)) {
+      // LDS: the restriction's regions or the Horner buffers, then the theta
+      // of the part's slice of l_stop and of the levels above
+      const size_t toff = (std::max(bytes, hp.hbytes) + 15) / 16 * 16 / sizeof(T);
+      const size_t lds_c = (toff + (size_t)(hp.slice + hp.above)) * sizeof(T);
       if (lds_c + 1024 <= c->lds_budget && lds_ready(restrict_tail_kernel<T, true>, lds_c)) {
         H.w = (T *)c->w_buf;
-        H.l_stop = lth;
+        H.l_stop = hp.l_stop;
         H.toff = (int)toff;
-        // split the largest Horner level so a part has about 512 values
-        H.parts = (int)std::min<long>(8, std::max<long>(1, max_field(G, lth) / 512));
+        H.parts = hp.parts;
         lds = lds_c;
+        c->carry_stop = hp.l_stop;
         if (carried) *carried = true;
       }
     }
