@@ -124,6 +124,11 @@ __device__ inline void face_add(const NSCoef<T> &K, int axis, T sgi2h, const T (
 // has a forcing array (compiled out otherwise: its pointers would hold scalar
 // registers through the plane loop).
 //
+// The barriers of the plane loop order LDS traffic only (lds_barrier): global
+// loads issued for later planes stay in flight across them, and the stores
+// of the gather drain while the next plane is computed.  No thread reads
+// global memory that another thread of the launch writes.
+//
 // Walls in x and y: a cell next to a wall writes into the halo slot across
 // the wall (outside the grid, so no other cell owns it) the ghost values of
 // its (u, v, w, p), which its stencil then reads like any neighbour, and, for
@@ -249,7 +254,7 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
     cstore(k0 + 1, r1);
     res[k0 & 1] = k0;
     res[(k0 + 1) & 1] = k0 + 1;
-    __syncthreads();
+    lds_barrier();
   }
 
   // planes pz-3 .. pz of this column: U0w is w at pz-3 (the gather's lower
@@ -302,6 +307,12 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
     }
     T mq[NF], vq[NF];
     const int q = pz - 2, qb = q & 1;
+    // the measurement records of plane q (read early: the loop waits on them)
+    int mp0 = 0, mp1 = 0;
+    if (q >= z0 && q < z1) {
+      mp0 = A.mptr[key_base + (q - z0)];
+      mp1 = A.mptr[key_base + (q - z0) + 1];
+    }
     const bool gather = own_xy && q >= z0 && q < z1;
     const uint32_t qofs = pofs(q);
     if (ADAM && gather) {
@@ -353,7 +364,7 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
     if (wym) for (int f = 0; f < 4; ++f) Ul[sb][f][Y - 1][X] = GV(f, 1, 0, U2[f]);
     if (wyp) for (int f = 0; f < 4; ++f) Ul[sb][f][Y + 1][X] = GV(f, 1, 1, U2[f]);
     for (int f = 0; f < 4; ++f) Dl[f][Y][X] = T(0);
-    __syncthreads();
+    lds_barrier();
 
     // ---- 3. residual seeds at plane s; measurement seeds at plane q = pz-2
     T an[4] = {T(0), T(0), T(0), T(0)};
@@ -417,8 +428,7 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
     }
     for (int e = 0; e < 4; ++e) { A0[e] = A1[e]; A1[e] = A2[e]; A2[e] = an[e]; }
     if (q >= z0 && q < z1) {
-      const int key = key_base + (q - z0);
-      const int e0 = A.mptr[key], e1 = A.mptr[key + 1];
+      const int e0 = mp0, e1 = mp1;
       for (int e = e0 + tid; e < e1; e += NS_THREADS) {
         const FusedMeas me = A.mrec[e];
         const int f = me.field, k = me.cell;
@@ -433,7 +443,7 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
         }
       }
     }
-    __syncthreads();
+    lds_barrier();
 
     // ---- 4. gradient, and Adam, at plane q
     if (gather) {
@@ -489,7 +499,7 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
       cstore(cnext, cpre);
       res[cnext & 1] = cnext;
     }
-    __syncthreads();
+    lds_barrier();
   }
 
 #undef GV
