@@ -143,7 +143,7 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
   constexpr int NA = 5;                   // per cell: seeds a_0, a_c (1 - chi), and u for x faces
   __shared__ T Ul[2][4][NST_Y][NST_X];
   __shared__ T Al[2][NA][NST_Y][NST_X];
-  __shared__ T Dl[4][NST_Y][NST_X];
+  __shared__ T Dl[2][4][NST_Y][NST_X];  // data-term gradient, by plane parity
   __shared__ double red[NS_THREADS / 64][kTerms];
   static_assert(sizeof(T) == 4, "FP32 fields");
   // two coarse planes (coarse plane K in slot K & 1): the one a fine plane
@@ -307,11 +307,11 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
     }
     T mq[NF], vq[NF];
     const int q = pz - 2, qb = q & 1;
-    // the measurement records of plane q (read early: the loop waits on them)
+    // the measurement records of plane pz-1 (read early: the loop waits on them)
     int mp0 = 0, mp1 = 0;
-    if (q >= z0 && q < z1) {
-      mp0 = A.mptr[key_base + (q - z0)];
-      mp1 = A.mptr[key_base + (q - z0) + 1];
+    if (pz - 1 >= z0 && pz - 1 < z1) {
+      mp0 = A.mptr[key_base + (pz - 1 - z0)];
+      mp1 = A.mptr[key_base + (pz - 1 - z0) + 1];
     }
     const bool gather = own_xy && q >= z0 && q < z1;
     const uint32_t qofs = pofs(q);
@@ -363,10 +363,10 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
     if (wxp) for (int f = 0; f < 4; ++f) Ul[sb][f][Y][X + 1] = GV(f, 2, 1, U2[f]);
     if (wym) for (int f = 0; f < 4; ++f) Ul[sb][f][Y - 1][X] = GV(f, 1, 0, U2[f]);
     if (wyp) for (int f = 0; f < 4; ++f) Ul[sb][f][Y + 1][X] = GV(f, 1, 1, U2[f]);
-    for (int f = 0; f < 4; ++f) Dl[f][Y][X] = T(0);
+    for (int f = 0; f < 4; ++f) Dl[sb][f][Y][X] = T(0);
     lds_barrier();
 
-    // ---- 3. residual seeds at plane s; measurement seeds at plane q = pz-2
+    // ---- 3. residual and measurement seeds at plane s
     T an[4] = {T(0), T(0), T(0), T(0)};
     T Cs[5] = {T(0), T(0), T(0), T(0), T(0)};
     if (seed_xy && s >= 0 && s < nz && s >= z0 - 1 && s <= z1) {
@@ -427,25 +427,27 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
       }
     }
     for (int e = 0; e < 4; ++e) { A0[e] = A1[e]; A1[e] = A2[e]; A2[e] = an[e]; }
-    if (q >= z0 && q < z1) {
+    // measurements of plane s: their gradient is gathered one plane later
+    if (s >= z0 && s < z1) {
       const int e0 = mp0, e1 = mp1;
       for (int e = e0 + tid; e < e1; e += NS_THREADS) {
         const FusedMeas me = A.mrec[e];
         const int f = me.field, k = me.cell;
-        const T uv = Ul[qb][f][me.ly][me.lx];
+        const T uv = Ul[sb][f][me.ly][me.lx];
         const double r = (double)uv - me.val;
         part[me.term] += me.w * r * r;
         if (e == e0 || A.mrec[e - 1].field != f || A.mrec[e - 1].cell != k) {
           double gs = 0.0;
           for (int j = e; j < e1 && A.mrec[j].field == f && A.mrec[j].cell == k; ++j)
             gs += 2.0 * A.mrec[j].w * ((double)uv - A.mrec[j].val);
-          Dl[f][me.ly][me.lx] = T(gs);
+          Dl[sb][f][me.ly][me.lx] = T(gs);
         }
       }
     }
-    lds_barrier();
 
-    // ---- 4. gradient, and Adam, at plane q
+    // ---- 4. gradient, and Adam, at plane q: it reads what the previous plane
+    // wrote to LDS and its own column's seeds of plane s, so it shares the
+    // phase of the seeds of plane s
     if (gather) {
       T g[4] = {Cq[0], Cq[1], Cq[2], Cq[3]};
       // z faces: the neighbours below and above, or the wall's ghost map
@@ -476,7 +478,7 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
       NS_XY_FACE(2, T(-1), Y, X + 1, Al[qb][4][Y][X + 1])
 #undef NS_XY_FACE
       T gg[5];
-      for (int f = 0; f < 4; ++f) gg[f] = g[f] + Dl[f][Y][X];
+      for (int f = 0; f < 4; ++f) gg[f] = g[f] + Dl[qb][f][Y][X];
       gg[4] = Cq[4];
       const int base = inst * A.th_inst;
       for (int f = 0; f < NF; ++f) {
