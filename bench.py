@@ -116,8 +116,9 @@ def measured_traffic(workload, kernel_class):
 
     profiles/traffic_<workload>.json holds FETCH_SIZE and WRITE_SIZE of the
     dominant kernel, scaled by what the same counters read for a plain device
-    copy of known size, together with the SHA-256 of the kernel sources at the
-    time; a changed source makes the figure stale (None).
+    copy of known size, together with the SHA-256 of that kernel's source
+    files (listed in the record) at the time; a changed source makes the
+    figure stale (None).
     """
     import hashlib
     here = os.path.dirname(os.path.abspath(__file__))
@@ -125,12 +126,15 @@ def measured_traffic(workload, kernel_class):
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    if rec.get("kernel_class") != kernel_class:
+    if rec.get("kernel_class") != kernel_class or not rec.get("sources"):
         return None
     h = hashlib.sha256()
     csrc = os.path.join(here, "paper_2303_04679_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        h.update(open(os.path.join(csrc, name), "rb").read())
+    for name in rec["sources"]:
+        f = os.path.join(csrc, name)
+        if not os.path.exists(f):
+            return None
+        h.update(open(f, "rb").read())
     if h.hexdigest() != rec.get("source_sha256"):
         return None
     return rec["fetch_bytes"] + rec["write_bytes"]

@@ -226,10 +226,11 @@ __global__ __launch_bounds__(kBlock) void prolong_kernel(Levels G, int l, const 
 __device__ inline int field_cells(const Levels &G, int l, int f) {
   return G.n[l][f][0] * G.n[l][f][1] * G.n[l][f][2];
 }
-// e / m for 0 <= e < 2^22 and 1 <= m < 2^12 with rcp = 1 / m: the float
-// quotient is within one of the exact one, which one correction step fixes
-// (the LDS tail kernels index arrays of at most 2^22 elements this way,
-// several times cheaper than an integer division)
+// e / m for 0 <= e < 2^22 and m >= 1 with rcp = 1 / m (rounded): e is exact
+// in float and the product is within 2^-23 relative of e / m, i.e. less than
+// 1/2 from it, so the truncated quotient is off by at most one, which one
+// correction step fixes (the LDS tail kernels index arrays of far fewer than
+// 2^22 elements this way, several times cheaper than an integer division)
 __device__ inline int small_div(int e, int m, float rcp) {
   int q = (int)((float)e * rcp);
   const int r = e - q * m;
