@@ -370,7 +370,25 @@ def test_fused_channel_batch():
 def test_run_equals_steps(op, dims, L, dtype, n):
     """modil_run of n iterations equals n modil_step calls bit for bit
     (packs, moments and the last loss terms)."""
+    _run_equals_steps(op, dims, L, dtype, n)
+
+
+@pytest.mark.parametrize("op,dims,L,dtype", [("ns3d", (32, 32, 64), 4, "f32"),
+                                             ("cavity", (128, 128), 5, "f32"),
+                                             ("cavity_node", (64, 64), 4, "f64"),
+                                             ("heat", (256, 256), 6, "f64"),
+                                             ("ns3d", (128, 128, 128), 6, "f32")])
+def test_run_equals_steps_split_tail(op, dims, L, dtype):
+    """Sizes whose Horner tail splits its largest level over several blocks per
+    field, evenly or not (the restriction tail carries that split from one
+    iteration to the next; the 128^3 channel flow is the benchmark workload):
+    modil_run of 4 iterations equals 4 modil_step calls bit for bit."""
+    _run_equals_steps(op, dims, L, dtype, 4)
+
+
+def _run_equals_steps(op, dims, L, dtype, n):
     need_gpu()
+    print(f"\n[parity] run == steps {op} {dims} L={L} {dtype} n={n}", flush=True)
     spec = case(op, dims, L, seed=21, with_forcing=op != "poisson")
     lv = rounded(_levels(spec, 22), dtype)
     ctx = context_of(spec, dtype)
