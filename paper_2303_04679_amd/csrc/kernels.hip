@@ -792,12 +792,14 @@ struct TileMeas {
 };
 
 // ADAM: also Adam on level 0 of every field spanning the grid (A0: level-0
-// pointers of theta_in / theta_out / m / v, the pack layout)
-template <class Op, typename T, int TX, int TY, bool ADAM>
-__global__ __launch_bounds__(TX * TY) void fine_tile_kernel(FineArgs<T> A, int tiles_x, TileMeas M,
-                                                            AdamArgs<T> A0) {
+// pointers of theta_in / theta_out / m / v, the pack layout).  NT threads
+// (at least TX * TY): the first TX * TY own one cell each for the gather.
+template <class Op, typename T, int TX, int TY, int NT, bool ADAM>
+__global__ __launch_bounds__(NT) void fine_tile_kernel(FineArgs<T> A, int tiles_x, TileMeas M,
+                                                       AdamArgs<T> A0) {
   using FT = FineTile<TX, TY>;
-  constexpr int NT = TX * TY, NF = Op::NF, NE = Op::NE;
+  constexpr int NF = Op::NF, NE = Op::NE;
+  static_assert(NT >= TX * TY, "a thread per owned cell");
   __shared__ T Ut[NF][FT::UY][FT::UX];
   __shared__ T St[NF][7][FT::SY][FT::SX];
   __shared__ T Dt[NF][TY][TX];  // gradient of the data terms at the owned cells
@@ -805,7 +807,23 @@ __global__ __launch_bounds__(TX * TY) void fine_tile_kernel(FineArgs<T> A, int t
   const int x0 = (blockIdx.x % tiles_x) * TX, y0 = (blockIdx.x / tiles_x) * TY;
   const int ny = A.p.n[1], nx = A.p.n[2];
   const T *ub = A.u + (long)inst * A.ff.inst_stride;
-  for (int f = 0; f < NF; ++f) Dt[f][tid / TX][tid % TX] = T(0);
+  const bool owner = tid < TX * TY;
+  const int cx = tid % TX, cy = tid / TX, ox = x0 + cx, oy = y0 + cy;
+  const bool own_cell = owner && ox < nx && oy < ny;
+  if (owner)
+    for (int f = 0; f < NF; ++f) Dt[f][cy][cx] = T(0);
+  // Adam state of the owned cell, loaded first so its latency overlaps the
+  // residuals
+  T ath[NF], am[NF], av[NF];
+  for (int f = 0; f < NF; ++f) {
+    ath[f] = am[f] = av[f] = T(0);
+    if (ADAM && A.want_grad && own_cell && f != A.xonly_field) {
+      const long k = (long)inst * A.ff.inst_stride + A.ff.off[f] + (long)oy * nx + ox;
+      ath[f] = A0.th_in[k];
+      am[f] = A0.m[k];
+      av[f] = A0.v[k];
+    }
+  }
   for (int k = tid; k < FT::UX * FT::UY; k += NT) {
     const int X = k % FT::UX, Y = k / FT::UX, x = x0 - 2 + X, y = y0 - 2 + Y;
     const bool in = x >= 0 && x < nx && y >= 0 && y < ny;
@@ -865,8 +883,8 @@ __global__ __launch_bounds__(TX * TY) void fine_tile_kernel(FineArgs<T> A, int t
   }
   if (A.want_grad) {
     __syncthreads();
-    const int cx = tid % TX, cy = tid / TX, x = x0 + cx, y = y0 + cy;
-    if (x < nx && y < ny) {
+    const int x = ox, y = oy;
+    if (own_cell) {
       T gacc[NF];
       for (int f = 0; f < NF; ++f) gacc[f] = T(0);
       for (int o = 0; o < 7; ++o) {
@@ -888,7 +906,7 @@ __global__ __launch_bounds__(TX * TY) void fine_tile_kernel(FineArgs<T> A, int t
         } else {
           const long k = (long)inst * A.ff.inst_stride + A.ff.off[f] + c;
           A.g[k] = gf;
-          if (ADAM) adam_elem(A0, (int)k, gf);
+          if (ADAM) adam_elem_loaded(A0, (int)k, gf, ath[f], am[f], av[f]);
         }
       }
     }
@@ -1294,12 +1312,13 @@ static void launch_fine_tile(modil_ctx *c, const FineArgs<T> &A, const AdamArgs<
   c->fine_slots = (long)nbx * nby;
   const TileMeas M{c->tm_ptr, c->tm_rec};
   const dim3 grid(nbx * nby, c->prob.batch);
+  // the 16 x 4 tile forms residuals on 18 x 6 cells: two waves take them in one pass
   if (tx == 32) {
-    if (adam) fine_tile_kernel<Op, T, 32, 8, true><<<grid, 256, 0, c->stream>>>(A, nbx, M, A0);
-    else fine_tile_kernel<Op, T, 32, 8, false><<<grid, 256, 0, c->stream>>>(A, nbx, M, A0);
+    if (adam) fine_tile_kernel<Op, T, 32, 8, 256, true><<<grid, 256, 0, c->stream>>>(A, nbx, M, A0);
+    else fine_tile_kernel<Op, T, 32, 8, 256, false><<<grid, 256, 0, c->stream>>>(A, nbx, M, A0);
   } else {
-    if (adam) fine_tile_kernel<Op, T, 16, 4, true><<<grid, 64, 0, c->stream>>>(A, nbx, M, A0);
-    else fine_tile_kernel<Op, T, 16, 4, false><<<grid, 64, 0, c->stream>>>(A, nbx, M, A0);
+    if (adam) fine_tile_kernel<Op, T, 16, 4, 128, true><<<grid, 128, 0, c->stream>>>(A, nbx, M, A0);
+    else fine_tile_kernel<Op, T, 16, 4, 128, false><<<grid, 128, 0, c->stream>>>(A, nbx, M, A0);
   }
 }
 
