@@ -1312,10 +1312,11 @@ static void launch_fine_tile(modil_ctx *c, const FineArgs<T> &A, const AdamArgs<
   c->fine_slots = (long)nbx * nby;
   const TileMeas M{c->tm_ptr, c->tm_rec};
   const dim3 grid(nbx * nby, c->prob.batch);
-  // the 16 x 4 tile forms residuals on 18 x 6 cells: two waves take them in one pass
+  // residuals are formed on the tile plus a one-cell ring (34 x 10, 18 x 6
+  // cells): six and two waves take them in one pass
   if (tx == 32) {
-    if (adam) fine_tile_kernel<Op, T, 32, 8, 256, true><<<grid, 256, 0, c->stream>>>(A, nbx, M, A0);
-    else fine_tile_kernel<Op, T, 32, 8, 256, false><<<grid, 256, 0, c->stream>>>(A, nbx, M, A0);
+    if (adam) fine_tile_kernel<Op, T, 32, 8, 384, true><<<grid, 384, 0, c->stream>>>(A, nbx, M, A0);
+    else fine_tile_kernel<Op, T, 32, 8, 384, false><<<grid, 384, 0, c->stream>>>(A, nbx, M, A0);
   } else {
     if (adam) fine_tile_kernel<Op, T, 16, 4, 128, true><<<grid, 128, 0, c->stream>>>(A, nbx, M, A0);
     else fine_tile_kernel<Op, T, 16, 4, 128, false><<<grid, 128, 0, c->stream>>>(A, nbx, M, A0);
