@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
+#include "multigrid.h"
 
 namespace modil {
 
@@ -222,6 +223,34 @@ __global__ __launch_bounds__(64 * kMarchWaves) void restrict_march_kernel(Levels
 
   const int cnz = nz >> 1;
   const int Z0 = zc * ZR;
+  if (ZR == 1) {
+    // one coarse plane per wave: every fine plane it gathers (a window of four
+    // and the end planes, restrict_taps6; zero weights are skipped, uniformly
+    // over the wave) is loaded before any is used, so the wave waits on memory
+    // once instead of once per step of the march
+    int iz[6];
+    T wz[6];
+    restrict_taps6(Z0, cnz, iz, wz);
+    const long e0 = cbase + (long)Z0 * plane_c + row0;
+    load_adam<T, YR, ADAM>(A, e0, cnx, th, m, v);
+    RowLoad<T, SEG> rows[6][2 * YR + 2];
+#pragma unroll
+    for (int t = 0; t < 6; ++t)
+      if (wz[t] != T(0)) load_plane<T, YR, SEG>(fb + iz[t] * plane_f, nx, Y0, ny, cx, lo_off, hi_off, rows[t]);
+    T acc[YR];
+#pragma unroll
+    for (int j = 0; j < YR; ++j) acc[j] = T(0);
+#pragma unroll
+    for (int t = 0; t < 6; ++t)
+      if (wz[t] != T(0)) {
+        T P[YR];
+        y_restrict<T, YR, SEG>(rows[t], W, gl, cx, cnx, Y0, ny, P);
+#pragma unroll
+        for (int j = 0; j < YR; ++j) acc[j] += wz[t] * P[j];
+      }
+    emit_rows<T, YR, ADAM>(g, A, e0, cnx, acc, th, m, v);
+    return;
+  }
   T Ap[YR], Ac[YR], An[YR];
 #pragma unroll
   for (int j = 0; j < YR; ++j) Ap[j] = Ac[j] = An[j] = T(0);
