@@ -9,6 +9,10 @@
   ns3d64       channel flow past an ellipsoid, 64^3, FP32, L = 5, unknown
                u, v, w, p, chihat; velocity measured on the wake plane
   ns3d128      the same at 128^3, L = 6
+  ns3d128_shard8  one GPU's share of ns3d128 split in z-slabs over eight
+               GPUs: 16 x 128 x 128 cells at the same spacing, L = 4 (the
+               levels a slab keeps; the coarser ones would be replicated);
+               its z faces are walls here, where a rank would have halos
   cavity128    lid-driven cavity, 128 x 128, FP32, L = 5, Re ~ U(100, 1000),
                velocity at 64 random cells
 
@@ -73,6 +77,20 @@ def ns3d(n=128, levels=6, seed=6, dtype="f32"):
     return Workload(f"ns3d{n}", spec, meas, {"u": 1.0}, 1e-3, 3000, chi=chi)
 
 
+def ns3d_shard(n=128, ranks=8, levels=4, seed=6, dtype="f32"):
+    nz = n // ranks
+    spec = ProblemSpec("ns3d", (nz, n, n), (nz / n, 1.0, 1.0), levels, dtype=dtype,
+                       max_meas=3 * nz * n, re=60.0, diam=0.4, lam=1.0, chi_shift=5.0,
+                       tau_coef=0.5, u_ref=1.0, w_pde=1.0)
+    plane = synth.wake_plane_cells((nz, n, n))
+    g = synth.rng(seed + 100)
+    meas = []
+    for c, (mean, spread) in enumerate(((1.0, 0.1), (0.0, 0.05), (0.0, 0.05))):
+        vals = mean + spread * g.standard_normal(plane.size)
+        meas.append((0, c, "data", plane, vals, 1.0 / (n * n)))
+    return Workload(f"ns3d{n}_shard{ranks}", spec, meas, {"u": 1.0}, 1e-3, 3000)
+
+
 def cavity128(batch=1, seed=0):
     n = 128
     spec = ProblemSpec("cavity", (n, n), (1.0, 1.0), 5, dtype="f32", batch=batch,
@@ -92,6 +110,7 @@ WORKLOADS = {
     "heat256_f32": lambda: heat256("f32"),
     "ns3d64": lambda: ns3d(64, 5),
     "ns3d128": lambda: ns3d(128, 6),
+    "ns3d128_shard8": lambda: ns3d_shard(128, 8, 4),
     "cavity128": cavity128,
 }
 

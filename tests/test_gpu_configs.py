@@ -1,5 +1,6 @@
-"""Parity at the full sizes of the five benchmark workloads, through the same
-contexts bench.py times (fused channel-flow path for the 3-D problems)."""
+"""Parity at the full sizes of the benchmark workloads (and of one GPU's share
+of the 128^3 channel flow), through the same contexts bench.py times (fused
+channel-flow path for the 3-D problems)."""
 import numpy as np
 import pytest
 import torch
@@ -13,7 +14,7 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("name", ["burgers64", "heat256", "heat256_f32", "ns3d64", "ns3d128",
-                                  "cavity128"])
+                                  "ns3d128_shard8", "cavity128"])
 def test_workload_loss_and_gradient(name):
     need_gpu()
     print(f"\n[parity] workload {name}", flush=True)
