@@ -75,6 +75,26 @@ __device__ inline float adam_theta<float>(float th, float m, float v, float step
 // The memory clobber keeps the compiler from moving memory accesses across it.
 __device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
+// e / m for 0 <= e < 2^22 and m >= 1 with rcp = 1 / m (rounded): e is exact
+// in float and the product is within 2^-23 relative of e / m, i.e. less than
+// 1/2 from it, so the truncated quotient is off by at most one, which one
+// correction step fixes (the LDS tail kernels index arrays of far fewer than
+// 2^22 elements this way, several times cheaper than an integer division)
+__device__ inline int small_div(int e, int m, float rcp) {
+  int q = (int)((float)e * rcp);
+  const int r = e - q * m;
+  q += (r >= m ? 1 : 0) - (r < 0 ? 1 : 0);
+  return q;
+}
+
+// 3-D index (z, y, x) of element e < 2^22 of an array with dims (., n1, n2)
+__device__ inline void small_index(int e, int n1, int n2, float r1, float r2, int (&i)[3]) {
+  const int q = small_div(e, n2, r2);
+  i[2] = e - q * n2;
+  i[0] = small_div(q, n1, r1);
+  i[1] = q - i[0] * n1;
+}
+
 // Fixed-order final sum of one instance's FP64 loss partials: slots [0, n_a)
 // and [off_b, off_b + n_b) of src.  The first kBlock threads of the calling
 // block add kBlock-strided slots, then each wave's lanes by shuffles, then the
@@ -283,6 +303,10 @@ bool launch_restrict_march(const Levels &G, int l, T *g, const AdamArgs<T> &A, b
 template <typename T>
 bool launch_prolong_block(const Levels &G, int l, const T *theta, const T *csrc, T *dst,
                           hipStream_t s);
+// Two Horner steps (levels l + 2 -> l) in one launch where the levels admit it.
+template <typename T>
+bool launch_prolong2(const Levels &G, int l, const T *th_l, const T *th_m, const T *csrc, T *dst,
+                     hipStream_t s);
 hipError_t launch_adam(modil_ctx *c, const void *theta_in, void *theta_out, void *m, void *v,
                        const void *g, long n, const AdamHost &h);
 // generic finest-level kernel (tiled on 2-D problems); with adam given (tiled

@@ -226,26 +226,6 @@ __global__ __launch_bounds__(kBlock) void prolong_kernel(Levels G, int l, const 
 __device__ inline int field_cells(const Levels &G, int l, int f) {
   return G.n[l][f][0] * G.n[l][f][1] * G.n[l][f][2];
 }
-// e / m for 0 <= e < 2^22 and m >= 1 with rcp = 1 / m (rounded): e is exact
-// in float and the product is within 2^-23 relative of e / m, i.e. less than
-// 1/2 from it, so the truncated quotient is off by at most one, which one
-// correction step fixes (the LDS tail kernels index arrays of far fewer than
-// 2^22 elements this way, several times cheaper than an integer division)
-__device__ inline int small_div(int e, int m, float rcp) {
-  int q = (int)((float)e * rcp);
-  const int r = e - q * m;
-  q += (r >= m ? 1 : 0) - (r < 0 ? 1 : 0);
-  return q;
-}
-
-// 3-D index (z, y, x) of element e < 2^22 of an array with dims (., n1, n2)
-__device__ inline void small_index(int e, int n1, int n2, float r1, float r2, int (&i)[3]) {
-  const int q = small_div(e, n2, r2);
-  i[2] = e - q * n2;
-  i[0] = small_div(q, n1, r1);
-  i[1] = q - i[0] * n1;
-}
-
 __device__ inline void field_index(const Levels &G, int l, int f, int e, int (&i)[3]) {
   const int nx = G.n[l][f][2], ny = G.n[l][f][1];
   small_index(e, ny, nx, 1.0f / (float)ny, 1.0f / (float)nx, i);
@@ -1114,6 +1094,13 @@ static hipError_t horner_t(modil_ctx *c, const void *theta_v, void *fine_dst_v, 
   const int l_end = skip_fine ? 1 : 0;
   for (; l >= l_end; --l) {
     const T *src = (l == G.L - 2) ? theta + G.off[l + 1] : w + G.off[l + 1];
+    // two steps at once where the levels admit it (w_l is then never written)
+    if (l - 1 >= l_end && c->march_enabled &&
+        launch_prolong2<T>(G, l - 1, theta + G.off[l - 1], theta + G.off[l], src,
+                           (l - 1 == 0) ? fine_dst : w + G.off[l - 1], c->stream)) {
+      --l;
+      continue;
+    }
     T *dst = (l == 0) ? fine_dst : w + G.off[l];
     if (c->march_enabled && launch_prolong_block<T>(G, l, theta + G.off[l], src, dst, c->stream))
       continue;

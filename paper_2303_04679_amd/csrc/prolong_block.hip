@@ -10,7 +10,10 @@
 // around it; theta and the result move as pairs along x.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "internal.h"
+#include "multigrid.h"
 
 namespace modil {
 
@@ -120,6 +123,186 @@ __global__ __launch_bounds__(256) void prolong_block_kernel(Levels G, int l, con
     }
   (void)nz;
 }
+
+// Two Horner steps in one launch, for cell-based fields spanning z, y and x:
+// w_l = theta_l + T (theta_{l+1} + T w_{l+2}).  The level-(l+1) values are
+// formed in LDS where a block needs them and are never written.  A block
+// takes rows [y0, y0 + kP2Rows) of plane Jz of level l+1 of one field of one
+// instance: it stages the level-(l+2) planes that level-(l+1) planes Jz-1 ..
+// Jz+1 interpolate from, forms those planes on the rows y0-1 .. y0+kP2Rows
+// (theta_{l+1} plus the eight-tap T), and writes the level-l cells the owned
+// cells cover, one level-(l+1) cell per thread with the three-tap weights of
+// pair_weights along each axis (the same arithmetic as prolong_block_kernel).
+// All its global reads are issued when it starts.
+constexpr int kP2Threads = 512;
+
+template <typename T>
+__global__ __launch_bounds__(kP2Threads) void prolong2_kernel(Levels G, int l, int rows,
+                                                              const T *__restrict__ th_l,
+                                                              const T *__restrict__ th_m,
+                                                              const T *__restrict__ csrc,
+                                                              T *__restrict__ dst) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *const Cs = reinterpret_cast<T *>(smem_raw);
+  const int ny = G.n[l][0][1], nx = G.n[l][0][2];
+  const int mz = G.n[l + 1][0][0], my = G.n[l + 1][0][1], mx = G.n[l + 1][0][2];
+  const int cz = G.n[l + 2][0][0], cy = G.n[l + 2][0][1], cx = G.n[l + 2][0][2];
+  const int nyb = (my + rows - 1) / rows;  // row blocks per plane
+  int b = blockIdx.x;
+  const int yb = b % nyb;
+  b /= nyb;
+  const int Jz = b % mz, fi = b / mz;
+  const int f = fi % G.nf, inst = fi / G.nf;
+  const int tid = threadIdx.x;
+  const int y0 = yb * rows, y1 = y0 + rows < my ? y0 + rows : my;
+  // level-(l+1) planes m_lo .. m_hi on rows r_lo .. r_hi - 1, and the
+  // level-(l+2) planes they read (whole)
+  const int m_lo = Jz > 0 ? Jz - 1 : 0, m_hi = Jz < mz - 1 ? Jz + 1 : mz - 1;
+  const int r_lo = y0 > 0 ? y0 - 1 : 0, r_hi = y1 < my ? y1 + 1 : my;
+  int c_lo = (m_lo >> 1) - 1, c_hi = (m_hi >> 1) + 1;
+  c_lo = c_lo < 0 ? 0 : c_lo;
+  c_hi = c_hi > cz - 1 ? cz - 1 : c_hi;
+  const int cplane = cy * cx, mrows = r_hi - r_lo, mslab = mrows * mx;
+  const int ncs = (c_hi - c_lo + 1) * cplane, nms = (m_hi - m_lo + 1) * mslab;
+  T *const Ms = Cs + ncs;
+  const T *cb = csrc + (long)inst * G.stride[l + 2] + G.foff[l + 2][f] + (long)c_lo * cplane;
+  const T *mb = th_m + (long)inst * G.stride[l + 1] + G.foff[l + 1][f];
+  const long fb = (long)inst * G.stride[l] + G.foff[l][f];
+  const float rs = 1.0f / (float)mslab, rx = 1.0f / (float)mx;
+  // the loads: coarse planes (kC per thread), theta_{l+1} of the mid slab
+  // (kM), theta_l of the eight cells the thread's level-(l+1) cell covers
+  constexpr int kC = 2, kM = 4;
+  T cv[kC], mv[kM];
+#pragma unroll
+  for (int u = 0; u < kC; ++u) {
+    const int e = tid + u * kP2Threads;
+    cv[u] = e < ncs ? cb[e] : T(0);
+  }
+#pragma unroll
+  for (int u = 0; u < kM; ++u) {
+    const int e = tid + u * kP2Threads;
+    mv[u] = T(0);
+    if (e < nms) {
+      const int k = small_div(e, mslab, rs), rem = e - k * mslab, j = small_div(rem, mx, rx);
+      mv[u] = mb[((long)(m_lo + k) * my + r_lo + j) * mx + (rem - j * mx)];
+    }
+  }
+  const bool own = tid < (y1 - y0) * mx;
+  const int Jy = own ? y0 + small_div(tid, mx, rx) : y0, Jx = own ? tid - (Jy - y0) * mx : 0;
+  T tf[2][2][2];
+#pragma unroll
+  for (int ez = 0; ez < 2; ++ez)
+#pragma unroll
+    for (int ey = 0; ey < 2; ++ey) {
+      const long o = fb + ((long)(2 * Jz + ez) * ny + (2 * Jy + ey)) * nx + 2 * Jx;
+#pragma unroll
+      for (int ex = 0; ex < 2; ++ex) tf[ez][ey][ex] = own ? th_l[o + ex] : T(0);
+    }
+#pragma unroll
+  for (int u = 0; u < kC; ++u) {
+    const int e = tid + u * kP2Threads;
+    if (e < ncs) Cs[e] = cv[u];
+  }
+  lds_barrier();  // the theta loads stay in flight
+  // level-(l+1) slab: theta_{l+1} + T w_{l+2}
+#pragma unroll
+  for (int u = 0; u < kM; ++u) {
+    const int e = tid + u * kP2Threads;
+    if (e >= nms) continue;
+    const int kk = small_div(e, mslab, rs), rem = e - kk * mslab, jj = small_div(rem, mx, rx);
+    const int k = m_lo + kk, j = r_lo + jj, i = rem - jj * mx;
+    int iz[2], iy[2], ix[2];
+    T wz[2], wy[2], wx[2];
+    prolong_taps(k, cz, iz, wz);
+    prolong_taps(j, cy, iy, wy);
+    prolong_taps(i, cx, ix, wx);
+    T acc = T(0);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int bb = 0; bb < 2; ++bb) {
+        const T *r = Cs + (iz[a] - c_lo) * cplane + iy[bb] * cx;
+        acc += wz[a] * wy[bb] * (wx[0] * r[ix[0]] + wx[1] * r[ix[1]]);
+      }
+    Ms[e] = mv[u] + acc;
+  }
+  lds_barrier();
+  if (!own) return;
+  // the eight level-l cells of level-(l+1) cell (Jz, Jy, Jx)
+  T wz[2][3], wy[2][3], wx[2][3];
+  pair_weights(Jz, mz, wz);
+  pair_weights(Jy, my, wy);
+  pair_weights(Jx, mx, wx);
+  const int ks[3] = {Jz > 0 ? Jz - 1 : Jz, Jz, Jz < mz - 1 ? Jz + 1 : Jz};
+  const int js[3] = {Jy > 0 ? Jy - 1 : Jy, Jy, Jy < my - 1 ? Jy + 1 : Jy};
+  const int is[3] = {Jx > 0 ? Jx - 1 : Jx, Jx, Jx < mx - 1 ? Jx + 1 : Jx};
+  T X[3][3][2];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int bb = 0; bb < 3; ++bb) {
+      const T *r = Ms + (ks[a] - m_lo) * mslab + (js[bb] - r_lo) * mx;
+      const T v0 = r[is[0]], v1 = r[is[1]], v2 = r[is[2]];
+#pragma unroll
+      for (int e = 0; e < 2; ++e) X[a][bb][e] = wx[e][0] * v0 + wx[e][1] * v1 + wx[e][2] * v2;
+    }
+#pragma unroll
+  for (int ez = 0; ez < 2; ++ez)
+#pragma unroll
+    for (int ey = 0; ey < 2; ++ey) {
+      T v[2];
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        T acc = T(0);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const T yv = wy[ey][0] * X[a][0][e] + wy[ey][1] * X[a][1][e] + wy[ey][2] * X[a][2][e];
+          acc += wz[ez][a] * yv;
+        }
+        v[e] = tf[ez][ey][e] + acc;
+      }
+      const long o = fb + ((long)(2 * Jz + ez) * ny + (2 * Jy + ey)) * nx + 2 * Jx;
+      dst[o] = v[0];
+      dst[o + 1] = v[1];
+    }
+}
+
+// Launch the two-step Horner kernel for levels l + 2 -> l (w_l into dst;
+// th_l, th_m and dst are the level-l and level-(l+1) bases of theta and the
+// level-l base of the output, csrc the level-(l+2) base) if the levels admit
+// it: cell-based, every field the same 3-D shape halving along every axis,
+// and the per-thread load counts and LDS within the kernel's.  A block takes
+// kP2Threads / mx rows of a level-(l+1) plane.  False if nothing launched.
+template <typename T>
+bool launch_prolong2(const Levels &G, int l, const T *th_l, const T *th_m, const T *csrc, T *dst,
+                     hipStream_t s) {
+  if (G.node || l + 2 >= G.L) return false;
+  for (int j = l; j <= l + 2; ++j)
+    for (int f = 1; f < G.nf; ++f)
+      for (int a = 0; a < 3; ++a)
+        if (G.n[j][f][a] != G.n[j][0][a]) return false;
+  for (int j = l; j < l + 2; ++j)
+    for (int a = 0; a < 3; ++a)
+      if (G.n[j][0][a] != 2 * G.n[j + 1][0][a] || G.n[j + 1][0][a] < 2) return false;
+  const int mz = G.n[l + 1][0][0], my = G.n[l + 1][0][1], mx = G.n[l + 1][0][2];
+  const int cy = G.n[l + 2][0][1], cx = G.n[l + 2][0][2];
+  if (mx > kP2Threads) return false;
+  const int rows = std::min(my, kP2Threads / mx);  // owned rows per block
+  const long mslab = (long)(rows + 2) * mx;
+  // the loads per thread the kernel holds: coarse planes (2), mid slab (4)
+  if (4L * cy * cx > 2L * kP2Threads || 3 * mslab > 4L * kP2Threads) return false;
+  const size_t lds = (size_t)(4L * cy * cx + 3 * mslab) * sizeof(T);
+  if (lds > 64 * 1024) return false;
+  const long blocks = (long)G.batch * G.nf * mz * ((my + rows - 1) / rows);
+  if (blocks > (1L << 30)) return false;
+  prolong2_kernel<T><<<(unsigned)blocks, kP2Threads, lds, s>>>(G, l, rows, th_l, th_m, csrc, dst);
+  return true;
+}
+
+template bool launch_prolong2<float>(const Levels &, int, const float *, const float *, const float *,
+                                     float *, hipStream_t);
+template bool launch_prolong2<double>(const Levels &, int, const double *, const double *,
+                                      const double *, double *, hipStream_t);
 
 // Launch the block Horner step of level l (w_l into dst; theta and dst are
 // level-l bases in the pack layout, csrc the level-(l+1) base) if the level
