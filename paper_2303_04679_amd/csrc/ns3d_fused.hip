@@ -12,11 +12,11 @@
 // through a chunk of planes.  Its 768 threads hold the tile with a 2-cell
 // halo: 20 rows of 32 cache-line-aligned columns (the owned rows and the two
 // halo rows on each side) and two more waves for the four halo columns.  Each
-// thread keeps its column's last four prolonged planes and three planes of
-// residual seeds in registers; the current planes of fields and seeds are
-// staged in LDS for the xy neighbours, and so is each cell's derivatives,
-// from its seed pass to its gradient pass.  Seeds are formed for the owned cells
-// plus a 1-cell halo, the gradient for the owned cells.  The coarse plane
+// thread keeps its column's last prolonged planes, three planes of residual
+// seeds and its cell's own (centre) sensitivity in registers; the current
+// planes of fields and seeds are staged in LDS for the xy neighbours.  Seeds
+// are formed for the owned cells plus a 1-cell halo, the gradient for the
+// owned cells.  The coarse plane
 // interpolation is cached per column, so each coarse plane is read once per
 // two fine planes.  Blocks are mapped to tiles so that every XCD works on one
 // contiguous slab of z-chunks and neighbouring tiles share its L2.
