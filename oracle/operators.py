@@ -456,6 +456,84 @@ def cavity_node_residual(spec, fields):
     return res
 
 
+def channel_node_residual(spec, fields):
+    """Channel flow past a body on node-based values (Sections 2.2, 3.5).
+
+    Nodes x_i = i h on each axis (z, y, x).  Boundary nodes carry no equation;
+    the boundary conditions are imposed on their values, whatever the fine
+    field holds there:
+      inlet (x = 0)      u = (u_ref, 0, 0); p of the interior node next to it,
+      outlet (x = L)     p = 0; the velocity of the interior node next to it,
+      walls (y, z ends)  free slip: the normal velocity component is zero, the
+                         other components and p are those of the interior node
+                         next to the wall.
+    Nodes on an edge or a corner of the box lie in no interior node's 7-point
+    star, so the order of these substitutions does not matter.  Continuity
+    (with the pressure stabilisation) and the penalised momentum equations
+    hold at the interior nodes with central differences, as in the cell-based
+    form.  Returns [continuity, momentum u, momentum v, momentum w] on the
+    interior nodes."""
+    u, v, w, p = (x.clone() for x in fields[:4])
+    P = spec.params
+    u_ref = P.get("u_ref", 1.0)
+    # inlet and outlet (axis 2)
+    u[:, :, 0] = u_ref
+    v[:, :, 0] = 0.0
+    w[:, :, 0] = 0.0
+    p[:, :, 0] = p[:, :, 1]
+    for f in (u, v, w):
+        f[:, :, -1] = f[:, :, -2]
+    p[:, :, -1] = 0.0
+    # free-slip walls: y ends (normal component v), z ends (normal component w)
+    for f in (u, w, p):
+        f[:, 0, :] = f[:, 1, :]
+        f[:, -1, :] = f[:, -2, :]
+    v[:, 0, :] = 0.0
+    v[:, -1, :] = 0.0
+    for f in (u, v, p):
+        f[0, :, :] = f[1, :, :]
+        f[-1, :, :] = f[-2, :, :]
+    w[0, :, :] = 0.0
+    w[-1, :, :] = 0.0
+
+    h = spec.h
+    inner = (slice(1, -1),) * 3
+
+    def nb(f, a, s):   # values of the neighbours at offset s along axis a
+        idx = list(inner)
+        idx[a] = slice(1 + s, f.shape[a] - 1 + s)
+        return f[tuple(idx)]
+
+    def d1(f, a):
+        return (nb(f, a, 1) - nb(f, a, -1)) / (2.0 * h[a])
+
+    def d2(f, a):
+        return (nb(f, a, 1) - 2.0 * f[inner] + nb(f, a, -1)) / h[a] ** 2
+
+    vel = [u, v, w]           # component c points along axis 2 - c
+    axis_of = [2, 1, 0]
+    if spec.op == "ns3d":
+        chi = ns3d_chi(spec, fields[4])[inner]
+    else:
+        chi = torch.as_tensor(spec.chi, dtype=DT)[inner]
+    nu = P.get("diam", 0.4) / P["re"]
+    lam = P.get("lam", 1.0)
+    tau = P.get("tau_coef", 0.5)
+    cont = sum(d1(vel[c], axis_of[c]) for c in range(3))
+    cont = cont - sum(tau * h[a] * d2(p, a) for a in range(3))
+    res = [cont]
+    for c in range(3):
+        conv = sum(vel[k][inner] * d1(vel[c], axis_of[k]) for k in range(3))
+        lap = sum(d2(vel[c], a) for a in range(3))
+        body = conv + d1(p, axis_of[c]) - nu * lap
+        res.append((1.0 - chi) * body + lam * chi * vel[c][inner])
+    for e in range(4):
+        f = spec.forcing.get(e)
+        if f is not None:
+            res[e] = res[e] - torch.as_tensor(f, dtype=DT)[inner]
+    return res
+
+
 def residuals(spec, fine):
     """PDE residual arrays of the problem for the list of fine fields."""
     op = spec.op
@@ -463,6 +541,8 @@ def residuals(spec, fine):
         return poisson_node_residual(spec, fine[0])
     if op == "cavity" and spec.centering == "node":
         return cavity_node_residual(spec, fine)
+    if op in ("ns3d", "ns3d_fixed") and spec.centering == "node":
+        return channel_node_residual(spec, fine)
     if op == "poisson":
         return poisson_residual(spec, fine[0])
     if op == "burgers":

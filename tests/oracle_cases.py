@@ -3,6 +3,8 @@
 Each builder returns an oracle Spec plus the list-of-levels shapes; inputs
 are drawn from the seeded synthetic-input module.
 """
+import math
+
 import numpy as np
 
 from oracle import operators as ops
@@ -51,6 +53,19 @@ def case(op, dims, n_levels, seed=0, with_forcing=False):
         spec.meas = [(c, "data", plane, g.uniform(-1, 1, size=n), 1.0 / n) for c in range(3)]
         if op == "ns3d_fixed":
             spec.chi = synth.rng(seed + 31).uniform(0, 1, size=dims)
+    elif op in ("ns3d_node", "ns3d_fixed_node"):
+        base = op[:-5]
+        spec = ops.Spec(base, dims, (1.0, 1.0, 2.0), n_levels,
+                        params=dict(NS_PARAMS, u_ref=0.8),
+                        weights={"pde": 1.0, "data": 1.0}, centering="node")
+        shape = tuple(d + 1 for d in dims)
+        n = max(2, min(96, math.prod(dims) // 16))
+        # interior nodes only (the boundary nodes carry imposed values)
+        idx = synth.unique_cells(seed + 21, shape, lo=(1,) * 3, hi=dims, n=n)
+        g = synth.rng(seed + 22)
+        spec.meas = [(c, "data", idx, g.uniform(-1, 1, size=n), 1.0 / n) for c in range(3)]
+        if base == "ns3d_fixed":
+            spec.chi = synth.rng(seed + 31).uniform(0, 1, size=shape)
     elif op in ("cavity", "cavity_node"):
         node = op == "cavity_node"
         spec = ops.Spec("cavity", dims, (1.0, 1.0), n_levels,
@@ -66,7 +81,8 @@ def case(op, dims, n_levels, seed=0, with_forcing=False):
     else:
         raise ValueError(op)
     if with_forcing:
-        neq = {"burgers": 1, "heat": 1, "ns3d": 4, "ns3d_fixed": 4, "cavity": 3, "cavity_node": 3}[op]
+        neq = {"burgers": 1, "heat": 1, "ns3d": 4, "ns3d_fixed": 4, "ns3d_node": 4,
+               "ns3d_fixed_node": 4, "cavity": 3, "cavity_node": 3}[op]
         g = synth.rng(seed + 51)
         shape = tuple(d + 1 for d in dims) if spec.centering == "node" else dims
         spec.forcing = {e: g.uniform(-1, 1, size=shape) for e in range(neq)}

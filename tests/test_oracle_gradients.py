@@ -26,6 +26,8 @@ CASES = [
     ("heat", (8, 8), 3),
     ("ns3d", (4, 4, 4), 2),
     ("ns3d_fixed", (4, 4, 4), 2),
+    ("ns3d_node", (4, 4, 4), 2),
+    ("ns3d_fixed_node", (4, 2, 4), 2),
     ("cavity", (8, 8), 3),
     ("cavity_node", (8, 8), 3),
     ("cavity_node", (8, 4), 2),

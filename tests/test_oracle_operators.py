@@ -498,3 +498,172 @@ def test_node_lbfgs_converges_fast_in_1d():
     fine = ops.fine_fields(spec, [[torch.as_tensor(a[0])] for a in split(it.x)])[0].numpy()
     fine = fine * ops.poisson_node_interior(fine.shape).numpy()  # boundary values imposed
     assert np.max(np.abs(fine - u_ref)) < 1e-12, (k, np.max(np.abs(fine - u_ref)))
+
+
+# ---------------------------------------------------- node-based channel flow
+_NS_NODE = {"re": 50.0, "diam": 0.4, "lam": 2.0, "chi_shift": 5.0, "tau_coef": 0.5}
+
+
+def _channel_node_spec(dims, lengths, chi, u_ref=0.8, forcing=None):
+    return ops.Spec("ns3d_fixed", dims, lengths, 1, params=dict(_NS_NODE, u_ref=u_ref),
+                    weights={"pde": 1.0}, chi=chi, centering="node", forcing=forcing or {})
+
+
+def _node_grid(dims, lengths):
+    axes = [np.arange(n + 1) * (L / n) for n, L in zip(dims, lengths)]
+    return np.meshgrid(*axes, indexing="ij")   # Z, Y, X
+
+
+def _scramble_boundary(f, seed):
+    """Replace every boundary node's value by noise (the operator must not read it)."""
+    inside = ops.poisson_node_interior(f.shape).numpy()
+    rng = np.random.default_rng(seed)
+    return f * inside + 7.0 * (1 - inside) * rng.standard_normal(f.shape)
+
+
+def _channel(spec, u, v, w, p, seed=None):
+    fs = [u, v, w, p]
+    if seed is not None:
+        fs = [_scramble_boundary(f, seed + k) for k, f in enumerate(fs)]
+    return [r.numpy() for r in ops.channel_node_residual(spec, [torch.tensor(f) for f in fs])]
+
+
+def test_channel_node_exact_for_products_of_quadratics():
+    """Fields that are quadratic along each axis separately, where central
+    first and second differences are exact: away from the boundary (nodes
+    whose stars touch no boundary node) the node residuals are the continuous
+    penalised Navier-Stokes operators with the pressure stabilisation
+    tau h_a d2p/da2, body fraction included."""
+    dims, lengths = (6, 6, 10), (1.0, 1.2, 2.0)
+    Z, Y, X = _node_grid(dims, lengths)
+    rng = np.random.default_rng(17)
+
+    def quad(s):
+        a, b, c = rng.uniform(-1, 1, 3)
+        return a + b * s + c * s * s, b + 2 * c * s, 2 * c * np.ones_like(s)
+
+    F = []   # (value, first derivatives along z, y, x, second derivatives along z, y, x)
+    for _ in range(4):
+        (qz, dz, zz), (qy, dy, yy), (qx, dx, xx) = quad(Z), quad(Y), quad(X)
+        F.append((qz * qy * qx, (dz * qy * qx, qz * dy * qx, qz * qy * dx),
+                  (zz * qy * qx, qz * yy * qx, qz * qy * xx)))
+    chi = rng.uniform(0, 1, size=Z.shape)
+    h = tuple(L / n for L, n in zip(lengths, dims))
+    nu, lam, tau = 0.4 / 50.0, 2.0, 0.5
+    vel, P = F[:3], F[3]
+    axis_of = [2, 1, 0]   # velocity component c points along axis 2 - c
+    R = _channel(_channel_node_spec(dims, lengths, chi), *(f[0] for f in vel), P[0])
+    for r in R:
+        assert r.shape == tuple(d - 1 for d in dims)
+    deep = (slice(2, -2),) * 3      # on the node grid
+    rdeep = (slice(1, -1),) * 3     # on the interior-node arrays
+    cont = sum(vel[c][1][axis_of[c]] for c in range(3)) - sum(tau * h[a] * P[2][a] for a in range(3))
+    np.testing.assert_allclose(R[0][rdeep], cont[deep], rtol=1e-11, atol=1e-11)
+    for c in range(3):
+        body = (sum(vel[k][0] * vel[c][1][axis_of[k]] for k in range(3)) + P[1][axis_of[c]]
+                - nu * sum(vel[c][2]))
+        want = (1 - chi) * body + lam * chi * vel[c][0]
+        np.testing.assert_allclose(R[1 + c][rdeep], want[deep], rtol=1e-11, atol=1e-11)
+
+
+def test_channel_node_uniform_flow_is_exact():
+    """The free stream u = (u_ref, 0, 0), p = 0 without a body satisfies every
+    boundary condition: all residuals vanish, whatever the boundary nodes hold."""
+    dims, lengths = (4, 6, 8), (1.0, 1.0, 2.0)
+    shape = tuple(d + 1 for d in dims)
+    z = np.zeros(shape)
+    R = _channel(_channel_node_spec(dims, lengths, z), np.full(shape, 0.8), z, z, z, seed=3)
+    for r in R:
+        assert float(np.abs(r).max()) == 0.0
+
+
+def test_channel_node_inlet_and_outlet():
+    """u = u_ref + a x, p = s (x - L) without a body.  The inlet imposes
+    u = u_ref (on the line) and copies p from the first interior node; the
+    outlet imposes p = 0 (on the line) and copies the velocity.  Next to the
+    inlet the pressure sees half the slope and a one-sided second difference;
+    next to the outlet the velocity does; elsewhere the line is exact."""
+    dims, lengths = (4, 4, 8), (1.0, 1.0, 2.0)
+    Z, Y, X = _node_grid(dims, lengths)
+    a, s, u_ref = 0.3, -1.5, 0.8
+    h, nx = lengths[2] / dims[2], dims[2]
+    nu, tau = 0.4 / 50.0, 0.5
+    spec = _channel_node_spec(dims, lengths, np.zeros(X.shape), u_ref=u_ref)
+    z = np.zeros(X.shape)
+    cont, mu, mv, mw = _channel(spec, u_ref + a * X, z, z, s * (X - lengths[2]), seed=9)
+    xi = np.arange(1, nx) * h
+    ux = np.full(nx - 1, a)
+    uxx = np.zeros(nx - 1)
+    ux[-1], uxx[-1] = a / 2, -a / h
+    px = np.full(nx - 1, s)
+    pxx = np.zeros(nx - 1)
+    px[0], pxx[0] = s / 2, s / h
+    # the outlet node copies u(N-1), so the node next to it sees u = u_ref + a x there
+    ui = u_ref + a * xi
+    want_cont = ux - tau * h * pxx
+    want_mu = ui * ux + px - nu * uxx
+    for zi in range(dims[0] - 1):
+        for yi in range(dims[1] - 1):
+            np.testing.assert_allclose(cont[zi, yi], want_cont, rtol=1e-12, atol=1e-13)
+            np.testing.assert_allclose(mu[zi, yi], want_mu, rtol=1e-12, atol=1e-13)
+    assert float(np.abs(mv).max()) == 0.0 and float(np.abs(mw).max()) == 0.0
+
+
+@pytest.mark.parametrize("wall_axis", [0, 1])
+def test_channel_node_free_slip_walls(wall_axis):
+    """Across the walls of axis 0 (z) or 1 (y): the normal component n = b q,
+    q = s (L - s), vanishes on the wall and is quadratic, so it is exact; the
+    tangential u = u_ref + c s is copied to the wall node (zero normal
+    derivative), which halves its slope and gives a one-sided second difference
+    next to the wall.  Checked away from the inlet and outlet."""
+    dims, lengths = (6, 6, 8), (1.0, 1.0, 2.0)
+    G = _node_grid(dims, lengths)
+    S = G[wall_axis]
+    Ls, n = lengths[wall_axis], dims[wall_axis]
+    h = Ls / n
+    b, c, u_ref = 0.7, 0.4, 0.8
+    nu = 0.4 / 50.0
+    z = np.zeros(S.shape)
+    normal = b * S * (Ls - S)
+    u = u_ref + c * S
+    v, w = (normal, z) if wall_axis == 1 else (z, normal)
+    spec = _channel_node_spec(dims, lengths, z, u_ref=u_ref)
+    cont, mu, mv, mw = _channel(spec, u, v, w, z, seed=21)
+    si = np.arange(1, n) * h
+    us = np.full(n - 1, c)
+    uss = np.zeros(n - 1)
+    us[0] = us[-1] = c / 2
+    uss[0], uss[-1] = c / h, -c / h
+    nv = b * si * (Ls - si)
+    ns = b * (Ls - 2 * si)
+    want = {"cont": ns, "mu": nv * us - nu * uss, "mn": nv * ns + 2 * nu * b}
+    mn, mt = (mv, mw) if wall_axis == 1 else (mw, mv)
+    xs = slice(1, -1)   # away from the inlet and outlet nodes' neighbours
+    for name, arr in (("cont", cont), ("mu", mu), ("mn", mn)):
+        arr = np.moveaxis(arr, wall_axis, 0)[:, :, xs]
+        np.testing.assert_allclose(arr, np.broadcast_to(want[name][:, None, None], arr.shape),
+                                   rtol=1e-12, atol=1e-13, err_msg=name)
+    assert float(np.abs(mt).max()) == 0.0
+
+
+def test_channel_node_boundary_values_do_not_matter():
+    """Every boundary node's value is replaced (imposed or copied): the loss
+    does not depend on the fine field there and its gradient is zero."""
+    dims = (4, 4, 8)
+    shape = tuple(d + 1 for d in dims)
+    spec = ops.Spec("ns3d", dims, (1.0, 1.0, 2.0), 1, params=dict(_NS_NODE, u_ref=1.0),
+                    weights={"pde": 1.0}, centering="node")
+    rng = np.random.default_rng(12)
+    f = [rng.standard_normal(shape) for _ in range(5)]
+    g = [_scramble_boundary(x, 40 + k) for k, x in enumerate(f)]
+    assert ops.loss_value(spec, [f])["pde"] == ops.loss_value(spec, [g])["pde"]
+    _, gr = ops.loss_and_grad(spec, [f])
+    mask = ops.poisson_node_interior(shape).numpy()
+    for k in range(5):
+        assert np.all(gr[0][k][mask == 0] == 0.0)
+        assert np.linalg.norm(gr[0][k]) > 0
+
+
+def test_channel_node_level_shapes():
+    assert ops.level_shapes("ns3d", (64, 64, 128), 3, "node") == \
+        [[(65, 65, 129)] * 5, [(33, 33, 65)] * 5, [(17, 17, 33)] * 5]
