@@ -149,10 +149,11 @@ def oracle_baseline(workload, theta_levels, seconds):
     op = "ns3d_fixed" if spec.chi_fixed else spec.op
     ospec = ops.Spec(op, spec.dims, spec.lengths, spec.n_levels,
                      params={"re": spec.re, "diam": spec.diam, "lam": spec.lam,
-                             "chi_shift": spec.chi_shift, "tau_coef": spec.tau_coef},
+                             "chi_shift": spec.chi_shift, "tau_coef": spec.tau_coef,
+                             "u_ref": spec.u_ref},
                      weights={"pde": spec.w_pde, "reg": spec.w_reg, "bc": spec.w_bc},
                      meas=[(f, t, idx, vals, w) for inst, f, t, idx, vals, w in workload.meas if inst == 0],
-                     chi=workload.chi if spec.chi_fixed else None)
+                     chi=workload.chi if spec.chi_fixed else None, centering=spec.centering)
     state = [[(x, x * 0.0, x * 0.0) for x in row] for row in theta_levels]
     t0 = time.perf_counter()
     it = 0

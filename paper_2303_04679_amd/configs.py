@@ -1,4 +1,4 @@
-"""The five benchmark workloads, as ProblemSpec + seeded synthetic inputs.
+"""The benchmark workloads, as ProblemSpec + seeded synthetic inputs.
 
   burgers64    1-D inviscid Burgers, space-time 64 x 64, x in [-1, 1], t in
                [0, 1], FP64, levels 64..4 (L = 5), data at 32 random inner
@@ -15,6 +15,10 @@
                its z faces are walls here, where a rank would have halos
   cavity128    lid-driven cavity, 128 x 128, FP32, L = 5, Re ~ U(100, 1000),
                velocity at 64 random cells
+  channel_node129  the channel of the body-shape study on its node grid:
+               129 x 65 x 65 nodes over [0, 2] x [0, 1] x [0, 1] (h = 1/64),
+               FP32, L = 6, unknown u, v, w, p, chihat; velocity at a
+               19 x 6 x 6 lattice of nodes (684 points)
 
 Measured values are seeded synthetic numbers of the magnitude of the
 solution (the throughput of one iteration does not depend on them); the
@@ -91,6 +95,34 @@ def ns3d_shard(n=128, ranks=8, levels=4, seed=6, dtype="f32"):
     return Workload(f"ns3d{n}_shard{ranks}", spec, meas, {"u": 1.0}, 1e-3, 3000)
 
 
+def channel_node_lattice(dims, m=6):
+    """Flat node indices [z][y][x] of a lattice of 19 x-positions (x = 0.1 ..
+    1.9) times m x m evenly spaced (y, z) positions, each at its nearest node;
+    dims are cells (z, y, x) of [0, 1] x [0, 1] x [0, 2]."""
+    nz, ny, nx = dims
+    h = 2.0 / nx
+    ys = (np.arange(m) + 0.5) / m
+    out = [(int(round(z / h)) * (ny + 1) + int(round(y / h))) * (nx + 1) + int(round(x / h))
+           for x in 0.1 * np.arange(1, 20) for y in ys for z in ys]
+    out = np.array(out, dtype=np.int32)
+    assert np.unique(out).size == out.size
+    return np.sort(out)
+
+
+def channel_node129(seed=6, dtype="f32"):
+    dims = (64, 64, 128)
+    pts = channel_node_lattice(dims)
+    spec = ProblemSpec("ns3d", dims, (1.0, 1.0, 2.0), 6, dtype=dtype, max_meas=3 * pts.size,
+                       re=60.0, diam=0.4, lam=1.0, chi_shift=5.0, tau_coef=0.5, u_ref=1.0,
+                       w_pde=1.0, centering="node")
+    g = synth.rng(seed + 100)
+    meas = []
+    for c, (mean, spread) in enumerate(((1.0, 0.1), (0.0, 0.05), (0.0, 0.05))):
+        vals = mean + spread * g.standard_normal(pts.size)
+        meas.append((0, c, "data", pts, vals, 1.0 / pts.size))
+    return Workload("channel_node129", spec, meas, {"u": 1.0}, 1e-3, 20000)
+
+
 def cavity128(batch=1, seed=0):
     n = 128
     spec = ProblemSpec("cavity", (n, n), (1.0, 1.0), 5, dtype="f32", batch=batch,
@@ -112,6 +144,7 @@ WORKLOADS = {
     "ns3d128": lambda: ns3d(128, 6),
     "ns3d128_shard8": lambda: ns3d_shard(128, 8, 4),
     "cavity128": cavity128,
+    "channel_node129": channel_node129,
 }
 
 

@@ -70,8 +70,10 @@ int validate(const modil_problem *p, std::string &msg) {
     return MODIL_ERR_DTYPE;
   }
   if (p->centering != MODIL_CELL &&
-      !(p->centering == MODIL_NODE && (p->op == MODIL_OP_POISSON || p->op == MODIL_OP_CAVITY))) {
-    msg = "node-based values are implemented for MODIL_OP_POISSON and MODIL_OP_CAVITY only";
+      !(p->centering == MODIL_NODE && (p->op == MODIL_OP_POISSON || p->op == MODIL_OP_CAVITY ||
+                                       p->op == MODIL_OP_NS3D))) {
+    msg = "node-based values are implemented for MODIL_OP_POISSON, MODIL_OP_CAVITY and "
+          "MODIL_OP_NS3D only";
     return MODIL_ERR_DTYPE;
   }
   const int want = expected_ndim(p->op);
@@ -135,7 +137,7 @@ int validate(const modil_problem *p, std::string &msg) {
 
 struct Carve {
   size_t w, g, gq, partials, terms, flag, m_idx, m_field, m_term, m_ptr, m_val, m_w, inst_re;
-  size_t fm_ptr, fm_rec, tm_ptr, tm_rec, end;
+  size_t fm_ptr, fm_rec, tm_ptr, tm_rec, sens, end;
   long n_fine_blocks, n_data_blocks, n_keys;
 };
 
@@ -143,7 +145,7 @@ struct Carve {
 // measurement buckets (0 for other operators)
 void fused_geometry(const modil_problem &p, long &blocks, long &keys) {
   blocks = keys = 0;
-  if (p.op != MODIL_OP_NS3D) return;
+  if (p.op != MODIL_OP_NS3D || p.centering != MODIL_CELL) return;
   int tz, nzt, ntx, nty, ox, oy;
   ns3d_tiles(p, tz, nzt, ntx, nty, ox, oy);
   blocks = (long)nzt * ntx * nty;
@@ -178,6 +180,7 @@ Carve carve(const modil_problem &p, const modil_pack_layout &L) {
   bool xonly = false;
   for (int f = 0; f < L.n_fields; ++f) xonly |= field_is_x_only(p, f);
   c.gq = take(xonly ? (size_t)p.batch * L.fine_cells * ts : 0);
+  c.sens = take((size_t)6 * sens_fields(p) * p.batch * L.fine_cells * ts);
   c.partials = take((size_t)p.batch * (c.n_fine_blocks + c.n_data_blocks) * kTerms * 8);
   c.terms = take((size_t)p.batch * kTerms * 8);
   c.flag = take(4);
@@ -257,7 +260,7 @@ int upload_measurements(modil_ctx *c) {
   c->fused_ok = false;
   std::vector<int32_t> fptr;
   std::vector<FusedMeas> frec;
-  if (c->prob.op == MODIL_OP_NS3D) {
+  if (c->prob.op == MODIL_OP_NS3D && c->prob.centering == MODIL_CELL) {
     int tz, nzt, ntx, nty, ox, oy;
     ns3d_tiles(c->prob, tz, nzt, ntx, nty, ox, oy);
     const int nz = c->prob.dims[0], ny = c->prob.dims[1], nx = c->prob.dims[2];
@@ -346,7 +349,7 @@ int upload_measurements(modil_ctx *c) {
 
 bool use_fused(const modil_ctx *c) {
   return c->fused_enabled && c->fused_ok && c->prob.op == MODIL_OP_NS3D &&
-         c->prob.dtype == MODIL_F32 && ns3d_offsets_fit(c->prob);
+         c->prob.centering == MODIL_CELL && c->prob.dtype == MODIL_F32 && ns3d_offsets_fit(c->prob);
 }
 
 // Loss terms at theta; with grad the gradient of every level; with adam
@@ -576,6 +579,7 @@ int modil_create(const modil_problem *p, void *ws, size_t ws_bytes, void *stream
   c->w_buf = c->ws + cv.w;
   c->g_buf = c->ws + cv.g;
   c->gq_buf = c->ws + cv.gq;
+  c->sens_buf = c->ws + cv.sens;
   c->partials = (double *)(c->ws + cv.partials);
   c->terms_tmp = (double *)(c->ws + cv.terms);
   c->flag = (int32_t *)(c->ws + cv.flag);

@@ -177,6 +177,7 @@ struct modil_ctx {
   void *w_buf = nullptr;     // Horner intermediates, levels 0..L-2 (level 0 = fine u)
   void *g_buf = nullptr;     // gradient pack used by modil_step
   void *gq_buf = nullptr;    // per-cell contributions of 1-D fields (heat q)
+  void *sens_buf = nullptr;  // 3-D adjoint: face-slot sensitivities [6][nnb][batch][cells]
   void *fine_tmp = nullptr;  // one fine-field array (scratch)
   double *partials = nullptr;  // [batch][n_part_blocks][kTerms]
   double *terms_tmp = nullptr; // [batch][kTerms]
@@ -321,6 +322,9 @@ void fine_tile_shape(const modil_problem &P, int &tx, int &ty, int &tiles_x, int
 bool fine_uses_tiles(const modil_ctx *c);
 // most partial slots per instance the generic fine kernels use
 long fine_partial_slots(const modil_problem &P);
+// fields whose neighbours enter the stencil (a prefix of the fields), for the
+// two-pass 3-D adjoint; 0 when the problem is not 3-D
+int sens_fields(const modil_problem &P);
 // column sums of the x-only field's contributions; with adam given also Adam
 // on that field's level 0
 hipError_t launch_colsum(modil_ctx *c, void *g_fine, const AdamHost *adam = nullptr,

@@ -588,16 +588,22 @@ struct FineArgs {
   int xonly_field;     // index of the field spanning x only, or -1
 };
 
-template <class Op, typename T>
+// ND: the grid's dimension when known at compile time (3 for the 3-D
+// kernels, whose slot indices then stay in registers), else 0 (p.ndim)
+template <class Op, int ND = 0, typename T>
 __device__ inline void load_star(const OpParams &p, const FineFields &ff, const T *ub,
                                  const int (&i)[3], T (&U)[Op::NF][7]) {
+  const int a0 = ND ? 3 - ND : 3 - p.ndim;
+#pragma unroll
   for (int f = 0; f < Op::NF; ++f) {
     const T *base = ub + ff.off[f];
     const long lin = i[0] * ff.stride[f][0] + i[1] * ff.stride[f][1] + i[2] * ff.stride[f][2];
     const T c = base[lin];
     for (int s = 0; s < 7; ++s) U[f][s] = c;
     if (!Op::needs_nb(f)) continue;
-    for (int a = 3 - p.ndim; a < 3; ++a) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (a < a0) continue;
       const long st = ff.stride[f][a];
       if (st == 0) continue;
       if (i[a] > 0) {
@@ -616,12 +622,16 @@ __device__ inline void load_star(const OpParams &p, const FineFields &ff, const 
   }
 }
 
-template <class Op, typename T>
+template <class Op, int ND = 0, typename T>
 __device__ inline void fold_ghosts(const OpParams &p, const FineFields &ff, const int (&i)[3],
                                    T (&s)[Op::NF][7]) {
+  const int a0 = ND ? 3 - ND : 3 - p.ndim;
+#pragma unroll
   for (int f = 0; f < Op::NF; ++f) {
     if (!Op::needs_nb(f)) continue;
-    for (int a = 3 - p.ndim; a < 3; ++a) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (a < a0) continue;
       if (ff.stride[f][a] == 0) continue;
       if (i[a] == 0) {
         const GhostRule gr = Op::ghost(p, f, a, 0);
@@ -642,12 +652,12 @@ __device__ inline void fold_ghosts(const OpParams &p, const FineFields &ff, cons
 }
 
 // residuals (forcing subtracted) and weights at cell j of instance inst
-template <class Op, typename T>
+template <class Op, int ND = 0, typename T>
 __device__ inline void cell_residual(const FineArgs<T> &A, int inst, const int (&j)[3],
                                      T (&U)[Op::NF][7], T &chi, T (&r)[Op::NE], T (&wv)[Op::NE],
                                      int (&term)[Op::NE]) {
   const long lin = ((long)j[0] * A.p.n[1] + j[1]) * A.p.n[2] + j[2];
-  load_star<Op>(A.p, A.ff, A.u + (long)inst * A.ff.inst_stride, j, U);
+  load_star<Op, ND>(A.p, A.ff, A.u + (long)inst * A.ff.inst_stride, j, U);
   chi = A.chi ? A.chi[(long)inst * A.ncell + lin] : T(0);
   Op::eval(A.p, j, inst, U, chi, r, wv, term);
   for (int e = 0; e < Op::NE && e < 4; ++e)
@@ -701,6 +711,89 @@ __global__ __launch_bounds__(kBlock) void fine_kernel(FineArgs<T> A) {
     }
   }
   block_terms(part, A.partials + ((long)inst * A.n_part_blocks + blockIdx.x) * kTerms);
+}
+
+// ------------------------------------------------ 3-D adjoint in two passes
+// fine_kernel forms the residuals of all seven cells of a star for every
+// cell, which costs seven times the work of the residuals.  In 3-D the
+// adjoint runs in two streaming passes instead:
+//   fine_sens_kernel    every cell forms its residuals once (loss partials),
+//                       the sensitivities of its weighted residual to the 7
+//                       slots of its star (ghost slots folded back), writes the
+//                       centre slot to the gradient and the six face slots of
+//                       the first nnb fields (those whose neighbours enter the
+//                       stencil) to S[face slot - 1][field][inst][cell];
+//   fine_gather_kernel  every cell adds the face slots of its six neighbours
+//                       that refer to it.
+// Same sum as fine_kernel, in another order.
+template <class Op, typename T>
+__global__ __launch_bounds__(kBlock) void fine_sens_kernel(FineArgs<T> A, T *S, int nnb, int batch) {
+  const int inst = blockIdx.y;
+  const long c = (long)blockIdx.x * kBlock + threadIdx.x;
+  double part[kTerms] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (c < A.ncell) {
+    int i[3];
+    i[2] = (int)(c % A.p.n[2]);
+    i[1] = (int)((c / A.p.n[2]) % A.p.n[1]);
+    i[0] = (int)(c / ((long)A.p.n[1] * A.p.n[2]));
+    T U[Op::NF][7], r[Op::NE], wv[Op::NE], chi, a[Op::NE];
+    int term[Op::NE];
+    cell_residual<Op, 3>(A, inst, i, U, chi, r, wv, term);
+    for (int e = 0; e < Op::NE; ++e) {
+      part[term[e]] += (double)wv[e] * (double)r[e] * (double)r[e];
+      a[e] = T(2) * wv[e] * r[e];
+    }
+    T s[Op::NF][7];
+    for (int f = 0; f < Op::NF; ++f)
+      for (int q = 0; q < 7; ++q) s[f][q] = T(0);
+    Op::vjp(A.p, i, inst, U, chi, a, s);
+    fold_ghosts<Op, 3>(A.p, A.ff, i, s);
+    const long plane = (long)batch * A.ncell;
+    for (int f = 0; f < Op::NF; ++f) {
+      A.g[(long)inst * A.ff.inst_stride + A.ff.off[f] + c] = s[f][S_C];
+      if (f < nnb)
+        for (int o = 1; o < 7; ++o)
+          S[((long)(o - 1) * nnb + f) * plane + (long)inst * A.ncell + c] = s[f][o];
+    }
+  }
+  block_terms(part, A.partials + ((long)inst * A.n_part_blocks + blockIdx.x) * kTerms);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void fine_gather_kernel(FineArgs<T> A, const T *S, int nnb,
+                                                             int batch) {
+  const int inst = blockIdx.y;
+  const long c = (long)blockIdx.x * kBlock + threadIdx.x;
+  if (c >= A.ncell) return;
+  int i[3];
+  i[2] = (int)(c % A.p.n[2]);
+  i[1] = (int)((c / A.p.n[2]) % A.p.n[1]);
+  i[0] = (int)(c / ((long)A.p.n[1] * A.p.n[2]));
+  const long st[3] = {(long)A.p.n[1] * A.p.n[2], (long)A.p.n[2], 1};
+  const long plane = (long)batch * A.ncell;
+  const T *Si = S + (long)inst * A.ncell + c;
+  for (int f = 0; f < nnb; ++f) {
+    T *gp = A.g + (long)inst * A.ff.inst_stride + A.ff.off[f] + c;
+    T acc = *gp;
+    for (int ax = 0; ax < 3; ++ax) {
+      // slot_m of the cell above refers to c, slot_p of the cell below too
+      if (i[ax] + 1 < A.p.n[ax]) acc += Si[((long)(slot_m(ax) - 1) * nnb + f) * plane + st[ax]];
+      if (i[ax] > 0) acc += Si[((long)(slot_p(ax) - 1) * nnb + f) * plane - st[ax]];
+    }
+    *gp = acc;
+  }
+}
+
+template <class Op, typename T>
+static void launch_fine_3d(modil_ctx *c, const FineArgs<T> &A, dim3 grid) {
+  const int nnb = sens_fields(c->prob);
+  if (!A.want_grad || nnb == 0) {
+    fine_kernel<Op, T><<<grid, kBlock, 0, c->stream>>>(A);
+    return;
+  }
+  T *S = (T *)c->sens_buf;
+  fine_sens_kernel<Op, T><<<grid, kBlock, 0, c->stream>>>(A, S, nnb, c->prob.batch);
+  fine_gather_kernel<T><<<grid, kBlock, 0, c->stream>>>(A, S, nnb, c->prob.batch);
 }
 
 // ------------------------------------------------ 2-D stencil engine by tiles
@@ -835,7 +928,7 @@ __global__ __launch_bounds__(NT) void fine_tile_kernel(FineArgs<T> A, int tiles_
         T a[NE];
         for (int e = 0; e < NE; ++e) a[e] = T(2) * wv[e] * r[e];
         Op::vjp(A.p, i, inst, U, chi, a, s);
-        fold_ghosts<Op>(A.p, A.ff, i, s);
+        fold_ghosts<Op, 2>(A.p, A.ff, i, s);
       }
     }
     if (A.want_grad)
@@ -1269,6 +1362,12 @@ void fine_tile_shape(const modil_problem &P, int &tx, int &ty, int &tiles_x, int
   }
 }
 
+int sens_fields(const modil_problem &P) {
+  if (P.op == MODIL_OP_NS3D) return 4;  // u, v, w, p (chihat enters at the centre only)
+  if (P.op == MODIL_OP_POISSON && P.ndim == 3) return 1;
+  return 0;
+}
+
 long fine_partial_slots(const modil_problem &P) {
   long cells = 1;
   for (int k = 0; k < P.ndim; ++k) cells *= P.dims[k] + (P.centering == MODIL_NODE ? 1 : 0);
@@ -1340,9 +1439,9 @@ static hipError_t launch_fine_t(modil_ctx *c, const void *u, void *g, bool want_
   switch (P.op) {
     case MODIL_OP_POISSON:
       if (P.centering == MODIL_NODE)
-        fine_kernel<OpPoissonNode, T><<<grid, kBlock, 0, c->stream>>>(A);
+        launch_fine_3d<OpPoissonNode, T>(c, A, grid);
       else
-        fine_kernel<OpPoisson, T><<<grid, kBlock, 0, c->stream>>>(A);
+        launch_fine_3d<OpPoisson, T>(c, A, grid);
       break;
     case MODIL_OP_BURGERS:
       fine_kernel<OpBurgers, T><<<grid, kBlock, 0, c->stream>>>(A);
@@ -1351,10 +1450,16 @@ static hipError_t launch_fine_t(modil_ctx *c, const void *u, void *g, bool want_
       fine_kernel<OpHeat, T><<<grid, kBlock, 0, c->stream>>>(A);
       break;
     case MODIL_OP_NS3D:
-      if (P.flags & MODIL_FLAG_CHI_FIXED)
-        fine_kernel<OpNS<3, 1>, T><<<grid, kBlock, 0, c->stream>>>(A);
-      else
-        fine_kernel<OpNS<3, 2>, T><<<grid, kBlock, 0, c->stream>>>(A);
+      if (P.centering == MODIL_NODE) {
+        if (P.flags & MODIL_FLAG_CHI_FIXED)
+          launch_fine_3d<OpChannelNode<1>, T>(c, A, grid);
+        else
+          launch_fine_3d<OpChannelNode<2>, T>(c, A, grid);
+      } else if (P.flags & MODIL_FLAG_CHI_FIXED) {
+        launch_fine_3d<OpNS<3, 1>, T>(c, A, grid);
+      } else {
+        launch_fine_3d<OpNS<3, 2>, T>(c, A, grid);
+      }
       break;
     case MODIL_OP_CAVITY:
       if (P.centering == MODIL_NODE)

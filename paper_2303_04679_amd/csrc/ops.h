@@ -59,7 +59,9 @@ struct OpPoisson {
   __device__ static void eval(const OpParams &p, const int *, int, const T (&U)[NF][7],
                               T, T *r, T *wv, int *term) {
     T acc = 0;
-    for (int a = 3 - p.ndim; a < 3; ++a) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (a < 3 - p.ndim) continue;
       T ih2 = T(1.0 / (p.h[a] * p.h[a]));
       acc += (U[0][slot_p(a)] - T(2) * U[0][S_C] + U[0][slot_m(a)]) * ih2;
     }
@@ -70,7 +72,9 @@ struct OpPoisson {
   template <typename T>
   __device__ static void vjp(const OpParams &p, const int *, int, const T (&)[NF][7],
                              T, const T *a, T (&s)[NF][7]) {
-    for (int ax = 3 - p.ndim; ax < 3; ++ax) {
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      if (ax < 3 - p.ndim) continue;
       T ih2 = T(1.0 / (p.h[ax] * p.h[ax]));
       s[0][slot_p(ax)] += a[0] * ih2;
       s[0][slot_m(ax)] += a[0] * ih2;
@@ -106,7 +110,9 @@ struct OpPoissonNode {
       return;
     }
     T acc = 0;
-    for (int a = 3 - p.ndim; a < 3; ++a) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (a < 3 - p.ndim) continue;
       const T ih2 = T(1.0 / (p.h[a] * p.h[a]));
       const T um = j[a] - 1 == 0 ? T(0) : U[0][slot_m(a)];
       const T up = j[a] + 1 == p.n[a] - 1 ? T(0) : U[0][slot_p(a)];
@@ -119,7 +125,9 @@ struct OpPoissonNode {
   __device__ static void vjp(const OpParams &p, const int *j, int, const T (&)[NF][7], T,
                              const T *a, T (&s)[NF][7]) {
     if (on_boundary(p, j)) return;
-    for (int ax = 3 - p.ndim; ax < 3; ++ax) {
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      if (ax < 3 - p.ndim) continue;
       const T ih2 = T(1.0 / (p.h[ax] * p.h[ax]));
       if (j[ax] + 1 != p.n[ax] - 1) s[0][slot_p(ax)] += a[0] * ih2;
       if (j[ax] - 1 != 0) s[0][slot_m(ax)] += a[0] * ih2;
@@ -555,6 +563,109 @@ struct OpCavityNode {
         t[1][k] = T(0);
         t[2][S_C] += t[2][k];
         t[2][k] = T(0);
+      }
+    for (int f = 0; f < NF; ++f)
+      for (int k = 0; k < 7; ++k) s[f][k] += t[f][k];
+  }
+};
+
+// Node-based channel flow past a body (Sections 2.2, 3.5): values at the
+// nodes x_i = i h.  Boundary nodes carry no equation; the boundary conditions
+// replace their values, whatever the prolonged field holds there:
+//   inlet (axis 2, side 0)   u = (u_ref, 0, 0), p copied from the neighbouring
+//                            interior node,
+//   outlet (axis 2, side 1)  p = 0, the velocity copied,
+//   free-slip walls (axes 0, 1)  the normal velocity component is zero, the
+//                            other components and p are copied.
+// For the interior node whose star reaches the boundary node, the copied
+// neighbour is that node itself.  Nodes on an edge or a corner of the box lie
+// in no interior star.  Interior nodes carry the equations of OpNS<3, CHI> on
+// the star with these substitutions, so the adjoint drops the imposed slots
+// and moves the copied slots onto the centre.
+template <int CHI>
+struct OpChannelNode {
+  using Base = OpNS<3, CHI>;
+  static constexpr bool kForcePdeOnly = false;
+  static constexpr int NF = Base::NF, NE = Base::NE;
+
+  __device__ static bool needs_nb(int f) { return f <= 3; }
+  __device__ static GhostRule ghost(const OpParams &, int, int, int) {
+    return GhostRule{0.0, 0.0, 0.0};  // never used by an equation
+  }
+  __device__ static bool on_boundary(const OpParams &p, const int *j) {
+    bool b = false;
+    for (int a = 0; a < 3; ++a) b = b || j[a] == 0 || j[a] == p.n[a] - 1;
+    return b;
+  }
+  // bit (2 a + side) set when the star's neighbour along axis a on that side is a boundary node
+  __device__ static int wall_mask(const OpParams &p, const int *j) {
+    int m = 0;
+    for (int a = 0; a < 3; ++a) {
+      if (j[a] - 1 == 0) m |= 1 << (2 * a);
+      if (j[a] + 1 == p.n[a] - 1) m |= 1 << (2 * a + 1);
+    }
+    return m;
+  }
+  // field f (u, v, w, p) on the boundary (axis a, side): imposed (true, value) or copied
+  __device__ static bool imposed(const OpParams &p, int f, int a, int side, double &val) {
+    val = 0.0;
+    if (a == 2) {
+      if (side == 0) {
+        if (f == 0) val = p.u_ref;
+        return f < 3;
+      }
+      return f == 3;
+    }
+    return f == 2 - a;
+  }
+  template <typename T>
+  __device__ static void impose(const OpParams &p, int m, const T (&U)[NF][7], T (&W)[NF][7]) {
+    for (int f = 0; f < NF; ++f)
+      for (int k = 0; k < 7; ++k) W[f][k] = U[f][k];
+    for (int a = 0; a < 3; ++a)
+      for (int side = 0; side < 2; ++side) {
+        if (!(m >> (2 * a + side) & 1)) continue;
+        const int k = side ? slot_p(a) : slot_m(a);
+        for (int f = 0; f < 4; ++f) {
+          double val;
+          W[f][k] = imposed(p, f, a, side, val) ? T(val) : U[f][S_C];
+        }
+      }
+  }
+  template <typename T>
+  __device__ static void eval(const OpParams &p, const int *j, int inst, const T (&U)[NF][7],
+                              T chi_fixed, T *r, T *wv, int *term) {
+    if (on_boundary(p, j)) {
+      for (int e = 0; e < NE; ++e) {
+        r[e] = T(0);
+        wv[e] = T(0);
+        term[e] = MODIL_TERM_PDE;
+      }
+      return;
+    }
+    T W[NF][7];
+    impose(p, wall_mask(p, j), U, W);
+    Base::eval(p, j, inst, W, chi_fixed, r, wv, term);
+  }
+  template <typename T>
+  __device__ static void vjp(const OpParams &p, const int *j, int inst, const T (&U)[NF][7],
+                             T chi_fixed, const T *a, T (&s)[NF][7]) {
+    if (on_boundary(p, j)) return;
+    const int m = wall_mask(p, j);
+    T W[NF][7], t[NF][7];
+    impose(p, m, U, W);
+    for (int f = 0; f < NF; ++f)
+      for (int k = 0; k < 7; ++k) t[f][k] = T(0);
+    Base::vjp(p, j, inst, W, chi_fixed, a, t);
+    for (int ax = 0; ax < 3; ++ax)
+      for (int side = 0; side < 2; ++side) {
+        if (!(m >> (2 * ax + side) & 1)) continue;
+        const int k = side ? slot_p(ax) : slot_m(ax);
+        for (int f = 0; f < 4; ++f) {
+          double val;
+          if (!imposed(p, f, ax, side, val)) t[f][S_C] += t[f][k];
+          t[f][k] = T(0);
+        }
       }
     for (int f = 0; f < NF; ++f)
       for (int k = 0; k < 7; ++k) s[f][k] += t[f][k];

@@ -41,7 +41,7 @@ class ProblemSpec:
     w_pde: float = 1.0
     w_reg: float = 0.0
     w_bc: float = 0.0
-    centering: str = "cell"   # "cell", or "node" (Poisson, cavity)
+    centering: str = "cell"   # "cell", or "node" (Poisson, cavity, channel flow)
 
     @property
     def torch_dtype(self):

@@ -82,7 +82,7 @@ def assert_terms(gpu_terms, ref_terms, tol, ctx_msg=""):
             (ctx_msg, t, g, r)
 
 
-def cancellation(ref_levels, field_axes_list):
+def cancellation(ref_levels, field_axes_list, centering="cell"):
     """Per (level, field): || |M^T| |g_fine| || / || g_level ||.
 
     A coarse-level gradient is the restriction of the fine gradient, a sum of
@@ -102,8 +102,9 @@ def cancellation(ref_levels, field_axes_list):
             a = np.abs(np.asarray(ref_levels[0][fi], dtype=np.float64))
             for _ in range(li):
                 for ax in field_axes_list[fi]:
-                    n_c = a.shape[ax] // 2
-                    Ta = np.abs(mg.cell_T_matrix(n_c))
+                    n_c = a.shape[ax] // 2   # coarse cells (node arrays hold 2 n_c + 1 values)
+                    T = mg.node_T_matrix(n_c) if centering == "node" else mg.cell_T_matrix(n_c)
+                    Ta = np.abs(T)
                     a = np.moveaxis(np.tensordot(Ta.T, np.moveaxis(a, ax, 0), axes=1), 0, ax)
             nr = np.linalg.norm(r)
             frow.append(max(1.0, np.linalg.norm(a) / nr) if nr > 0 else 1.0)
@@ -118,7 +119,7 @@ def assert_levels(gpu_levels, ref_levels, tol, ctx_msg="", spec=None):
     if spec is not None:
         from oracle import operators as ops
         axes = [ops.field_axes(spec.op, name, spec.ndim) for name in spec.fields]
-        factors = cancellation(ref_levels, axes)
+        factors = cancellation(ref_levels, axes, spec.centering)
     for li, (grow, rrow) in enumerate(zip(gpu_levels, ref_levels)):
         for fi, (g, r) in enumerate(zip(grow, rrow)):
             e = rel(g, r)

@@ -78,9 +78,8 @@ def test_validation_errors(kw, status):
 
 
 @pytest.mark.parametrize("op,dims,lengths", [("burgers", (16, 16), (1.0, 2.0)),
-                                             ("heat", (16, 16), (0.02, 1.0)),
-                                             ("ns3d", (8, 8, 16), (1.0, 1.0, 2.0))])
-def test_node_centering_only_for_poisson_and_cavity(op, dims, lengths):
+                                             ("heat", (16, 16), (0.02, 1.0))])
+def test_node_centering_not_for_burgers_and_heat(op, dims, lengths):
     p = ProblemSpec(op, dims, lengths, 2).to_c()
     p.centering = L.NODE
     out = L.PackLayout()
@@ -94,6 +93,15 @@ def test_node_cavity_layout():
         assert [tuple(lay.field_dims[l][f])[1:] for f in range(3)] == [(n, n)] * 3
     assert lay.fine_cells == 65 * 65
     assert lay.total == 3 * sum(n * n for n in (65, 33, 17, 9, 5))
+
+
+def test_node_channel_layout():
+    """Node-based channel flow: five fields of (dims >> l) + 1 values per axis."""
+    lay = layout(ProblemSpec("ns3d", (64, 64, 128), (1.0, 1.0, 2.0), 3, re=200.0, centering="node"))
+    for l, (nz, nx) in enumerate(((65, 129), (33, 65), (17, 33))):
+        assert [tuple(lay.field_dims[l][f]) for f in range(5)] == [(nz, nz, nx)] * 5
+    assert lay.fine_cells == 65 * 65 * 129
+    assert lay.total == 5 * sum(a * a * b for a, b in ((65, 129), (33, 65), (17, 33)))
 
 
 def test_node_layout():

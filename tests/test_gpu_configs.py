@@ -14,14 +14,14 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("name", ["burgers64", "heat256", "heat256_f32", "ns3d64", "ns3d128",
-                                  "ns3d128_shard8", "cavity128"])
+                                  "ns3d128_shard8", "cavity128", "channel_node129"])
 def test_workload_loss_and_gradient(name):
     need_gpu()
     print(f"\n[parity] workload {name}", flush=True)
     wl = configs.WORKLOADS[name]()
     ctx, theta0 = configs.build(wl)
     spec = oracle_spec(wl)
-    shapes = ops.level_shapes(spec.op, spec.dims, spec.n_levels)
+    shapes = ops.level_shapes(spec.op, spec.dims, spec.n_levels, spec.centering)
     lv = synth.uniform_levels(shapes, 90, -0.5, 0.5)
     # start from the workload's own initial state plus a random perturbation
     base = [[v.detach().cpu().double().numpy() for v in row] for row in ctx.level_views(theta0)]

@@ -36,6 +36,9 @@ CASES = [
     ("poisson_node", (8, 16, 8), 2),
     ("cavity_node", (32, 48), 4),
     ("cavity_node", (24, 16), 3),
+    ("ns3d_node", (16, 16, 24), 3),
+    ("ns3d_node", (8, 12, 20), 2),
+    ("ns3d_fixed_node", (8, 16, 24), 3),
 ]
 
 
@@ -117,7 +120,8 @@ def test_adam(dtype):
 
 @pytest.mark.parametrize("op,dims,L", [("burgers", (32, 32), 4), ("heat", (32, 32), 4),
                                        ("ns3d", (8, 8, 16), 3), ("cavity", (32, 32), 4),
-                                       ("poisson_node", (32, 32), 4), ("cavity_node", (32, 32), 4)])
+                                       ("poisson_node", (32, 32), 4), ("cavity_node", (32, 32), 4),
+                                       ("ns3d_node", (8, 8, 16), 3)])
 def test_step_sequence_f64(op, dims, L):
     """Three modil_step calls (ping-pong theta) follow the oracle's loss, gradient and Adam."""
     need_gpu()
@@ -365,7 +369,8 @@ def test_fused_channel_batch():
 
 @pytest.mark.parametrize("op,dims,L,dtype", [("cavity", (32, 48), 4, "f32"), ("heat", (32, 64), 4, "f64"),
                                              ("cavity_node", (32, 48), 4, "f64"),
-                                             ("ns3d", (16, 16, 32), 3, "f32")])
+                                             ("ns3d", (16, 16, 32), 3, "f32"),
+                                             ("ns3d_node", (16, 16, 32), 3, "f32")])
 @pytest.mark.parametrize("n", [1, 4, 5])
 def test_run_equals_steps(op, dims, L, dtype, n):
     """modil_run of n iterations equals n modil_step calls bit for bit
@@ -377,7 +382,8 @@ def test_run_equals_steps(op, dims, L, dtype, n):
                                              ("cavity", (128, 128), 5, "f32"),
                                              ("cavity_node", (64, 64), 4, "f64"),
                                              ("heat", (256, 256), 6, "f64"),
-                                             ("ns3d", (128, 128, 128), 6, "f32")])
+                                             ("ns3d", (128, 128, 128), 6, "f32"),
+                                             ("ns3d_node", (64, 64, 128), 6, "f32")])
 def test_run_equals_steps_split_tail(op, dims, L, dtype):
     """Sizes whose Horner tail splits its largest level over several blocks per
     field, evenly or not (the restriction tail carries that split from one

@@ -509,7 +509,7 @@ def _channel_node_spec(dims, lengths, chi, u_ref=0.8, forcing=None):
                     weights={"pde": 1.0}, chi=chi, centering="node", forcing=forcing or {})
 
 
-def _node_grid(dims, lengths):
+def _channel_grid(dims, lengths):
     axes = [np.arange(n + 1) * (L / n) for n, L in zip(dims, lengths)]
     return np.meshgrid(*axes, indexing="ij")   # Z, Y, X
 
@@ -535,7 +535,7 @@ def test_channel_node_exact_for_products_of_quadratics():
     penalised Navier-Stokes operators with the pressure stabilisation
     tau h_a d2p/da2, body fraction included."""
     dims, lengths = (6, 6, 10), (1.0, 1.2, 2.0)
-    Z, Y, X = _node_grid(dims, lengths)
+    Z, Y, X = _channel_grid(dims, lengths)
     rng = np.random.default_rng(17)
 
     def quad(s):
@@ -584,7 +584,7 @@ def test_channel_node_inlet_and_outlet():
     inlet the pressure sees half the slope and a one-sided second difference;
     next to the outlet the velocity does; elsewhere the line is exact."""
     dims, lengths = (4, 4, 8), (1.0, 1.0, 2.0)
-    Z, Y, X = _node_grid(dims, lengths)
+    Z, Y, X = _channel_grid(dims, lengths)
     a, s, u_ref = 0.3, -1.5, 0.8
     h, nx = lengths[2] / dims[2], dims[2]
     nu, tau = 0.4 / 50.0, 0.5
@@ -617,7 +617,7 @@ def test_channel_node_free_slip_walls(wall_axis):
     derivative), which halves its slope and gives a one-sided second difference
     next to the wall.  Checked away from the inlet and outlet."""
     dims, lengths = (6, 6, 8), (1.0, 1.0, 2.0)
-    G = _node_grid(dims, lengths)
+    G = _channel_grid(dims, lengths)
     S = G[wall_axis]
     Ls, n = lengths[wall_axis], dims[wall_axis]
     h = Ls / n
