@@ -304,6 +304,11 @@ bool launch_restrict_march(const Levels &G, int l, T *g, const AdamArgs<T> &A, b
 template <typename T>
 bool launch_prolong_block(const Levels &G, int l, const T *theta, const T *csrc, T *dst,
                           hipStream_t s);
+// the same for node-based fields of one shape spanning three axes; false when
+// the level does not qualify
+template <typename T>
+bool launch_prolong_node(const Levels &G, int l, const T *theta, const T *csrc, T *dst,
+                         hipStream_t s);
 // Two Horner steps (levels l + 2 -> l) in one launch where the levels admit it.
 template <typename T>
 bool launch_prolong2(const Levels &G, int l, const T *th_l, const T *th_m, const T *csrc, T *dst,

@@ -1197,6 +1197,8 @@ static hipError_t horner_t(modil_ctx *c, const void *theta_v, void *fine_dst_v, 
     T *dst = (l == 0) ? fine_dst : w + G.off[l];
     if (c->march_enabled && launch_prolong_block<T>(G, l, theta + G.off[l], src, dst, c->stream))
       continue;
+    if (c->march_enabled && launch_prolong_node<T>(G, l, theta + G.off[l], src, dst, c->stream))
+      continue;
     const long total = (long)G.stride[l] * G.batch;
     prolong_kernel<T><<<nblk(total), kBlock, 0, c->stream>>>(G, l, theta, src, dst);
   }

@@ -349,6 +349,69 @@ bool launch_prolong_block(const Levels &G, int l, const T *theta, const T *csrc,
   return true;
 }
 
+// Horner step for node-based fields of one shape that span all three axes
+// (Section 2.2: T is the tensor product of the 1-D node interpolation; an even
+// fine node takes the coarse node it sits on, an odd one the mean of its two
+// coarse neighbours).  One thread per fine node, x fastest; the (instance,
+// field, z, y) of a node comes from divisions by block-uniform sizes.  Same
+// taps and order of operations as the generic per-value kernel.
+template <typename T>
+__global__ __launch_bounds__(256) void prolong_node_kernel(Levels G, int l, const T *__restrict__ theta,
+                                                           const T *__restrict__ csrc,
+                                                           T *__restrict__ dst, int total) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= total) return;
+  const int nz = G.n[l][0][0], ny = G.n[l][0][1], nx = G.n[l][0][2];
+  const int cny = G.n[l + 1][0][1], cnx = G.n[l + 1][0][2];
+  const int cells = nz * ny * nx;
+  const int q = e / cells, r = e - q * cells;  // q = instance * fields + field
+  const int inst = q / G.nf, f = q - inst * G.nf;
+  const int zy = r / nx, x = r - zy * nx;
+  const int z = zy / ny, y = zy - z * ny;
+  int ix[2], iy[2], iz[2];
+  T wx[2], wy[2], wz[2];
+  prolong_taps_node(x, ix, wx);
+  prolong_taps_node(y, iy, wy);
+  prolong_taps_node(z, iz, wz);
+  const T *cb = csrc + (long)inst * G.stride[l + 1] + G.foff[l + 1][f];
+  T acc = T(0);
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const T *rw = cb + ((long)iz[a] * cny + iy[b]) * cnx;
+      acc += wz[a] * wy[b] * (wx[0] * rw[ix[0]] + wx[1] * rw[ix[1]]);
+    }
+  const long k = (long)inst * G.stride[l] + G.foff[l][f] + r;
+  dst[k] = theta[k] + acc;
+}
+
+template <typename T>
+bool launch_prolong_node(const Levels &G, int l, const T *theta, const T *csrc, T *dst,
+                         hipStream_t s) {
+  if (!G.node || l + 1 >= G.L) return false;
+  for (int f = 0; f < G.nf; ++f)
+    for (int a = 0; a < 3; ++a) {
+      if (G.n[l][f][a] != G.n[l][0][a] || G.n[l + 1][f][a] != G.n[l + 1][0][a]) return false;
+      // nodes of a spanned axis: 2 (coarse cells) + 1
+      if (G.n[l + 1][0][a] < 2 || G.n[l][0][a] != 2 * (G.n[l + 1][0][a] - 1) + 1) return false;
+    }
+  // one instance's level is contiguous: fields at foff = f * cells
+  const long cells = (long)G.n[l][0][0] * G.n[l][0][1] * G.n[l][0][2];
+  for (int f = 0; f < G.nf; ++f)
+    if (G.foff[l][f] != f * cells) return false;
+  const long total = (long)G.batch * G.nf * cells;
+  if (total >= (1L << 31) - 256) return false;
+  prolong_node_kernel<T><<<(unsigned)((total + 255) / 256), 256, 0, s>>>(G, l, theta, csrc, dst,
+                                                                         (int)total);
+  return true;
+}
+
+template bool launch_prolong_node<float>(const Levels &, int, const float *, const float *, float *,
+                                         hipStream_t);
+template bool launch_prolong_node<double>(const Levels &, int, const double *, const double *,
+                                          double *, hipStream_t);
+
 template bool launch_prolong_block<float>(const Levels &, int, const float *, const float *, float *,
                                           hipStream_t);
 template bool launch_prolong_block<double>(const Levels &, int, const double *, const double *,
