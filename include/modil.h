@@ -62,7 +62,7 @@ extern "C" {
 #define MODIL_F64 1
 
 #define MODIL_CELL 0 /* values at cell centres                           */
-#define MODIL_NODE 1 /* values at grid nodes, POISSON and CAVITY only   */
+#define MODIL_NODE 1 /* values at grid nodes: POISSON, CAVITY, NS3D    */
 
 /* Residual operators (the discretised PDEs of Sections 3.1-3.5).
  *   POISSON   d = 1,2,3; Laplacian u = f, Dirichlet u = 0 by quadratic
@@ -115,7 +115,7 @@ extern "C" {
  * Validation: ndim matches the operator, dims[a] divisible by
  * 2^(n_levels-1) with at least 2 coarsest cells per axis (cell-based
  * extrapolation needs two), lengths > 0, batch >= 1, 1 <= n_levels <= 8.
- * MODIL_NODE (POISSON and CAVITY; Sections 2.2, 3.1, 3.3): dims are cells
+ * MODIL_NODE (POISSON, CAVITY, NS3D; Sections 2.2, 3.1, 3.3, 3.5): dims are cells
  * per axis and a field holds (dims[a] >> l) + 1 nodes per axis on level l,
  * boundary nodes included; T is the node-based interpolation of Section 2.2
  * (even fine nodes copy the coarse node, odd ones average two).  Boundary
@@ -129,7 +129,13 @@ extern "C" {
  *   (central differences, stabilised continuity); on the wall nodes the
  *   velocity is imposed (zero, u = u_ref on the lid row y = 1 without its
  *   corners) and the pressure is that of the interior neighbour across the
- *   wall (zero normal derivative), whatever the prolonged fields hold there. */
+ *   wall (zero normal derivative), whatever the prolonged fields hold there.
+ *   NS3D: interior nodes carry the four cell-based channel equations; on the
+ *   boundary nodes the inlet imposes u = (u_ref, 0, 0) and copies p from the
+ *   interior node next to it, the outlet imposes p = 0 and copies the
+ *   velocity, the free-slip walls impose a zero normal velocity and copy the
+ *   other components and p, whatever the prolonged fields hold there.  The
+ *   fused FP32 kernel is cell-based; node values run on the generic engine. */
 typedef struct {
   int32_t ndim;
   int32_t dims[3];
