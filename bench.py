@@ -35,8 +35,9 @@ def parse():
     ap.add_argument("--workload", default="ns3d128")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="budget of the oracle CPU-baseline sample (0 disables it)")
-    ap.add_argument("--copy-probe-mib", type=int, default=0,
-                    help="also run a plain device copy of this size (for counter scaling)")
+    ap.add_argument("--copy-probe-mib", type=int, default=1024,
+                    help="size of the plain device copy timed as the measured HBM peak "
+                         "(and used to scale the traffic counters); 0 skips it")
     ap.add_argument("--optimizer", choices=("adam", "lbfgs", "autograd"), default="adam",
                     help="adam: the library's fused iteration; lbfgs: L-BFGS on the device; autograd: "
                          "the loss as a torch.autograd.Function (adjoint kernels in backward) with "
@@ -47,20 +48,27 @@ def parse():
     return ap.parse_args()
 
 
-def alg_bytes(ctx, spec, fused, adam=True, tiled=False):
+MEAS_BYTES = 12  # one measurement: int32 cell index and its value in double
+
+
+def alg_bytes(ctx, spec, fused, adam=True, tiled=False, n_meas=0):
     """Algorithmic bytes of one launch of each kernel class and of one iteration.
 
-    Every array a kernel must read or write is counted once; halo re-reads
-    and caching are not.  One iteration touches every parameter of every level
-    six times (theta, m, v read and written): 6 * b * S.
+    One iteration reads and writes every parameter of every level, and Adam's
+    two moments of it, once: 6 * b * S, plus the measurements it must read
+    (cell index and value, B_data).  Intermediates (the prolonged coarse
+    levels w_l, the gradients g_l), halo re-reads and caching are not counted:
+    they are the implementation's traffic, which rocprofv3 counters measure.
 
-    Fused channel-flow path: the finest-level kernel reads theta, m, v of the
-    finest level and the prolonged level 1, and writes theta', m', v' and the
-    finest gradient; the restriction class reads each gradient level, writes
-    the next one and applies Adam to it.  Generic path: the fine kernel reads
-    the prolonged field and writes the finest gradient; Adam is one sweep, or
-    (2-D tiled engine) Adam of level 0 sits in the fine kernel and that of the
-    coarse levels in the restriction, as in the fused path.
+    Fused channel-flow path: the finest-level kernel owns the finest level's
+    share, 6 * b * F * N + B_data (theta, m, v of level 0 read and written and
+    the measurements; plus the fixed body fraction when chi is given); the
+    restriction class owns the coarse levels' 6 * b * F * S_l (it applies Adam
+    to them) and the Horner class none.  The iteration's figure is
+    6 * b * S + B_data.  Generic path (no Adam in the fine kernel): the fine
+    kernel reads the prolonged field and writes the finest gradient; Adam is
+    one sweep, or (2-D tiled engine) Adam of level 0 sits in the fine kernel
+    and that of the coarse levels in the restriction, as in the fused path.
     """
     b = 4 if spec.dtype == "f32" else 8
     lay = ctx.lay
@@ -68,15 +76,16 @@ def alg_bytes(ctx, spec, fused, adam=True, tiled=False):
     size = [int(lay.level_stride[l]) * spec.batch for l in range(L)]
     S = int(lay.total)
     chi = spec.batch * spec.fine_cells * b if spec.chi_fixed else 0
+    data = MEAS_BYTES * n_meas
     if fused and not adam:  # loss and gradient only (L-BFGS evaluations)
-        fine = (2 * size[0] + (size[1] if L > 1 else 0)) * b + chi
-        horner = sum((2 * size[l] + size[l + 1]) * b for l in range(1, L - 1))
-        restrict = sum((size[l] + size[l + 1]) * b for l in range(L - 1))
+        fine = 2 * size[0] * b + chi + data
+        horner = sum(size[l + 1] * b for l in range(L - 1))
+        restrict = sum(size[l + 1] * b for l in range(L - 1))
         adam = 0
     elif fused:
-        fine = (7 * size[0] + (size[1] if L > 1 else 0)) * b + chi
-        horner = sum((2 * size[l] + size[l + 1]) * b for l in range(1, L - 1))
-        restrict = sum((size[l] + 7 * size[l + 1]) * b for l in range(L - 1))
+        fine = 6 * size[0] * b + chi + data
+        horner = 0
+        restrict = sum(6 * size[l + 1] * b for l in range(L - 1))
         adam = 0
     elif tiled and adam:
         fine = 8 * size[0] * b + chi
@@ -89,7 +98,7 @@ def alg_bytes(ctx, spec, fused, adam=True, tiled=False):
         restrict = sum((size[l] + size[l + 1]) * b for l in range(L - 1))
         adam = 7 * S * b if adam else 0
     return {"fine": fine, "horner": horner, "restrict": restrict, "adam": adam,
-            "reduce": 0, "lbfgs_dots": 0, "lbfgs_update": 0, "iteration": 6 * S * b}
+            "reduce": 0, "lbfgs_dots": 0, "lbfgs_update": 0, "iteration": 6 * S * b + data}
 
 
 def lbfgs_vector_bytes(n, b, infos, pairs0):
@@ -140,11 +149,36 @@ def measured_traffic(workload, kernel_class):
     return rec["fetch_bytes"] + rec["write_bytes"]
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def oracle_baseline(workload, theta_levels, seconds):
-    """The FP64 oracle (loss, autodiff gradient, Adam) on the same workload."""
+    """The FP64 oracle (loss, autodiff gradient, Adam) on the same workload,
+    on one host core: the process is pinned to the first core of its affinity
+    set and torch to one thread for the duration (both restored after)."""
     import torch
     from oracle import adam as oadam
     from oracle import operators as ops
+    affinity = sorted(os.sched_getaffinity(0))
+    threads = torch.get_num_threads()
+    os.sched_setaffinity(0, {affinity[0]})
+    torch.set_num_threads(1)
+    try:
+        return _oracle_baseline(workload, theta_levels, seconds, ops, oadam, affinity)
+    finally:
+        torch.set_num_threads(threads)
+        os.sched_setaffinity(0, affinity)
+
+
+def _oracle_baseline(workload, theta_levels, seconds, ops, oadam, affinity):
+    import torch
     spec = workload.spec
     op = "ns3d_fixed" if spec.chi_fixed else spec.op
     ospec = ops.Spec(op, spec.dims, spec.lengths, spec.n_levels,
@@ -166,10 +200,32 @@ def oracle_baseline(workload, theta_levels, seconds):
         el = time.perf_counter() - t0
         if el >= seconds or it >= 50:
             break
-    return {"value": spec.fine_cells * it / el, "unit": "cell-iter/s",
+    return {"value": spec.fine_cells * spec.batch * it / el, "unit": "cell-iter/s",
             "cores": torch.get_num_threads(), "kind": "oracle",
             "sample": f"{it} full iterations (loss, autodiff gradient, Adam) of {workload.name} "
-                      f"in FP64 on the host CPU, {el:.1f} s"}
+                      f"in FP64 on one host core, {el:.1f} s",
+            "nproc": os.cpu_count(), "affinity_cpus": len(affinity), "cpu_model": cpu_model()}
+
+
+def copy_probe(device, mib, reps=5):
+    """A plain device-to-device copy of `mib` MiB timed with HIP events: the
+    HBM bandwidth a streaming kernel reaches on this GPU (read + write bytes
+    per second), the measured counterpart of the vendor peak."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device=device)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return {"bytes": 2 * n * 4, "avg_ms": ms, "gbs": 2 * n * 4 / (ms * 1e-3) / 1e9}
 
 
 def main():
@@ -239,20 +295,15 @@ def main():
         kern[name] = {"total_ms": tot, "launches": cnt, "avg_ms": tot / max(cnt, 1)}
     ctx.profile(False)
     fused = ctx.fused_active()
-    ab = alg_bytes(ctx, spec, fused, tiled=ctx.tiled_active())
+    n_meas = sum(len(m[3]) for m in wl.meas)
+    ab = alg_bytes(ctx, spec, fused, tiled=ctx.tiled_active(), n_meas=n_meas)
     dom = max(CLASSES, key=lambda n: kern[n]["total_ms"])
     avg_s = kern[dom]["avg_ms"] * 1e-3
     achieved = ab[dom] / avg_s / 1e9 if avg_s > 0 else 0.0
     ms_step = ms / args.steps
     value = spec.fine_cells * spec.batch * args.steps / (ms * 1e-3)
     it_gbs = ab["iteration"] / (ms_step * 1e-3) / 1e9
-    if args.copy_probe_mib:
-        n = args.copy_probe_mib * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device=ctx.device)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
+    copy = copy_probe(ctx.device, args.copy_probe_mib) if args.copy_probe_mib else None
     cpu = None
     if args.cpu_seconds > 0:
         print("[bench] oracle CPU baseline ...", file=sys.stderr, flush=True)
@@ -275,12 +326,14 @@ def main():
                    "levels": spec.n_levels, "fields": len(spec.fields), "params": int(ctx.lay.total),
                    "batch": spec.batch, "optimizer": "adam", "loss_reduction": "f64",
                    "loop": "modil_run" if args.loop == "run" else "modil_step"},
+        "iteration_bytes_algorithmic": ab["iteration"],
         "hbm_gbs_algorithmic": it_gbs,
         "iteration_roofline_frac": it_gbs / HBM_PEAK_GBS,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "bytes_per_launch": ab[dom], "avg_launch_ms": kern[dom]["avg_ms"],
                      "traffic": measured_traffic(wl.name, dom)},
+        "hbm_copy_probe": None if copy is None else dict(copy, frac_of_peak=copy["gbs"] / HBM_PEAK_GBS),
         "kernels": kern,
         "fused_fine_kernel": fused,
         "ms_per_step_profiled": ms_prof / args.steps,

@@ -206,7 +206,10 @@ int modil_set_stream(modil_ctx *ctx, void *hip_stream);
  * condition).  Host arrays are copied (synchronously) into the workspace;
  * values are kept in double.  Indices must be in range and unique within
  * the list (MODIL_ERR_SHAPE / MODIL_ERR_INVALID_ARG), the total over all
- * lists must not exceed max_meas.  Lists accumulate until
+ * lists must not exceed max_meas.  With node-based values an index on a
+ * boundary node is rejected (MODIL_ERR_SHAPE): the boundary nodes hold
+ * imposed values that no equation reads from the unknowns, so a measurement
+ * there would fit a free value.  Lists accumulate until
  * modil_clear_measurements.                                              */
 int modil_set_measurements(modil_ctx *ctx, int32_t instance, int32_t field, int32_t term,
                            int32_t n, const int32_t *cell_idx_host,
@@ -245,9 +248,12 @@ int modil_set_instance_scalar(modil_ctx *ctx, int32_t instance, int32_t which, d
  *   Loss terms of the last iteration go to terms (if not NULL).  The same
  *   arithmetic as calling modil_step n_steps times, without a host round
  *   trip per iteration.  theta_a must differ from theta_b.
- * modil_residual_metric: r[instance] = RMS over cells and PDE equations of
- *   the cell-integrated residual, sqrt(sum (V R)^2 / (n_eq * n_cells)),
- *   evaluated in double from the PDE term.                               */
+ * modil_residual_metric: r[instance] = RMS over the points carrying the PDE
+ *   equations and over the equations of the cell-integrated residual,
+ *   sqrt(sum (V R)^2 / (n_eq * n_points)), evaluated in double from the PDE
+ *   term.  The points are every cell (cell-based values), the interior nodes
+ *   (node-based values) or the inner points n >= 1, 1 <= i <= N_x - 2 of the
+ *   space-time grids (BURGERS, HEAT_KX).                                  */
 int modil_prolong(modil_ctx *ctx, const void *theta_pack, void *fine_out);
 int modil_restrict_adjoint(modil_ctx *ctx, const void *fine_in, void *grad_pack_out);
 int modil_loss(modil_ctx *ctx, const void *theta_pack, double *terms);
@@ -287,6 +293,16 @@ int modil_residual_metric(modil_ctx *ctx, const void *theta_pack, double *r);
  * the per-cell kernel, which forms the residuals of each cell's neighbours
  * again.  Same results up to the order of the sums.                       */
 #define MODIL_OPT_TILE 4
+/* MODIL_OPT_TWO_PASS (default 1): the generic engine on 3-D problems forms
+ * every cell's residuals once and writes the face sensitivities of its star
+ * to workspace scratch, then gathers them per cell; 0 selects the per-cell
+ * kernel, which forms the residuals of each cell's neighbours again.  The
+ * scratch (6 x fields coupled through neighbours x cells) is part of the
+ * workspace only where the two-pass form can run: 3-D problems except FP32
+ * cell-based NS3D, whose generic engine (when the fused kernel does not
+ * apply) is always the per-cell kernel.  Same results up to the order of
+ * the sums.                                                               */
+#define MODIL_OPT_TWO_PASS 5
 int modil_set_option(modil_ctx *ctx, int32_t option, int64_t value);
 /* modil_fused_active: 1 if the next loss / gradient / step of this context
  * runs the fused finest-level kernel (option on and the problem, its

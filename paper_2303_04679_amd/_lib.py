@@ -24,6 +24,7 @@ OPT_MARCH = 1
 OPT_MARCH_TILE = 2
 OPT_TAIL = 3
 OPT_TILE = 4
+OPT_TWO_PASS = 5
 MAX_LEVELS, MAX_FIELDS = 8, 5
 TERM_NAMES = ("pde", "data", "reg", "ic", "bc")
 

@@ -9,6 +9,8 @@
   ns3d64       channel flow past an ellipsoid, 64^3, FP32, L = 5, unknown
                u, v, w, p, chihat; velocity measured on the wake plane
   ns3d128      the same at 128^3, L = 6
+  ns3d256      the same at 256^3, L = 7 (2.3 GB per iteration, beyond the
+               256 MB last-level cache)
   ns3d128_shard8  one GPU's share of ns3d128 split in z-slabs over eight
                GPUs: 16 x 128 x 128 cells at the same spacing, L = 4 (the
                levels a slab keeps; the coarser ones would be replicated);
@@ -142,6 +144,7 @@ WORKLOADS = {
     "heat256_f32": lambda: heat256("f32"),
     "ns3d64": lambda: ns3d(64, 5),
     "ns3d128": lambda: ns3d(128, 6),
+    "ns3d256": lambda: ns3d(256, 7),
     "ns3d128_shard8": lambda: ns3d_shard(128, 8, 4),
     "cavity128": cavity128,
     "channel_node129": channel_node129,

@@ -180,7 +180,7 @@ Carve carve(const modil_problem &p, const modil_pack_layout &L) {
   bool xonly = false;
   for (int f = 0; f < L.n_fields; ++f) xonly |= field_is_x_only(p, f);
   c.gq = take(xonly ? (size_t)p.batch * L.fine_cells * ts : 0);
-  c.sens = take((size_t)6 * sens_fields(p) * p.batch * L.fine_cells * ts);
+  c.sens = take(two_pass_adjoint(p) ? (size_t)6 * sens_fields(p) * p.batch * L.fine_cells * ts : 0);
   c.partials = take((size_t)p.batch * (c.n_fine_blocks + c.n_data_blocks) * kTerms * 8);
   c.terms = take((size_t)p.batch * kTerms * 8);
   c.flag = take(4);
@@ -345,6 +345,17 @@ int upload_measurements(modil_ctx *c) {
   HIP_OR_RETURN(c, hipStreamSynchronize(s), "upload");
   c->n_meas_dev = (int)n;
   return MODIL_OK;
+}
+
+// a node index on the boundary of its field's grid (index 0 or n - 1 along an
+// axis the field spans)
+bool on_boundary_node(const FieldGeom &g, long idx) {
+  for (int a = 2; a >= 0; --a) {
+    const long i = idx % g.n[a];
+    idx /= g.n[a];
+    if (g.n[a] > 1 && (i == 0 || i == g.n[a] - 1)) return true;
+  }
+  return false;
 }
 
 bool use_fused(const modil_ctx *c) {
@@ -579,7 +590,7 @@ int modil_create(const modil_problem *p, void *ws, size_t ws_bytes, void *stream
   c->w_buf = c->ws + cv.w;
   c->g_buf = c->ws + cv.g;
   c->gq_buf = c->ws + cv.gq;
-  c->sens_buf = c->ws + cv.sens;
+  c->sens_buf = two_pass_adjoint(*p) ? c->ws + cv.sens : nullptr;
   c->partials = (double *)(c->ws + cv.partials);
   c->terms_tmp = (double *)(c->ws + cv.terms);
   c->flag = (int32_t *)(c->ws + cv.flag);
@@ -653,6 +664,8 @@ int modil_set_measurements(modil_ctx *c, int32_t inst, int32_t field, int32_t te
   for (int k = 0; k < n; ++k) {
     if (sorted[k] < 0 || sorted[k] >= g.size) return fail(c, MODIL_ERR_SHAPE, "cell index out of range");
     if (k && sorted[k] == sorted[k - 1]) return fail(c, MODIL_ERR_INVALID_ARG, "duplicate cell index in list");
+    if (c->prob.centering == MODIL_NODE && on_boundary_node(g, sorted[k]))
+      return fail(c, MODIL_ERR_SHAPE, "measurement on a boundary node (its value is imposed)");
   }
   for (int k = 0; k < n; ++k) c->meas.push_back(Meas{inst, field, term, idx[k], val[k], weight});
   return upload_measurements(c);
@@ -831,6 +844,10 @@ int modil_set_option(modil_ctx *c, int32_t option, int64_t value) {
   }
   if (option == MODIL_OPT_TILE) {
     c->tile_enabled = value != 0;
+    return MODIL_OK;
+  }
+  if (option == MODIL_OPT_TWO_PASS) {
+    c->two_pass_enabled = value != 0;
     return MODIL_OK;
   }
   if (option == MODIL_OPT_MARCH_TILE) {

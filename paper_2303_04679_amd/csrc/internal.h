@@ -199,6 +199,7 @@ struct modil_ctx {
   bool tail_enabled = true;   // MODIL_OPT_TAIL
   int carry_stop = 0;  // lowest level of the Horner tail the last restriction tail carried
   bool tile_enabled = true;   // MODIL_OPT_TILE
+  bool two_pass_enabled = true;  // MODIL_OPT_TWO_PASS
   size_t lds_budget = 64 * 1024;  // LDS bytes one block of the tail kernels may use
 
   long n_fine_blocks = 0;   // partial blocks of the fine kernel per instance
@@ -330,6 +331,11 @@ long fine_partial_slots(const modil_problem &P);
 // fields whose neighbours enter the stencil (a prefix of the fields), for the
 // two-pass 3-D adjoint; 0 when the problem is not 3-D
 int sens_fields(const modil_problem &P);
+// whether the workspace holds the two-pass adjoint's face-sensitivity scratch:
+// 3-D problems that can run the generic engine with a gradient, except FP32
+// cell-based channel flow, which runs the fused kernel (or, when that does
+// not apply, the single-pass per-cell kernel)
+bool two_pass_adjoint(const modil_problem &P);
 // column sums of the x-only field's contributions; with adam given also Adam
 // on that field's level 0
 hipError_t launch_colsum(modil_ctx *c, void *g_fine, const AdamHost *adam = nullptr,

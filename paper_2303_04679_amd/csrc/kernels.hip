@@ -787,7 +787,7 @@ __global__ __launch_bounds__(kBlock) void fine_gather_kernel(FineArgs<T> A, cons
 template <class Op, typename T>
 static void launch_fine_3d(modil_ctx *c, const FineArgs<T> &A, dim3 grid) {
   const int nnb = sens_fields(c->prob);
-  if (!A.want_grad || nnb == 0) {
+  if (!A.want_grad || nnb == 0 || !c->sens_buf || !c->two_pass_enabled) {
     fine_kernel<Op, T><<<grid, kBlock, 0, c->stream>>>(A);
     return;
   }
@@ -1370,6 +1370,11 @@ int sens_fields(const modil_problem &P) {
   return 0;
 }
 
+bool two_pass_adjoint(const modil_problem &P) {
+  if (sens_fields(P) == 0) return false;
+  return !(P.op == MODIL_OP_NS3D && P.centering == MODIL_CELL && P.dtype == MODIL_F32);
+}
+
 long fine_partial_slots(const modil_problem &P) {
   long cells = 1;
   for (int k = 0; k < P.ndim; ++k) cells *= P.dims[k] + (P.centering == MODIL_NODE ? 1 : 0);
@@ -1546,10 +1551,14 @@ hipError_t launch_metric(modil_ctx *c, const double *terms, double *r) {
   const modil_problem &P = c->prob;
   double V = 1.0;
   for (int k = 0; k < P.ndim; ++k) V *= P.lengths[k] / P.dims[k];
-  double rows = (double)c->lay.fine_cells;  // points carrying the PDE equations
+  // points carrying the PDE equations: every cell; the interior nodes of
+  // node-based grids; the inner points n >= 1, 1 <= i <= N - 2 of space-time grids
+  double rows = (double)c->lay.fine_cells;
   if (P.centering == MODIL_NODE) {
     rows = 1.0;
-    for (int k = 0; k < P.ndim; ++k) rows *= P.dims[k] - 1;  // interior nodes
+    for (int k = 0; k < P.ndim; ++k) rows *= P.dims[k] - 1;
+  } else if (P.op == MODIL_OP_BURGERS || P.op == MODIL_OP_HEAT_KX) {
+    rows = (double)(P.dims[0] - 1) * (double)(P.dims[1] - 2);
   }
   const double scale = V / (P.w_pde * (double)op_pde_equations(P) * rows);
   metric_kernel<<<(P.batch + 63) / 64, 64, 0, c->stream>>>(terms, r, P.batch, scale);

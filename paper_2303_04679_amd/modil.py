@@ -292,6 +292,12 @@ class Context:
         L.check(L.lib().modil_set_option(self.h, L.OPT_TILE, 1 if enabled else 0), self.h)
         self._tile = bool(enabled)
 
+    def set_two_pass(self, enabled: bool):
+        """Generic engine on 3-D problems: residuals formed once per cell with
+        the star sensitivities gathered in a second pass (default, where the
+        workspace holds their scratch), or the per-cell kernel."""
+        L.check(L.lib().modil_set_option(self.h, L.OPT_TWO_PASS, 1 if enabled else 0), self.h)
+
     def set_march_tile(self, rows: int = 0, planes: int = 0):
         """Coarse rows and planes per wave of the marching kernel (0, 0: automatic)."""
         L.check(L.lib().modil_set_option(self.h, L.OPT_MARCH_TILE, 16 * rows + planes), self.h)

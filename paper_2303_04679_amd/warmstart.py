@@ -145,35 +145,39 @@ class WarmStartNet:
 
 
 # ----------------------------------------------------------- level targets
-def interp_cell(c):
-    """Cell-based linear interpolation (the decomposition's T) of [.., n, n] to [.., 2n, 2n]."""
-    def axis(x, dim):
-        x = torch.movedim(x, dim, -1)
-        n = x.shape[-1]
-        fine = torch.empty(x.shape[:-1] + (2 * n,), dtype=x.dtype, device=x.device)
-        fine[..., 2::2] = 0.75 * x[..., 1:] + 0.25 * x[..., :-1]
-        fine[..., 1:-1:2] = 0.75 * x[..., :-1] + 0.25 * x[..., 1:]
-        fine[..., 0] = 1.25 * x[..., 0] - 0.25 * x[..., 1]
-        fine[..., -1] = 1.25 * x[..., -1] - 0.25 * x[..., -2]
-        return torch.movedim(fine, -1, dim)
-    return axis(axis(c, -1), -2)
+def _prolonged(levels):
+    """M(levels) of cavity fields through the library: levels is a list of
+    [B, 3, n_l, n_l] tensors, finest first; returns [B, 3, n_0, n_0] (float64)."""
+    from .modil import ProblemSpec
+    B, n = levels[0].shape[0], levels[0].shape[-1]
+    spec = ProblemSpec("cavity", (n, n), (1.0, 1.0), len(levels), dtype="f64", batch=B, max_meas=0)
+    ctx = Context(spec, device=levels[0].device)
+    pack = ctx.new_pack()
+    for b in range(B):
+        for lv, src in zip(ctx.level_views(pack, b), levels):
+            for f in range(3):
+                lv[f].copy_(src[b, f])
+    out = ctx.prolong(pack).view(B, 3, n, n).clone()
+    ctx.close()
+    return out
 
 
 def canonical_targets(fine):
     """fine [B, 3, N, N] converged (u, v, p) -> y at N/4, N/8, N/16.
 
     p is taken relative to its mean (the loss is invariant under p + c).
-    y_c = A_c(fine) - T(coarser part), coarsest first, with A_c the block average.
+    y_c = A_c(fine) - T(coarser part), coarsest first, with A_c the block
+    average; the interpolation T(...) is the library's prolongation of the
+    decomposition (levels below the target set to zero on the finer ones).
     """
-    f = fine.clone()
+    f = fine.clone().double()
     f[:, 2] -= f[:, 2].mean(dim=(-1, -2), keepdim=True)
-    N = f.shape[-1]
     a8 = F.avg_pool2d(f, 16)
     a16 = F.avg_pool2d(f, 8)
     a32 = F.avg_pool2d(f, 4)
     y8 = a8
-    y16 = a16 - interp_cell(y8)
-    y32 = a32 - interp_cell(y16 + interp_cell(y8))
+    y16 = a16 - _prolonged([torch.zeros_like(a16), y8])
+    y32 = a32 - _prolonged([torch.zeros_like(a32), y16, y8])
     return y32, y16, y8
 
 

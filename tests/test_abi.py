@@ -111,3 +111,22 @@ def test_node_layout():
     assert dims == [(33, 17), (17, 9), (9, 5)]
     assert lay.fine_cells == 33 * 17
     assert lay.total == 33 * 17 + 17 * 9 + 9 * 5
+
+
+def test_workspace_holds_two_pass_scratch_only_where_it_runs():
+    """The two-pass 3-D adjoint's face sensitivities (6 x 4 fields x cells)
+    are reserved for node-based and FP64 channel flow, not for FP32
+    cell-based channel flow, which runs the fused kernel (or the per-cell
+    kernel)."""
+    n = 128
+    cells = n ** 3
+    f32 = layout(ProblemSpec("ns3d", (n,) * 3, (1.0,) * 3, 6, dtype="f32")).workspace_bytes
+    f64 = layout(ProblemSpec("ns3d", (n,) * 3, (1.0,) * 3, 6, dtype="f64")).workspace_bytes
+    # FP32: the gradient pack and the Horner levels dominate, no 24 values per cell
+    assert f32 < 12 * cells * 4
+    assert f64 > 6 * 4 * cells * 8
+    node = layout(ProblemSpec("ns3d", (32, 32, 64), (1.0, 1.0, 2.0), 3, dtype="f32",
+                              centering="node")).workspace_bytes
+    assert node > 6 * 4 * 33 * 33 * 65 * 4
+    p3 = layout(ProblemSpec("poisson", (32, 32, 32), (1.0,) * 3, 3, dtype="f32")).workspace_bytes
+    assert p3 > 6 * 32 ** 3 * 4

@@ -40,4 +40,8 @@ def test_bench_prints_one_json_line():
         assert k in rf, k
     assert rf["peak"] > 0 and abs(rf["frac"] - rf["achieved"] / rf["peak"]) < 1e-9
     cb = d["cpu_baseline"]
-    assert cb["kind"] == "oracle" and cb["value"] > 0 and cb["cores"] >= 1 and cb["sample"]
+    assert cb["kind"] == "oracle" and cb["value"] > 0 and cb["cores"] == 1 and cb["sample"]
+    assert cb["nproc"] >= 1 and cb["cpu_model"]
+    cp = d["hbm_copy_probe"]
+    assert cp["gbs"] > 0 and cp["bytes"] > 0
+    assert d["iteration_roofline_frac"] > 0

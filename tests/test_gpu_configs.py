@@ -13,7 +13,7 @@ from tests.workload_oracle import oracle_spec
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("name", ["burgers64", "heat256", "heat256_f32", "ns3d64", "ns3d128",
+@pytest.mark.parametrize("name", ["burgers64", "heat256", "heat256_f32", "ns3d64", "ns3d128", "ns3d256",
                                   "ns3d128_shard8", "cavity128", "channel_node129"])
 def test_workload_loss_and_gradient(name):
     need_gpu()

@@ -137,12 +137,37 @@ def test_step_sequence_f64(op, dims, L):
         torch.cuda.synchronize()
         cur = [[s[0] for s in row] for row in ref]
         rterms, rgrad = ops.loss_and_grad(spec, cur)
-        assert_terms(terms[0].cpu().numpy(), rterms, 1e-11, (op, t))
+        print(f"[parity] step {t} terms", {k: abs(float(terms[0, i]) - rterms[k]) / max(abs(rterms[k]), 1e-300)
+                                            for i, k in enumerate(TERMS) if rterms[k]}, flush=True)
+        assert_terms(terms[0].cpu().numpy(), rterms, 1e-12, (op, t))
         ref = [[oadam.adam_step(s[0], s[1], s[2], g, 1e-2, 0.9, 0.999, 1e-8, t)
                 for s, g in zip(row, grow)] for row, grow in zip(ref, rgrad)]
         a, b = b, a
-    assert_levels(levels_of(ctx, a), [[s[0] for s in row] for row in ref], 1e-11, op)
-    assert_levels(levels_of(ctx, m), [[s[1] for s in row] for row in ref], 1e-11, op)
+    for name, pk, k in (("theta", a, 0), ("m", m, 1), ("v", v, 2)):
+        got, want = levels_of(ctx, pk), [[s[k] for s in row] for row in ref]
+        print(f"[parity] {name}", max(rel(g, r) for gr, rr in zip(got, want) for g, r in zip(gr, rr)), flush=True)
+        assert_levels(got, want, 1e-12, (op, name))
+
+
+def test_burgers_zero_face_speed():
+    """FP64 Burgers with faces of exactly zero speed: a finest level
+    antisymmetric in x (coarse levels zero) gives u_{N/2-1} = -u_{N/2} in
+    every row, so the middle face has (a + b)/2 = 0 and the upwind flux is at
+    its kink.  The derivative of |s| at s = 0 is taken as 0 on both sides."""
+    need_gpu()
+    dims = (24, 40)
+    spec = case("burgers", dims, 3, seed=9, with_forcing=True)
+    lv = [[np.zeros(s) for s in row] for row in ops.level_shapes("burgers", dims, 3)]
+    half = np.random.default_rng(31).uniform(0.05, 0.6, size=(dims[0], dims[1] // 2))
+    lv[0][0] = np.concatenate([-half[:, ::-1], half], axis=1)
+    fine = lv[0][0]
+    assert np.all(fine[:, dims[1] // 2 - 1] + fine[:, dims[1] // 2] == 0.0)
+    rterms, rgrad = ops.loss_and_grad(spec, lv)
+    ctx = context_of(spec, "f64")
+    terms, grad = ctx.loss_grad(pack_of(ctx, [lv]))
+    torch.cuda.synchronize()
+    assert_terms(terms[0].cpu().numpy(), rterms, 1e-12, "burgers kink")
+    assert_levels(levels_of(ctx, grad), rgrad, 1e-12, "burgers kink")
 
 
 @pytest.mark.parametrize("op,dims,L", [("heat", (32, 32), 4), ("ns3d", (8, 8, 16), 3)])
@@ -312,6 +337,12 @@ def test_fused_channel_kernel(op, dims, L):
     # in FP32 Adam's first steps are sign-like for near-zero gradients: compare m, v only
     for a, b in list(zip(outs[0], outs[1]))[1:]:
         assert_levels(levels_of(ctx, a), levels_of(ctx, b), tol, "step")
+    # after one fused step from zero moments m = (1 - b1) g with g the oracle's gradient
+    o, m, v = ctx.new_pack(), ctx.new_pack(), ctx.new_pack()
+    ctx.set_fused(True)
+    ctx.step(theta, o, m, v, 1, lr=1e-2)
+    torch.cuda.synchronize()
+    assert_levels(levels_of(ctx, m), [[0.1 * g for g in row] for row in rgrad], tol, "fused m", spec=spec)
 
 
 def test_fused_channel_kernel_fp32_only():
