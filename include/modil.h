@@ -266,6 +266,26 @@ int modil_run(modil_ctx *ctx, void *theta_a, void *theta_b, void *m, void *v,
               const modil_adam_hp *hp, int64_t step0, int32_t n_steps, double *terms);
 int modil_residual_metric(modil_ctx *ctx, const void *theta_pack, double *r);
 
+/* ---- allocation-free prolongation -------------------------------------------
+ * For callers that cannot allocate device memory or provide a workspace (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): modil_prolong_noalloc computes fine = M_L(theta) like
+ * modil_prolong, for a problem given directly (no context), on `hip_stream`
+ * of the current device.  The intermediate Horner levels go to a device
+ * array of MODIL_NOALLOC_SCRATCH_BYTES that the library holds on every GPU
+ * it runs on until the process ends; the call allocates nothing, host or
+ * device, on success.  theta_pack and fine_out are device arrays in the
+ * layouts above (caller-owned).  A problem whose intermediate levels need
+ * more scratch than that (bytes of the pack up to the coarsest level) fails
+ * with MODIL_ERR_SHAPE before any launch; an invalid problem as in
+ * modil_layout.  Every call on one GPU uses that GPU's one array: calls
+ * whose work overlaps on one GPU (other streams, other threads) race, and
+ * must be ordered by the caller.  Nothing in the array needs clearing: each
+ * call writes every value it reads.                                       */
+#define MODIL_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int modil_prolong_noalloc(const modil_problem *problem, const void *theta_pack, void *fine_out,
+                          void *hip_stream);
+
 /* ---- options --------------------------------------------------------------
  * MODIL_OPT_FUSED (default 1): use the fused finest-level kernel where one
  * exists (NS3D in FP32, one Reynolds number for the batch, measurements on

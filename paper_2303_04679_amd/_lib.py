@@ -117,6 +117,7 @@ _SIGS = {
     "modil_set_instance_scalar": (_I, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double]),
     "modil_prolong": (_I, [_P, _P, _P]),
     "modil_restrict_adjoint": (_I, [_P, _P, _P]),
+    "modil_prolong_noalloc": (_I, [ctypes.POINTER(Problem), _P, _P, _P]),
     "modil_loss": (_I, [_P, _P, _P]),
     "modil_loss_grad": (_I, [_P, _P, _P, _P]),
     "modil_adam": (_I, [_P, _P, _P, _P, _P, _P, ctypes.POINTER(AdamHP), ctypes.c_int64]),

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -14,6 +15,14 @@
 #include "internal.h"
 
 using namespace modil;
+
+// Scratch of the allocation-free entry point (modil_prolong_noalloc): a fixed
+// device array that every GPU the library runs on holds until the process
+// ends.  Host code never passes the array's name to a kernel (on the host it
+// stands for a host-side shadow, not a device address): it takes the device
+// address of the current device's copy once, with hipGetSymbolAddress, and
+// uses that address.
+static __device__ __align__(256) unsigned char scratch[MODIL_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -471,6 +480,25 @@ int evaluate(modil_ctx *c, const void *theta, void *grad, double *terms, const A
 
 bool check_ctx(modil_ctx *c) { return c != nullptr; }
 
+// device address of the current device's copy of `scratch`, taken once per
+// device with that device current
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kScratchDevices] = {};
+
+hipError_t scratch_address(int device, void **out) {
+  if (device < 0 || device >= kScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------- op metadata
@@ -726,6 +754,36 @@ int modil_prolong(modil_ctx *c, const void *theta, void *fine_out) {
     return MODIL_OK;
   }
   HIP_OR_RETURN(c, launch_horner(c, theta, fine_out, false), "prolong");
+  return MODIL_OK;
+}
+
+int modil_prolong_noalloc(const modil_problem *p, const void *theta, void *fine_out, void *stream) {
+  std::string msg;
+  const int st = validate(p, msg);
+  if (st) return fail_global(st, msg);
+  if (!theta || !fine_out) return fail_global(MODIL_ERR_INVALID_ARG, "NULL pointer");
+  modil_ctx c;  // host-side description only: no workspace, no measurements
+  c.prob = *p;
+  fill_layout(*p, c.lay);
+  c.stream = (hipStream_t)stream;
+  // the Horner intermediates w_l of levels 1 .. L-2 sit at their pack
+  // offsets, so the scratch must hold the pack up to level L-1
+  const size_t need = p->n_levels >= 3 ? (size_t)c.lay.level_offset[p->n_levels - 1] * dtype_size(*p) : 0;
+  if (need > MODIL_NOALLOC_SCRATCH_BYTES)
+    return fail_global(MODIL_ERR_SHAPE, "modil_prolong_noalloc: the intermediate levels need " +
+                                            std::to_string(need) + " bytes of scratch, more than " +
+                                            std::to_string((size_t)MODIL_NOALLOC_SCRATCH_BYTES));
+  hipError_t e = hipGetDevice(&c.device);
+  if (e == hipSuccess) e = scratch_address(c.device, &c.w_buf);
+  if (e != hipSuccess) return fail_global(MODIL_ERR_HIP, std::string("prolong_noalloc: ") + hipGetErrorString(e));
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c.device) == hipSuccess && lds > 0)
+    c.lds_budget = std::min<size_t>((size_t)lds, 160 * 1024);
+  if (p->n_levels == 1)
+    e = hipMemcpyAsync(fine_out, theta, c.lay.fine_total * dtype_size(*p), hipMemcpyDeviceToDevice, c.stream);
+  else
+    e = launch_horner(&c, theta, fine_out, false);
+  if (e != hipSuccess) return fail_global(MODIL_ERR_HIP, std::string("prolong_noalloc: ") + hipGetErrorString(e));
   return MODIL_OK;
 }
 
