@@ -86,6 +86,16 @@ extern "C" {
 #define MODIL_OP_CAVITY 4
 
 #define MODIL_FLAG_CHI_FIXED 1
+/* MODIL_FLAG_FUSED_RESTRICT: where the fused finest-level kernel runs (FP32
+ * cell-based NS3D with coarse levels), it also sums the finest gradient over
+ * the fine planes of every level-1 plane (the z part of M_L^T) and stores
+ * those sums in place of the finest gradient; an assembly kernel applies
+ * T^T in y and x, adds the sums at z-chunk ends and updates level 1.  The
+ * workspace then holds the sums (fine cells / 2 x (1 + 4 / chunk planes)
+ * values per field).  Same gradient up to the order of the sums; measured
+ * slower than the default (finest gradient written, marching restriction)
+ * on 128^3 and even on 256^3, so off by default.                          */
+#define MODIL_FLAG_FUSED_RESTRICT 2
 
 /* Loss terms, in the order of every terms array. */
 #define MODIL_TERM_PDE 0

@@ -15,6 +15,7 @@ F32, F64 = 0, 1
 CELL, NODE = 0, 1
 OP_POISSON, OP_BURGERS, OP_HEAT_KX, OP_NS3D, OP_CAVITY = 0, 1, 2, 3, 4
 FLAG_CHI_FIXED = 1
+FLAG_FUSED_RESTRICT = 2
 TERM_PDE, TERM_DATA, TERM_REG, TERM_IC, TERM_BC = 0, 1, 2, 3, 4
 N_TERMS = 5
 FIELD_FORCING0, FIELD_CHI = 0, 4

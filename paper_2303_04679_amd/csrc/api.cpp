@@ -137,7 +137,7 @@ int validate(const modil_problem *p, std::string &msg) {
     msg = "MODIL_FLAG_CHI_FIXED applies to MODIL_OP_NS3D only";
     return MODIL_ERR_INVALID_ARG;
   }
-  if (p->flags & ~MODIL_FLAG_CHI_FIXED) {
+  if (p->flags & ~(MODIL_FLAG_CHI_FIXED | MODIL_FLAG_FUSED_RESTRICT)) {
     msg = "unknown flags";
     return MODIL_ERR_INVALID_ARG;
   }
@@ -146,7 +146,7 @@ int validate(const modil_problem *p, std::string &msg) {
 
 struct Carve {
   size_t w, g, gq, partials, terms, flag, m_idx, m_field, m_term, m_ptr, m_val, m_w, inst_re;
-  size_t fm_ptr, fm_rec, tm_ptr, tm_rec, sens, end;
+  size_t fm_ptr, fm_rec, tm_ptr, tm_rec, sens, cpart, end;
   long n_fine_blocks, n_data_blocks, n_keys;
 };
 
@@ -207,6 +207,7 @@ Carve carve(const modil_problem &p, const modil_pack_layout &L) {
   const long tkeys = tile_keys(p);
   c.tm_ptr = take(tkeys ? ((size_t)tkeys + 1) * 4 : 0);
   c.tm_rec = take(tkeys ? mm * sizeof(FusedMeas) : 0);
+  c.cpart = take(fused_partial_bytes(p));
   c.end = off;
   return c;
 }
@@ -400,9 +401,14 @@ int evaluate(modil_ctx *c, const void *theta, void *grad, double *terms, const A
     sum.terms = terms;
     sum.flag = c->flag;
     bool summed = false;
+    // with MODIL_FLAG_FUSED_RESTRICT the fused kernel summed the finest
+    // gradient in z and the assembly kernel forms level 1
+    const int from = fused_partial_bytes(c->prob) ? 1 : 0;
     {
       Timed t(c, 2);
-      HIP_OR_RETURN(c, launch_restrict_chain(c, grad, 0, theta, th_out, m, v, adam, &sum, &summed,
+      if (from == 1)
+        HIP_OR_RETURN(c, launch_fused_assemble(c, grad, adam, theta, th_out, m, v), "assemble");
+      HIP_OR_RETURN(c, launch_restrict_chain(c, grad, from, theta, th_out, m, v, adam, &sum, &summed,
                                              carry_out, carried),
                     "restrict");
     }
@@ -619,6 +625,7 @@ int modil_create(const modil_problem *p, void *ws, size_t ws_bytes, void *stream
   c->g_buf = c->ws + cv.g;
   c->gq_buf = c->ws + cv.gq;
   c->sens_buf = two_pass_adjoint(*p) ? c->ws + cv.sens : nullptr;
+  c->cpart = fused_partial_bytes(*p) ? c->ws + cv.cpart : nullptr;
   c->partials = (double *)(c->ws + cv.partials);
   c->terms_tmp = (double *)(c->ws + cv.terms);
   c->flag = (int32_t *)(c->ws + cv.flag);

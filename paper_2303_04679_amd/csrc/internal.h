@@ -178,6 +178,7 @@ struct modil_ctx {
   void *g_buf = nullptr;     // gradient pack used by modil_step
   void *gq_buf = nullptr;    // per-cell contributions of 1-D fields (heat q)
   void *sens_buf = nullptr;  // 3-D adjoint: face-slot sensitivities [6][nnb][batch][cells]
+  void *cpart = nullptr;     // fused channel flow: level-1 gradient partials of every tile
   void *fine_tmp = nullptr;  // one fine-field array (scratch)
   double *partials = nullptr;  // [batch][n_part_blocks][kTerms]
   double *terms_tmp = nullptr; // [batch][kTerms]
@@ -350,6 +351,11 @@ hipError_t launch_reduce(modil_ctx *c, double *terms, long n_a, long off_b, long
 hipError_t launch_ns3d_fused(modil_ctx *c, const void *theta, void *g, const AdamHost *adam,
                              void *th_out, void *m, void *v);
 void ns3d_tiles(const modil_problem &P, int &tz, int &nzt, int &ntx, int &nty, int &ox, int &oy);
+// bytes of the fused kernel's level-1 gradient partials (0 where it has none)
+size_t fused_partial_bytes(const modil_problem &P);
+// level 1 of the gradient from those partials (and, with adam, Adam on level 1)
+hipError_t launch_fused_assemble(modil_ctx *c, void *g, const AdamHost *adam, const void *th_in,
+                                 void *th_out, void *m, void *v);
 // the fused kernel addresses a plane's fields by 32-bit byte offsets
 bool ns3d_offsets_fit(const modil_problem &P);
 hipError_t launch_metric(modil_ctx *c, const double *terms, double *r);

@@ -26,6 +26,8 @@
 // FP64 problems run on the generic engine.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "internal.h"
 #include "multigrid.h"
 #include "ops.h"
@@ -58,7 +60,9 @@ struct NS3DArgs {
   int th_inst;        // instance stride on level 0
   const T *w1;        // level 1 of the prolonged coarse levels
   int w1_inst;
-  T *g;               // level 0 of the gradient pack
+  T *g;               // level 0 of the gradient pack (written without Adam only)
+  T *cpart;           // level-1 gradient partials of every tile (with coarse levels)
+  int ncz, ncy, ncx;  // level-1 cells per axis
   const T *forcing[4];
   const T *chi;       // fixed chi, [instance][cells]
   const int32_t *mptr;      // [key + 1]: measurement records of (tile, plane)
@@ -72,6 +76,17 @@ struct NS3DArgs {
 // interpolation of its 36 x 20 fine columns touches, 20 x 12 per field.
 constexpr int NCT_X = NST_X / 2 + 2, NCT_Y = NST_Y / 2 + 2;
 constexpr int NCT = NCT_X * NCT_Y;
+
+// Restriction of the finest gradient to level 1 (T^T, Section 2.2): its z
+// part is fused into the gradient write.  Each owned cell sums its column's
+// gradient over the fine planes of each coarse plane (every fine plane adds
+// to the two coarse planes of its row of T, in a ring of four LDS slots) and
+// stores the sum once the plane is complete: a chunk writes the z sums of
+// its coarse planes and of the one on each side (those take its fine planes
+// next to the chunk ends), at fine (y, x) resolution.  The assembly kernel
+// applies T^T in y and x and adds the two chunks' sums of the coarse planes
+// at chunk ends, in a fixed order.
+constexpr int NACC = 4;  // ring of z accumulators
 
 // xy interpolation of one coarse plane of every field from its LDS window;
 // lx, ly are window coordinates of the taps
@@ -137,7 +152,7 @@ __device__ inline void face_add(const NSCoef<T> &K, int axis, T sgi2h, const T (
 // u_f), the slot holds a_0 -c_k, a_c c_c (k the component normal to the
 // wall) and normal velocity -u_k.  This relies on c_k = -c_p, which the host
 // checks.  Walls in z are uniform over a plane and take a branch.
-template <typename T, int CHI, bool ADAM, bool FORCING>
+template <typename T, int CHI, bool ADAM, bool FORCING, bool ZSUM>
 __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel(NS3DArgs<T> A) {
   constexpr int NF = (CHI == 2) ? 5 : 4;  // unknown fields
   constexpr int NA = 5;                   // per cell: seeds a_0, a_c (1 - chi), and u for x faces
@@ -150,6 +165,8 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
   // interpolates from and the next; the next one is loaded a plane ahead
   static_assert(NF_MAX_COARSE * NCT <= 2 * NS_THREADS, "two coarse values per thread");
   __shared__ T Cw[2][NF_MAX_COARSE * NCT];
+  // level-1 restriction: z sums per owned cell (ring of coarse planes), x-pass rows
+  __shared__ T Acc[ZSUM ? NACC : 1][NF_MAX_COARSE][NSO_Y][NSO_X];
 
   const OpParams &p = A.p;
   const int tid = threadIdx.x;
@@ -198,6 +215,19 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
   // byte offset of plane z (uniform); planes before the grid map to plane 0
   auto pofs = [&](int z) { return (uint32_t)max(z, 0) * plane_b; };
   const T *chi_base = CHI == 1 ? A.chi + inst * A.fsize : nullptr;
+
+  // ---- z part of the level-1 restriction (with coarse levels): the owned
+  // cell's sums sit in Acc[.][.][Y - 2][X - 2]; a chunk's sums are stored as
+  // zsum[instance][chunk][field][plane][y][x] with plane = K - (z0 / 2 - 1)
+  const int kz0 = z0 / 2 - 1, nkz = A.tz / 2 + 2;
+  // first and last gather planes of this chunk adding to coarse plane K (the
+  // first assigns, later ones add, the last stores): 2K - 1 .. 2K + 2 within
+  // the chunk; fine plane 0 also reaches coarse plane 1, and fine plane
+  // nz - 1 coarse plane ncz - 2
+  auto first_plane = [&](int K) { return (K == 1 && z0 == 0) ? 0 : max(z0, 2 * K - 1); };
+  auto last_plane = [&](int K) { return min(z1 - 1, K == A.ncz - 2 ? 2 * K + 3 : 2 * K + 2); };
+  T *zs_base = A.cpart + ((long)inst * A.nzt + bz) * (long)NF * nkz * plane;
+  const uint32_t zs_field_b = (uint32_t)nkz * plane_b;  // one field's planes, bytes
 
   // xy interpolation taps of this column from level 1
   int jx[2] = {0, 0}, jy[2] = {0, 0};
@@ -277,7 +307,7 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
 
   // theta (and chi) of the next plane are loaded one iteration ahead; theta
   // of the two planes before is kept for the Adam update of the gather plane
-  T thn[NF], chin = T(0), tA[NF], tB[NF];
+  T thn[NF], chin = T(0), tA[NF], tB[NF];  // tA, tB: theta of the two planes below (without ZSUM)
   for (int f = 0; f < NF; ++f) thn[f] = tA[f] = tB[f] = T(0);
   if (in_xy && z0 - 2 >= 0) {
     const uint32_t zb = pofs(z0 - 2);
@@ -305,7 +335,7 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
       for (int f = 0; f < NF; ++f) thn[f] = ld_at(th_base, fo[f] + zb);
       if (CHI == 1) chin = ld_at(chi_base, fo[0] + zb);
     }
-    T mq[NF], vq[NF];
+    T mq[NF], vq[NF], tq[NF];
     const int q = pz - 2, qb = q & 1;
     // the measurement records of plane pz-1 (read early: the loop waits on them)
     int mp0 = 0, mp1 = 0;
@@ -317,6 +347,7 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
     const uint32_t qofs = pofs(q);
     if (ADAM && gather) {
       for (int f = 0; f < NF; ++f) {
+        tq[f] = ZSUM ? ld_at(th_base, fo[f] + qofs) : tB[f];
         mq[f] = ld_at(A.adam.m + inst * A.th_inst, fo[f] + qofs);
         vq[f] = ld_at(A.adam.v + inst * A.th_inst, fo[f] + qofs);
       }
@@ -481,19 +512,36 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
       for (int f = 0; f < 4; ++f) gg[f] = g[f] + Dl[qb][f][Y][X];
       gg[4] = Cq[4];
       const int base = inst * A.th_inst;
+      if (ZSUM && A.has_coarse) {
+        // z sums: plane q adds to the two coarse planes of its row of T
+        int kk[2];
+        T ww[2];
+        prolong_taps(q, A.ncz, kk, ww);
+        for (int t = 0; t < 2; ++t) {
+          T *acc = &Acc[kk[t] & (NACC - 1)][0][Y - 2][X - 2];
+          const bool first = q == first_plane(kk[t]), last = q == last_plane(kk[t]);
+          const uint32_t zb = (uint32_t)(kk[t] - kz0) * plane_b + fo[0];
+          for (int f = 0; f < NF; ++f) {
+            const T v = (first ? T(0) : acc[f * NSO_Y * NSO_X]) + ww[t] * gg[f];
+            if (last) st_at(zs_base, zb + (uint32_t)f * zs_field_b, v);
+            else acc[f * NSO_Y * NSO_X] = v;
+          }
+        }
+      }
       for (int f = 0; f < NF; ++f) {
-        st_at(A.g + base, fo[f] + qofs, gg[f]);
+        if (!ADAM || !ZSUM) st_at(A.g + base, fo[f] + qofs, gg[f]);
         if (ADAM) {
           const T mm = A.adam.b1 * mq[f] + (T(1) - A.adam.b1) * gg[f];
           const T vv = A.adam.b2 * vq[f] + (T(1) - A.adam.b2) * gg[f] * gg[f];
           st_at(A.adam.m + base, fo[f] + qofs, mm);
           st_at(A.adam.v + base, fo[f] + qofs, vv);
           st_at(A.adam.th_out + base, fo[f] + qofs,
-                adam_theta(tB[f], mm, vv, A.adam.step, A.adam.isb2, A.adam.eps));
+                adam_theta(tq[f], mm, vv, A.adam.step, A.adam.isb2, A.adam.eps));
         }
       }
     }
-    for (int f = 0; f < NF; ++f) { tB[f] = tA[f]; tA[f] = th[f]; }
+    if (!ZSUM)
+      for (int f = 0; f < NF; ++f) { tB[f] = tA[f]; tA[f] = th[f]; }
     for (int f = 0; f < 5; ++f) Cq[f] = Cs[f];
     // the slot taken by the next coarse plane held the one below this fine
     // plane's pair, which nobody reads after step 1
@@ -589,6 +637,10 @@ static hipError_t fused_t(modil_ctx *c, const void *theta, void *g, const AdamHo
   A.theta = (const T *)theta;
   if (A.has_coarse) {
     for (int a = 0; a < 3; ++a) A.nc[a] = P.dims[a] / 2;
+    A.ncz = A.nc[0];
+    A.ncy = A.nc[1];
+    A.ncx = A.nc[2];
+    A.cpart = (T *)c->cpart;
     A.csize = A.nc[0] * A.nc[1] * A.nc[2];
     A.w1_inst = (int)c->lay.level_stride[1];
     // level 1 of the prolonged coarse fields: theta itself when it is the coarsest
@@ -611,13 +663,156 @@ static hipError_t fused_t(modil_ctx *c, const void *theta, void *g, const AdamHo
   const bool fixed = (P.flags & MODIL_FLAG_CHI_FIXED) != 0;
   const bool forcing = A.forcing[0] || A.forcing[1] || A.forcing[2] || A.forcing[3];
   auto go = [&](auto kernel) { kernel<<<grid, block, 0, c->stream>>>(A); };
-  if (fixed) {
-    if (ad) forcing ? go(ns3d_fused_kernel<T, 1, true, true>) : go(ns3d_fused_kernel<T, 1, true, false>);
-    else forcing ? go(ns3d_fused_kernel<T, 1, false, true>) : go(ns3d_fused_kernel<T, 1, false, false>);
-  } else {
-    if (ad) forcing ? go(ns3d_fused_kernel<T, 2, true, true>) : go(ns3d_fused_kernel<T, 2, true, false>);
-    else forcing ? go(ns3d_fused_kernel<T, 2, false, true>) : go(ns3d_fused_kernel<T, 2, false, false>);
+  const bool zsum = A.has_coarse && (P.flags & MODIL_FLAG_FUSED_RESTRICT) != 0;
+  auto pick = [&](auto chi_tag) {
+    constexpr int C = decltype(chi_tag)::value;
+    if (zsum) {
+      if (ad) forcing ? go(ns3d_fused_kernel<T, C, true, true, true>) : go(ns3d_fused_kernel<T, C, true, false, true>);
+      else forcing ? go(ns3d_fused_kernel<T, C, false, true, true>) : go(ns3d_fused_kernel<T, C, false, false, true>);
+    } else {
+      if (ad) forcing ? go(ns3d_fused_kernel<T, C, true, true, false>) : go(ns3d_fused_kernel<T, C, true, false, false>);
+      else forcing ? go(ns3d_fused_kernel<T, C, false, true, false>) : go(ns3d_fused_kernel<T, C, false, false, false>);
+    }
+  };
+  if (fixed) pick(std::integral_constant<int, 1>{});
+  else pick(std::integral_constant<int, 2>{});
+  return hipGetLastError();
+}
+
+// Level-1 gradient from the chunks' z sums.  A block owns 32 x 8 level-1
+// cells of one coarse plane, field and instance: it adds the (one or two)
+// chunks' z sums of its fine region (the cells' rows and columns of T plus
+// two on each side) into LDS, lower chunk first, applies T^T along x and then
+// along y, writes the sums to the gradient pack and, with Adam, updates
+// level 1.  Grid: (ncx / 32, ncy / 8, (instance * nf + field) * ncz + z).
+constexpr int AS_X = 32, AS_Y = 8;                      // level-1 cells per block
+constexpr int AS_FX = 2 * AS_X + 4, AS_FY = 2 * AS_Y + 4;  // fine region: two more each side
+
+template <typename T>
+struct AssembleArgs {
+  const T *zsum;         // [instance][chunk][field][plane][fine y][fine x]
+  T *g;                  // gradient pack (level 1 is written)
+  int batch, nf, tz, nzt;
+  int ncz, ncy, ncx;
+  int off1, stride1;     // pack offset of level 1, its elements per instance
+  AdamArgs<T> adam;      // pack bases
+};
+
+// One level-1 cell of T^T along an axis: coarse cell J (of n), v[0..3] the
+// fine cells 2J - 1 .. 2J + 2 (zero outside the grid), v[-S] fine cell
+// 2J - 2 and v[4S] fine cell 2J + 3.  Interior cells take 1/4, 3/4, 3/4,
+// 1/4; the end rows of T (fine cells 0 and 2n - 1 extrapolate: 5/4 and -1/4)
+// add to coarse cells 0, 1, n - 2 and n - 1.
+template <typename T, int S>
+__device__ inline T restrict_tap(const T *v, int J, int n) {
+  T acc = T(0.25) * v[0] + T(0.75) * v[S] + T(0.75) * v[2 * S] + T(0.25) * v[3 * S];
+  if (J <= 1 || J >= n - 2) {
+    if (J == 0) acc += T(0.5) * v[S];          // fine 0: 5/4 instead of 3/4
+    if (J == n - 1) acc += T(0.5) * v[2 * S];  // fine 2n - 1: 5/4 instead of 3/4
+    if (J == 1) acc += T(-0.25) * v[-S];       // fine 0 reaches coarse 1
+    if (J == n - 2) acc += T(-0.25) * v[4 * S];  // fine 2n - 1 reaches coarse n - 2
   }
+  return acc;
+}
+
+template <typename T, bool ADAM>
+__global__ __launch_bounds__(256) void fused_assemble_kernel(AssembleArgs<T> A) {
+  __shared__ T F[AS_FY][AS_FX];  // fine region: row i is fine row 2 y0 - 2 + i
+  __shared__ T Xs[AS_FY][AS_X];  // x sums of every fine row of the region
+  const int tid = threadIdx.x;
+  const int x0 = blockIdx.x * AS_X, y0 = blockIdx.y * AS_Y;
+  const int bz = blockIdx.z;
+  const int z = bz % A.ncz, rest = bz / A.ncz;
+  const int f = rest % A.nf, inst = rest / A.nf;
+  const int hz = A.tz / 2, nkz = hz + 2;
+  const int nx = 2 * A.ncx, ny = 2 * A.ncy;
+  const long plane = (long)nx * ny;
+  // the chunks holding z sums of coarse plane z (three when a chunk holds one
+  // coarse plane): (chunk, plane slot), lower first
+  int cz[3], sz[3], nc = 0;
+  {
+    const int c = z / hz, k = z - c * hz;
+    if (k == 0 && c > 0) { cz[nc] = c - 1; sz[nc++] = hz + 1; }
+    cz[nc] = c; sz[nc++] = k + 1;
+    if (k == hz - 1 && c + 1 < A.nzt) { cz[nc] = c + 1; sz[nc++] = 0; }
+  }
+  // the level-1 state of this thread's cell, loaded early
+  const int lx = tid % AS_X, ly = tid / AS_X;
+  const int cx = x0 + lx, cy = y0 + ly;
+  const bool mine = cx < A.ncx && cy < A.ncy;
+  const long pe = (long)A.off1 + (long)inst * A.stride1 + ((long)f * A.ncz + z) * A.ncy * A.ncx +
+                  (long)cy * A.ncx + cx;
+  T th = T(0), mo = T(0), vo = T(0);
+  if (ADAM && mine) { th = A.adam.th_in[pe]; mo = A.adam.m[pe]; vo = A.adam.v[pe]; }
+  // fine region, chunks added in order (0 outside the grid)
+  const int fy0 = 2 * y0 - 2, fx0 = 2 * x0 - 2;
+  for (int e = tid; e < AS_FY * AS_FX; e += 256) {
+    const int i = e / AS_FX, j = e - i * AS_FX;
+    const int fy = fy0 + i, fx = fx0 + j;
+    T v = T(0);
+    if (fy >= 0 && fy < ny && fx >= 0 && fx < nx)
+      for (int t = 0; t < nc; ++t)
+        v += A.zsum[(((long)inst * A.nzt + cz[t]) * A.nf + f) * nkz * plane + sz[t] * plane +
+                    (long)fy * nx + fx];
+    F[i][j] = v;
+  }
+  __syncthreads();
+  // x sums: fine row i, level-1 column x0 + c (fine columns 2(x0 + c) - 1 .. at F[i][2c + 1 ..])
+  for (int e = tid; e < AS_FY * AS_X; e += 256) {
+    const int i = e / AS_X, c = e - i * AS_X;
+    Xs[i][c] = x0 + c < A.ncx ? restrict_tap<T, 1>(&F[i][2 * c + 1], x0 + c, A.ncx) : T(0);
+  }
+  __syncthreads();
+  if (!mine) return;
+  const T sum = restrict_tap<T, AS_X>(&Xs[2 * ly + 1][lx], cy, A.ncy);
+  A.g[pe] = sum;
+  if (ADAM) {
+    const T mm = A.adam.b1 * mo + (T(1) - A.adam.b1) * sum;
+    const T vv = A.adam.b2 * vo + (T(1) - A.adam.b2) * sum * sum;
+    A.adam.m[pe] = mm;
+    A.adam.v[pe] = vv;
+    A.adam.th_out[pe] = adam_theta(th, mm, vv, A.adam.step, A.adam.isb2, A.adam.eps);
+  }
+}
+
+size_t fused_partial_bytes(const modil_problem &P) {
+  if (P.op != MODIL_OP_NS3D || P.centering != MODIL_CELL || P.dtype != MODIL_F32 || P.n_levels < 2 ||
+      !(P.flags & MODIL_FLAG_FUSED_RESTRICT))
+    return 0;
+  int tz, nzt, ntx, nty, ox, oy;
+  ns3d_tiles(P, tz, nzt, ntx, nty, ox, oy);
+  const int nf = (P.flags & MODIL_FLAG_CHI_FIXED) ? 4 : 5;
+  return (size_t)P.batch * nzt * nf * (tz / 2 + 2) * P.dims[1] * P.dims[2] * sizeof(float);
+}
+
+hipError_t launch_fused_assemble(modil_ctx *c, void *g, const AdamHost *ad, const void *th_in,
+                                 void *th_out, void *m, void *v) {
+  const modil_problem &P = c->prob;
+  if (P.dtype != MODIL_F32 || P.n_levels < 2) return hipErrorInvalidValue;
+  AssembleArgs<float> A{};
+  int ox, oy, ntx, nty;
+  ns3d_tiles(P, A.tz, A.nzt, ntx, nty, ox, oy);
+  A.zsum = (const float *)c->cpart;
+  A.g = (float *)g;
+  A.batch = P.batch;
+  A.nf = c->lay.n_fields;
+  A.ncz = P.dims[0] / 2;
+  A.ncy = P.dims[1] / 2;
+  A.ncx = P.dims[2] / 2;
+  A.off1 = (int)c->lay.level_offset[1];
+  A.stride1 = (int)c->lay.level_stride[1];
+  if (ad) {
+    A.adam.th_in = (const float *)th_in; A.adam.th_out = (float *)th_out;
+    A.adam.m = (float *)m; A.adam.v = (float *)v;
+    A.adam.b1 = float(ad->b1); A.adam.b2 = float(ad->b2); A.adam.step = float(ad->step);
+    A.adam.isb2 = float(ad->isb2); A.adam.eps = float(ad->eps);
+  }
+  const dim3 grid((unsigned)((A.ncx + AS_X - 1) / AS_X), (unsigned)((A.ncy + AS_Y - 1) / AS_Y),
+                  (unsigned)(A.ncz * A.nf * A.batch)),
+      block(256);
+  if (grid.x > 65535 || grid.y > 65535 || grid.z > 65535) return hipErrorInvalidConfiguration;
+  if (ad) fused_assemble_kernel<float, true><<<grid, block, 0, c->stream>>>(A);
+  else fused_assemble_kernel<float, false><<<grid, block, 0, c->stream>>>(A);
   return hipGetLastError();
 }
 

@@ -42,6 +42,7 @@ class ProblemSpec:
     w_reg: float = 0.0
     w_bc: float = 0.0
     centering: str = "cell"   # "cell", or "node" (Poisson, cavity, channel flow)
+    fused_restrict: bool = False  # MODIL_FLAG_FUSED_RESTRICT
 
     @property
     def torch_dtype(self):
@@ -75,7 +76,8 @@ class ProblemSpec:
         p.centering = L.NODE if self.centering == "node" else L.CELL
         p.dtype = DTYPES[self.dtype][0]
         p.op = OPS[self.op]
-        p.flags = L.FLAG_CHI_FIXED if self.chi_fixed else 0
+        p.flags = (L.FLAG_CHI_FIXED if self.chi_fixed else 0) | \
+            (L.FLAG_FUSED_RESTRICT if self.fused_restrict else 0)
         p.batch = int(self.batch)
         p.max_meas = int(self.max_meas)
         p.re, p.diam, p.lambda_ = float(self.re), float(self.diam), float(self.lam)
