@@ -28,9 +28,10 @@ class SolveResult:
     r_history: list             # (iteration, r[batch]) every check
     seconds: float              # wall time of the loop (device synchronised)
     theta: torch.Tensor         # final parameter pack
-    iters_run: int
+    iters_run: int              # iteration count at the end (it0 included)
     iterations_monitor: Optional[np.ndarray] = None  # first check with monitor <= target
     monitor_history: Optional[list] = None           # (iteration, monitor[batch]) every check
+    moments: Optional[tuple] = None                  # Adam (m, v) at the end
 
 
 def cosine_lr(lr0, lr_min, total):
@@ -46,11 +47,15 @@ def solve(ctx: Context, theta: torch.Tensor, lr: float | Callable[[int], float],
           r_target: float = 1e-6, check_every: int = 50, betas=(0.9, 0.999), eps=1e-8,
           log: Optional[Callable[[int, np.ndarray], None]] = None,
           monitor: Optional[Callable[[torch.Tensor], np.ndarray]] = None,
-          monitor_target: float = 0.0) -> SolveResult:
+          monitor_target: float = 0.0, moments: Optional[tuple] = None, it0: int = 0,
+          stop_when_done: bool = True) -> SolveResult:
+    """Adam iterations it0 .. max_iters from theta (and Adam moments `moments`,
+    zero if None); iteration numbers (steps of the bias correction, checks,
+    the schedule) continue from it0."""
     B = ctx.spec.batch
     a = theta.clone()
     b = ctx.new_pack()
-    m, v = ctx.new_pack(), ctx.new_pack()
+    m, v = (ctx.new_pack(), ctx.new_pack()) if moments is None else (moments[0].clone(), moments[1].clone())
     r_dev = torch.empty((B,), dtype=torch.float64, device=ctx.device)
     r_host = torch.empty((B,), dtype=torch.float64, pin_memory=True)
     iters = np.full(B, -1, dtype=np.int64)
@@ -59,7 +64,7 @@ def solve(ctx: Context, theta: torch.Tensor, lr: float | Callable[[int], float],
     lr_f = lr if callable(lr) else (lambda t: lr)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    it = 0
+    it = it0
     while True:
         if it % check_every == 0:
             ctx.residual_metric(a, out=r_dev)
@@ -75,7 +80,7 @@ def solve(ctx: Context, theta: torch.Tensor, lr: float | Callable[[int], float],
                 iters_m[(iters_m < 0) & (e <= monitor_target)] = it
             if log:
                 log(it, r)
-            done = np.all(iters >= 0) and np.all(iters_m >= 0)
+            done = np.all(iters >= 0) and np.all(iters_m >= 0) and stop_when_done
             if done or it >= max_iters or not np.all(np.isfinite(r)):
                 break
         ctx.step(a, b, m, v, it + 1, lr=lr_f(it), beta1=betas[0], beta2=betas[1], eps=eps)
@@ -84,4 +89,4 @@ def solve(ctx: Context, theta: torch.Tensor, lr: float | Callable[[int], float],
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
     return SolveResult(iters, hist[-1][1], hist, secs, a, it,
-                       iters_m if monitor else None, mhist if monitor else None)
+                       iters_m if monitor else None, mhist if monitor else None, (m, v))

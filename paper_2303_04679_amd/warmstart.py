@@ -249,16 +249,58 @@ def predict(net, re, idx, u_obs, v_obs):
     return net.split(net.forward(B))
 
 
+def _take(ctx, dst, src, which):
+    """Copy the instances b with which[b] of pack src into pack dst."""
+    for b in range(ctx.spec.batch):
+        if which[b]:
+            for ld, ls in zip(ctx.level_views(dst, b), ctx.level_views(src, b)):
+                for fd, fs in zip(ld, ls):
+                    fd.copy_(fs)
+    return dst
+
+
 def choose_start(ctx, cold, warm):
-    """Fallback rule: keep the warm start only where its residual metric is below
-    the cold start's; returns (theta, used_warm[B])."""
+    """Fallback rule at the start: keep the warm start only where its residual
+    metric is below the cold start's; returns (theta, used_warm[B])."""
     rc = ctx.residual_metric(cold).cpu().numpy()
     rw = ctx.residual_metric(warm).cpu().numpy()
     use = rw < rc
-    theta = cold.clone()
-    for b in range(ctx.spec.batch):
-        if use[b]:
-            for lc, lw in zip(ctx.level_views(theta, b), ctx.level_views(warm, b)):
-                for fc, fw in zip(lc, lw):
-                    fc.copy_(fw)
-    return theta, use
+    return _take(ctx, cold.clone(), warm, use), use
+
+
+def solve_with_fallback(ctx, cold, warm, lr, max_iters, checkpoint, r_target=1e-6, check_every=50):
+    """mODIL from the warm start, judged by cold-start mODIL.
+
+    The warm start is used only where its residual metric is below the cold
+    start's (choose_start).  Both runs then go on to iteration `checkpoint`
+    (a multiple of check_every); every instance whose warm run has not
+    brought its residual below the cold run's at that iteration continues
+    from the cold run's state (parameters and Adam moments), the others from
+    the warm run's.  Returns (result, used_at_start, kept_at_checkpoint): the
+    SolveResult of the continued run, whose `iterations` holds, per instance,
+    the first checked iteration with r <= r_target of the run it kept.
+    """
+    from .solve import solve
+    assert checkpoint % check_every == 0
+    start, use0 = choose_start(ctx, cold, warm)
+    rw = solve(ctx, start, lr, checkpoint, r_target=r_target, check_every=check_every,
+               stop_when_done=False)
+    rc = solve(ctx, cold, lr, checkpoint, r_target=r_target, check_every=check_every,
+               stop_when_done=False)
+    keep = use0 & (rw.r_final < rc.r_final)
+    back = ~keep
+    theta = _take(ctx, rw.theta.clone(), rc.theta, back)
+    m = _take(ctx, rw.moments[0].clone(), rc.moments[0], back)
+    v = _take(ctx, rw.moments[1].clone(), rc.moments[1], back)
+    out = solve(ctx, theta, lr, max_iters, r_target=r_target, check_every=check_every,
+                moments=(m, v), it0=checkpoint)
+    early = np.where(keep, _first_hits(rw, r_target), _first_hits(rc, r_target))
+    out.iterations = np.where(early >= 0, early, out.iterations)
+    return out, use0, keep
+
+
+def _first_hits(res, target):
+    it = np.full(len(res.r_final), -1)
+    for i, r in res.r_history:
+        it[(it < 0) & (r <= target)] = i
+    return it

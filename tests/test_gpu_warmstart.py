@@ -1,0 +1,122 @@
+"""What the trained warm-start network gains over mODIL without it, on the
+128^2 lid-driven cavity (Section 3.3's problem with Re ~ U(100, 1000) per
+instance), and the cold-start fallback.
+
+A network trained on 96 cold-start solutions (its own forward and backward
+kernels, Adam on the GPU) starts 16 held-out instances from predicted coarse
+levels; the same iteration from zero is the baseline.  Both runs use the same
+step schedule; the metric is the first checked iteration with residual
+r <= 1e-5.  The fallback (cold-start mODIL as the judge) keeps a prediction
+only where it lowers the starting residual and, at a checkpoint, only where
+the warm run's residual is below the cold run's.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2303_04679_amd import warmstart as W
+from paper_2303_04679_amd.solve import cosine_lr, solve
+from tests.gpu_helpers import need_gpu
+
+pytestmark = pytest.mark.gpu
+
+N, LEVELS, N_OBS = 128, 5, 64
+TARGET = 1e-5
+
+
+def _net(seed):
+    return W.WarmStartNet(W.NetConfig(batch=32, size=N, n_obs=N_OBS, width1=16, width2=24, width3=24),
+                          seed=seed)
+
+
+@pytest.fixture(scope="module")
+def setup():
+    need_gpu()
+    print("\n[warmstart] cold solves of 96 training instances", flush=True)
+    res, idx = W.instances(list(range(96)), n=N, n_obs=N_OBS)
+    ctx = W.cavity_context(res, n=N, levels=LEVELS)
+    out = solve(ctx, ctx.new_pack(), cosine_lr(3e-3, 1e-6, 20000), 20000, r_target=0.0, check_every=500)
+    fine = W.fine_fields(ctx, out.theta)
+    ys = W.canonical_targets(fine.double())
+    u, v = W.observe(fine, idx)
+    ctx.close()
+    print("[warmstart] training the network", flush=True)
+    net = _net(0)
+    tgt = torch.cat([y.float().reshape(len(res), -1) for y in ys], 1).contiguous()
+    g = np.random.default_rng(0)
+    lrf = cosine_lr(3e-3, 3e-5, 1500)
+    losses = []
+    for s in range(1500):
+        pick = np.sort(g.choice(len(res), 32, replace=False))
+        pt = torch.as_tensor(pick, device="cuda")
+        W.predict(net, res[pick], idx[pick], u[pt].contiguous(), v[pt].contiguous())
+        losses.append(float(net.loss_backward(32, tgt[pt].contiguous())))
+        net.adam(lrf(s))
+    print("[warmstart] held-out references", flush=True)
+    tres, tidx = W.instances(list(range(5000, 5016)), n=N, n_obs=N_OBS)
+    cref = W.cavity_context(tres, n=N, levels=LEVELS)
+    ref = solve(cref, cref.new_pack(), cosine_lr(3e-3, 1e-6, 30000), 30000, r_target=0.0, check_every=500)
+    tf = W.fine_fields(cref, ref.theta)
+    tu, tv = W.observe(tf, tidx)
+    cref.close()
+    return {"net": net, "losses": losses, "tres": tres, "tidx": tidx, "tu": tu, "tv": tv}
+
+
+def _starts(net, d):
+    ctx = W.cavity_context(d["tres"], n=N, levels=LEVELS)
+    y = W.predict(net, d["tres"], d["tidx"], d["tu"], d["tv"])
+    return ctx, ctx.new_pack(), W.warm_levels(ctx, ctx.new_pack(), *y)
+
+
+def test_trained_network_gains_over_cold_start(setup):
+    d = setup
+    assert np.mean(d["losses"][-100:]) < 0.1 * d["losses"][0]   # the network learned
+    ctx, cold, warm = _starts(d["net"], d)
+    lr = cosine_lr(1e-3, 1e-6, 15000)
+    oc = solve(ctx, cold, lr, 15000, r_target=TARGET, check_every=25)
+    ow = solve(ctx, warm, lr, 15000, r_target=TARGET, check_every=25)
+    fo, use0, keep = W.solve_with_fallback(ctx, cold, warm, lr, 15000, checkpoint=500,
+                                           r_target=TARGET, check_every=25)
+    ic, iw, if_ = oc.iterations, ow.iterations, fo.iterations
+    print(f"[warmstart] iterations to r <= {TARGET}: cold median {np.median(ic)}, warm median "
+          f"{np.median(iw)}, with fallback {np.median(if_)} (warm kept {keep.mean():.2f})", flush=True)
+    assert np.all(ic >= 0) and np.all(iw >= 0) and np.all(if_ >= 0)
+    assert np.median(iw) <= 0.5 * np.median(ic)
+    assert np.median(if_) <= 0.5 * np.median(ic)
+    assert use0.mean() >= 0.75
+    ctx.close()
+
+
+def test_fallback_rejects_an_untrained_network(setup):
+    """Random weights predict worse than zero: the starting-residual rule takes
+    the cold start for every instance and the run equals cold-start mODIL."""
+    d = setup
+    ctx, cold, warm = _starts(_net(7), d)
+    _, use = W.choose_start(ctx, cold, warm)
+    assert not use.any()
+    lr = cosine_lr(1e-3, 1e-6, 15000)
+    oc = solve(ctx, cold, lr, 3000, r_target=TARGET, check_every=25)
+    fo, use0, keep = W.solve_with_fallback(ctx, cold, warm, lr, 3000, checkpoint=500,
+                                           r_target=TARGET, check_every=25)
+    assert not keep.any()
+    np.testing.assert_array_equal(fo.iterations, oc.iterations)
+    ctx.close()
+
+
+def test_canonical_targets_use_the_decompositions_interpolation():
+    """y16 = A16 u - T y8 and y32 = A32 u - T(y16 + T y8) with T the oracle's
+    cell-based interpolation (A: block averages, pressure relative to its mean)."""
+    need_gpu()
+    from oracle import multigrid as mg
+    g = torch.Generator().manual_seed(3)
+    fine = torch.rand((2, 3, 64, 64), generator=g, dtype=torch.float64).cuda()
+    y32, y16, y8 = W.canonical_targets(fine)
+    f = fine.cpu().clone()
+    f[:, 2] -= f[:, 2].mean(dim=(-1, -2), keepdim=True)
+    a = {k: torch.nn.functional.avg_pool2d(f, k) for k in (4, 8, 16)}
+    for b in range(2):
+        for c in range(3):
+            t8 = mg.decompose_horner([torch.zeros(8, 8), y8[b, c].cpu()], (0, 1), "cell")
+            assert torch.allclose(y16[b, c].cpu(), a[8][b, c] - t8, rtol=0, atol=1e-13)
+            t = mg.decompose_horner([torch.zeros(16, 16), y16[b, c].cpu(), y8[b, c].cpu()], (0, 1), "cell")
+            assert torch.allclose(y32[b, c].cpu(), a[4][b, c] - t, rtol=0, atol=1e-13)
