@@ -1,0 +1,159 @@
+"""Index walk of the fused channel-flow kernel on the host: the tile mapping,
+the thread roles, every LDS slot and every 32-bit global byte offset the
+kernel forms, for every block, thread and plane of the problem sizes the GPU
+tests and the benchmark use.  The formulas restate the kernel's index
+arithmetic (tiles of 32 x 16 owned cells with a 2-cell halo, 768 threads,
+z-chunks of 16/8/4/2 planes, the level-1 window of 20 x 12 coarse cells, the
+optional z sums of the gradient); a slot or offset outside its array, a cell
+owned twice or not at all, or an offset past 2^32 fails here, on the CPU."""
+import numpy as np
+import pytest
+
+NSO_X, NSO_Y = 32, 16
+NST_X, NST_Y = NSO_X + 4, NSO_Y + 4
+NS_MAIN = NSO_X * NST_Y
+NS_HALO = 4 * NST_Y
+NS_THREADS = NS_MAIN + (NS_HALO + 63) // 64 * 64
+NS_XCD, CUS = 8, 256
+NCT_X, NCT_Y = NST_X // 2 + 2, NST_Y // 2 + 2
+NF_MAX = 5
+
+
+def tiles(nz, ny, nx, batch):
+    ntx = -(-nx // NSO_X)
+    nty = -(-ny // NSO_Y)
+    xy = ntx * nty * batch
+    tz = 16
+    while tz > 2 and xy * (-(-nz // tz)) < CUS:
+        tz //= 2
+    return tz, -(-nz // tz), ntx, nty
+
+
+def threads():
+    tid = np.arange(NS_THREADS)
+    X = np.zeros_like(tid)
+    Y = np.zeros_like(tid)
+    active = np.ones(NS_THREADS, bool)
+    main = tid < NS_MAIN
+    X[main] = 2 + tid[main] % NSO_X
+    Y[main] = tid[main] // NSO_X
+    halo = (tid >= NS_MAIN) & (tid < NS_MAIN + NS_HALO)
+    h = tid[halo] - NS_MAIN
+    c = h // NST_Y
+    X[halo] = np.where(c < 2, c, NSO_X + c)
+    Y[halo] = h % NST_Y
+    active[tid >= NS_MAIN + NS_HALO] = False
+    return tid, X, Y, active
+
+
+def prolong_taps(i, n):
+    """Cell-based T taps of fine cell i (of 2n): parent and neighbour."""
+    J = i >> 1
+    nb = np.where(i & 1, J + 1, J - 1)
+    lo = nb < 0
+    hi = nb >= n
+    j1 = np.where(lo, J + 1, np.where(hi, J - 1, nb))
+    return J, j1
+
+
+CASES = [((24, 36, 60), 1, 3), ((16, 28, 24), 1, 3), ((64, 16, 32), 1, 4), ((8, 8, 8), 1, 1),
+         ((16, 16, 24), 1, 3), ((8, 16, 24), 1, 3), ((16, 24, 32), 2, 3), ((40, 12, 20), 4, 3),
+         ((40, 12, 20), 26, 3), ((40, 12, 20), 52, 3), ((40, 12, 20), 86, 3), ((16, 16, 32), 1, 3),
+         ((32, 32, 64), 1, 4), ((64, 64, 64), 1, 5), ((128, 128, 128), 1, 6),
+         ((16, 128, 128), 1, 4), ((256, 256, 256), 1, 7), ((8, 8, 16), 1, 3)]
+
+
+@pytest.mark.parametrize("dims,batch,L", CASES)
+@pytest.mark.parametrize("nf", [5, 4])
+def test_fused_kernel_indices(dims, batch, L, nf):
+    nz, ny, nx = dims
+    tz, nzt, ntx, nty = tiles(nz, ny, nx, batch)
+    ntiles = nzt * ntx * nty
+    tpx = -(-ntiles // NS_XCD)
+    # ---- block -> (instance, tile): every pair exactly once
+    blocks = np.arange(NS_XCD * tpx * batch)
+    per_inst = NS_XCD * tpx
+    inst = blocks // per_inst
+    bl = blocks - inst * per_inst
+    tile = (bl % NS_XCD) * tpx + bl // NS_XCD
+    ok = tile < ntiles
+    pairs = inst[ok] * ntiles + tile[ok]
+    assert np.array_equal(np.sort(pairs), np.arange(batch * ntiles))
+    # ---- thread roles cover the 36 x 20 tile once
+    tid, X, Y, active = threads()
+    pos = Y[active] * NST_X + X[active]
+    assert np.array_equal(np.sort(pos), np.arange(NST_X * NST_Y))
+    fsize = nz * ny * nx
+    plane = nx * ny
+    assert nf * fsize * 4 < 2 ** 32            # the host's 32-bit offset condition
+    owned = np.zeros(batch * nzt * ny * nx, np.int64)
+    for t in range(ntiles):
+        bx, by, bz = t % ntx, (t // ntx) % nty, t // (ntx * nty)
+        ox, oy = bx * NSO_X - 2, by * NSO_Y - 2
+        x, y = ox + X, oy + Y
+        z0, z1 = bz * tz, min(bz * tz + tz, nz)
+        in_xy = active & (x >= 0) & (x < nx) & (y >= 0) & (y < ny)
+        seed = in_xy & (X >= 1) & (X <= NST_X - 2) & (Y >= 1) & (Y <= NST_Y - 2)
+        own = in_xy & (X >= 2) & (X <= NST_X - 3) & (Y >= 2) & (Y <= NST_Y - 3)
+        # LDS: staged plane, wall slots across the grid's walls, stencil and gather reads
+        for cond, dx, dy in ((seed & (x == 0), -1, 0), (seed & (x == nx - 1), 1, 0),
+                             (seed & (y == 0), 0, -1), (seed & (y == ny - 1), 0, 1)):
+            xs, ys = X[cond] + dx, Y[cond] + dy
+            assert np.all((xs >= 0) & (xs < NST_X) & (ys >= 0) & (ys < NST_Y))
+        for m in (seed, own):
+            for dx, dy in ((-1, 0), (1, 0), (0, -1), (0, 1)):
+                xs, ys = X[m] + dx, Y[m] + dy
+                assert np.all((xs >= 0) & (xs < NST_X) & (ys >= 0) & (ys < NST_Y))
+        # ownership of the chunk's columns
+        col = y * nx + x
+        owned_idx = bz * plane + col[own]
+        np.add.at(owned, owned_idx, 1)  # instance 0's tiles; the others are the same
+        # global byte offsets: column in the last field plus the farthest plane
+        fo = ((nf - 1) * fsize + np.where(in_xy, col, 0)) * 4
+        planes = [z for z in range(z0 - 2, z1 + 2) if 0 <= z < nz]
+        assert np.all(fo + max(planes) * plane * 4 < nf * fsize * 4)
+        assert np.all(fo + max(planes) * plane * 4 < 2 ** 32)
+        if L > 1:
+            nc = (nz // 2, ny // 2, nx // 2)
+            cxb, cyb = (ox >> 1) - 1, (oy >> 1) - 1
+            jx = prolong_taps(x[in_xy], nc[2])
+            jy = prolong_taps(y[in_xy], nc[1])
+            for j in jx:
+                assert np.all((j - cxb >= 0) & (j - cxb < NCT_X)), "x window"
+                assert np.all((j >= 0) & (j < nc[2]))
+            for j in jy:
+                assert np.all((j - cyb >= 0) & (j - cyb < NCT_Y)), "y window"
+                assert np.all((j >= 0) & (j < nc[1]))
+            # coarse planes the march reads: kbase(z) and kbase(z) + 1 of every plane
+            zs = np.array(planes)
+            kb = np.where(zs == 0, 0, np.where(zs == nz - 1, nc[0] - 2, np.where(zs & 1, zs // 2, zs // 2 - 1)))
+            assert np.all((kb >= 0) & (kb + 1 < nc[0]))
+            # the window values the threads move: offsets inside level 1
+            e = np.concatenate([tid, tid + NS_THREADS])
+            e = e[e < nf * NCT_X * NCT_Y]
+            assert nf * NCT_X * NCT_Y <= 2 * NS_THREADS
+            f, rem = e // (NCT_X * NCT_Y), e % (NCT_X * NCT_Y)
+            cy, cx = cyb + rem // NCT_X, cxb + rem % NCT_X
+            cin = (cy >= 0) & (cy < nc[1]) & (cx >= 0) & (cx < nc[2])
+            csize = nc[0] * nc[1] * nc[2]
+            co = (f[cin] * csize + cy[cin] * nc[2] + cx[cin]) * 4
+            assert np.all(co + (nc[0] - 1) * nc[1] * nc[2] * 4 < nf * csize * 4)
+            # z sums of the gradient (optional path): slots and offsets
+            hz, kz0 = tz // 2, z0 // 2 - 1
+            nkz = hz + 2
+            for q in range(z0, z1):
+                for K in prolong_taps(np.array([q]), nc[0]):
+                    assert 0 <= int(K[0]) - kz0 < nkz
+            zmax = ((nkz - 1) * plane + (nf - 1) * nkz * plane + col[own]) * 4
+            assert np.all(zmax < nf * nkz * plane * 4) and np.all(zmax < 2 ** 32)
+    # every cell of every chunk owned exactly once
+    assert np.all(owned[:nzt * plane] == 1)
+
+
+def test_measurement_positions_in_tile():
+    """A measurement's position in its tile (halo included) is inside the staged plane."""
+    for nz, ny, nx in ((24, 36, 60), (128, 128, 128), (40, 12, 20)):
+        idx = np.arange(nz * ny * nx)
+        lx = idx % nx % NSO_X + 2
+        ly = idx // nx % ny % NSO_Y + 2
+        assert np.all((lx >= 2) & (lx < NST_X - 2) & (ly >= 2) & (ly < NST_Y - 2))
