@@ -154,7 +154,7 @@ struct Carve {
 // measurement buckets (0 for other operators)
 void fused_geometry(const modil_problem &p, long &blocks, long &keys) {
   blocks = keys = 0;
-  if (p.op != MODIL_OP_NS3D || p.centering != MODIL_CELL) return;
+  if (p.op != MODIL_OP_NS3D) return;
   int tz, nzt, ntx, nty, ox, oy;
   ns3d_tiles(p, tz, nzt, ntx, nty, ox, oy);
   blocks = (long)nzt * ntx * nty;
@@ -270,15 +270,17 @@ int upload_measurements(modil_ctx *c) {
   c->fused_ok = false;
   std::vector<int32_t> fptr;
   std::vector<FusedMeas> frec;
-  if (c->prob.op == MODIL_OP_NS3D && c->prob.centering == MODIL_CELL) {
+  if (c->prob.op == MODIL_OP_NS3D) {
     int tz, nzt, ntx, nty, ox, oy;
     ns3d_tiles(c->prob, tz, nzt, ntx, nty, ox, oy);
-    const int nz = c->prob.dims[0], ny = c->prob.dims[1], nx = c->prob.dims[2];
-    (void)nz;
+    // the fused kernel's grid: cells, or the interior nodes (measurements on
+    // boundary nodes are rejected when they are set)
+    const int e = c->prob.centering == MODIL_NODE ? 1 : 0;
+    const int ny = c->prob.dims[1] + e, nx = c->prob.dims[2] + e;
     std::vector<std::pair<long, size_t>> order(n);
     bool ok = true;
     for (size_t k = 0; k < n; ++k) {
-      const int cell = m[k].idx, x = cell % nx, y = (cell / nx) % ny, z = cell / (nx * ny);
+      const int cell = m[k].idx, x = cell % nx - e, y = (cell / nx) % ny - e, z = cell / (nx * ny) - e;
       const long tile = (((long)m[k].inst * nzt + z / tz) * nty + y / oy) * ntx + x / ox;
       order[k] = {tile * tz + z % tz, k};
       ok = ok && m[k].field < 4;
@@ -289,6 +291,7 @@ int upload_measurements(modil_ctx *c) {
                      });
     const long keys = (long)c->prob.batch * nzt * ntx * nty * tz;
     fptr.assign(keys + 1, 0);
+    const int ce = e;
     for (size_t k = 0; k < n; ++k) {
       const Meas &e = m[order[k].second];
       FusedMeas r{};
@@ -296,8 +299,8 @@ int upload_measurements(modil_ctx *c) {
       r.cell = e.idx;
       r.term = e.term;
       // position in the tile, whose first column and row are a 2-cell halo
-      r.lx = (int16_t)(e.idx % nx % ox + 2);
-      r.ly = (int16_t)(e.idx / nx % ny % oy + 2);
+      r.lx = (int16_t)((e.idx % nx - ce) % ox + 2);
+      r.ly = (int16_t)((e.idx / nx % ny - ce) % oy + 2);
       r.val = e.val;
       r.w = e.w;
       frec.push_back(r);
@@ -370,7 +373,7 @@ bool on_boundary_node(const FieldGeom &g, long idx) {
 
 bool use_fused(const modil_ctx *c) {
   return c->fused_enabled && c->fused_ok && c->prob.op == MODIL_OP_NS3D &&
-         c->prob.centering == MODIL_CELL && c->prob.dtype == MODIL_F32 && ns3d_offsets_fit(c->prob);
+         c->prob.dtype == MODIL_F32 && ns3d_offsets_fit(c->prob);
 }
 
 // Loss terms at theta; with grad the gradient of every level; with adam
@@ -391,6 +394,8 @@ int evaluate(modil_ctx *c, const void *theta, void *grad, double *terms, const A
     {
       Timed t(c, 0);
       HIP_OR_RETURN(c, launch_ns3d_fused(c, theta, grad, adam, th_out, m, v), "fused kernel");
+      if (c->prob.centering == MODIL_NODE)
+        HIP_OR_RETURN(c, launch_node_boundary(c, grad, adam, theta, th_out, m, v), "boundary nodes");
     }
     long blocks, keys;
     fused_geometry(c->prob, blocks, keys);

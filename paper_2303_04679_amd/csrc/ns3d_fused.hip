@@ -135,6 +135,25 @@ __device__ inline void face_add(const NSCoef<T> &K, int axis, T sgi2h, const T (
   g[3] += sgi2h * at[1 + kc] - K.tauh[axis] * at[0];
 }
 
+// Ghost value of field f (u, v, w, p) across face (axis, side) of a cell:
+// b2 + c0 * (the cell's value).  Cell-based: the channel's ghost rules.
+// Node-based (NODE): the boundary node itself, whose value the conditions
+// impose (inlet u = (u_ref, 0, 0), outlet p = 0, zero normal velocity at the
+// walls; c0 = 0) or take from the interior node next to it (c0 = 1).
+template <bool NODE>
+__host__ __device__ inline GhostRule channel_ghost(const OpParams &p, int f, int axis, int side) {
+  if (!NODE) return ns_ghost<3>(p, f, axis, side);
+  bool imposed;
+  double val = 0.0;
+  if (axis == 2) {
+    imposed = side == 0 ? f < 3 : f == 3;
+    if (side == 0 && f == 0) val = p.u_ref;
+  } else {
+    imposed = f == 2 - axis;
+  }
+  return imposed ? GhostRule{val, 0.0, 0.0} : GhostRule{0.0, 1.0, 0.0};
+}
+
 // CHI: 1 fixed chi array, 2 unknown chihat (field 4).  FORCING: some equation
 // has a forcing array (compiled out otherwise: its pointers would hold scalar
 // registers through the plane loop).
@@ -152,7 +171,7 @@ __device__ inline void face_add(const NSCoef<T> &K, int axis, T sgi2h, const T (
 // u_f), the slot holds a_0 -c_k, a_c c_c (k the component normal to the
 // wall) and normal velocity -u_k.  This relies on c_k = -c_p, which the host
 // checks.  Walls in z are uniform over a plane and take a branch.
-template <typename T, int CHI, bool ADAM, bool FORCING, bool ZSUM>
+template <typename T, int CHI, bool ADAM, bool FORCING, bool ZSUM, bool NODE>
 __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel(NS3DArgs<T> A) {
   constexpr int NF = (CHI == 2) ? 5 : 4;  // unknown fields
   constexpr int NA = 5;                   // per cell: seeds a_0, a_c (1 - chi), and u for x faces
@@ -201,8 +220,11 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
   // walls next to a seed cell (its halo slot across the wall is in the tile)
   const bool wxm = seed_xy && x == 0, wxp = seed_xy && x == nx - 1;
   const bool wym = seed_xy && y == 0, wyp = seed_xy && y == ny - 1;
-  const int plane = nx * ny;
-  const int col = y * nx + x;
+  // stored values per row and plane: cells, or the interior nodes and the two
+  // boundary nodes of each axis (NODE)
+  const int sx = NODE ? nx + 2 : nx;
+  const int plane = sx * (NODE ? ny + 2 : ny);
+  const int col = NODE ? (y + 1) * sx + (x + 1) : y * nx + x;
   const NSCoef<T> &K = A.K;
   const T wv = T(p.w_pde * p.V);
   const T *th_base = A.theta + inst * A.th_inst;
@@ -213,7 +235,7 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
   for (int f = 0; f < NF; ++f)
     fo[f] = ((uint32_t)f * (uint32_t)A.fsize + (uint32_t)(in_xy ? col : 0)) * (uint32_t)sizeof(T);
   // byte offset of plane z (uniform); planes before the grid map to plane 0
-  auto pofs = [&](int z) { return (uint32_t)max(z, 0) * plane_b; };
+  auto pofs = [&](int z) { return (uint32_t)(max(z, 0) + (NODE ? 1 : 0)) * plane_b; };
   const T *chi_base = CHI == 1 ? A.chi + inst * A.fsize : nullptr;
 
   // ---- z part of the level-1 restriction (with coarse levels): the owned
@@ -233,8 +255,13 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
   int jx[2] = {0, 0}, jy[2] = {0, 0};
   T wx[2] = {T(0), T(0)}, wy[2] = {T(0), T(0)};
   if (A.has_coarse && in_xy) {
-    prolong_taps(x, A.nc[2], jx, wx);
-    prolong_taps(y, A.nc[1], jy, wy);
+    if (NODE) {
+      prolong_taps_node(x + 1, jx, wx);
+      prolong_taps_node(y + 1, jy, wy);
+    } else {
+      prolong_taps(x, A.nc[2], jx, wx);
+      prolong_taps(y, A.nc[1], jy, wy);
+    }
   }
   T Wlo[NF], Whi[NF];
   for (int f = 0; f < NF; ++f) Wlo[f] = Whi[f] = T(0);
@@ -244,6 +271,7 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
   const int lx[2] = {jx[0] - cxb, jx[1] - cxb}, ly[2] = {jy[0] - cyb, jy[1] - cyb};
   // lower coarse plane of the interpolation of fine plane z (valid z)
   auto kbase = [&](int z) {
+    if (NODE) return min((z + 1) >> 1, A.nc[0] - 2);  // coarse nodes of fine node z + 1
     if (z == 0) return 0;
     if (z == nz - 1) return A.nc[0] - 2;
     return (z & 1) ? z / 2 : z / 2 - 1;
@@ -299,8 +327,8 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
   double part[kTerms] = {0.0, 0.0, 0.0, 0.0, 0.0};
 
   // ghost value of field f across face (axis a, side s) of a cell with value c
-#define GB(f, a, s) T(ns_ghost<3>(p, f, a, s).b2)
-#define GC0(f, a, s) T(ns_ghost<3>(p, f, a, s).c0)
+#define GB(f, a, s) T(channel_ghost<NODE>(p, f, a, s).b2)
+#define GC0(f, a, s) T(channel_ghost<NODE>(p, f, a, s).c0)
 #define GV(f, a, s, c) (GB(f, a, s) + GC0(f, a, s) * (c))
 
   const int key_base = (inst * A.nzt * A.ntx * A.nty + tile) * A.tz;
@@ -358,7 +386,14 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
       if (A.has_coarse) {
         int km;
         T wlo, whi;
-        if (pz == 0) { km = 0; wlo = T(1.25); whi = T(-0.25); }
+        if (NODE) {  // fine node pz + 1: even copies coarse node (pz + 1) / 2, odd averages two
+          const int n = pz + 1;
+          km = kbase(pz);
+          if (n & 1) { wlo = T(0.5); whi = T(0.5); }
+          else if (n / 2 == km) { wlo = T(1); whi = T(0); }
+          else { wlo = T(0); whi = T(1); }
+        }
+        else if (pz == 0) { km = 0; wlo = T(1.25); whi = T(-0.25); }
         else if (pz == nz - 1) { km = A.nc[0] - 2; wlo = T(-0.25); whi = T(1.25); }
         else if ((pz & 1) == 0) { km = pz / 2 - 1; wlo = T(0.25); whi = T(0.75); }
         else { km = pz / 2; wlo = T(0.75); whi = T(0.25); }
@@ -431,9 +466,13 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
 #define NS_WALL_SLOT(cond, axis, side, SY, SX)                                              \
       if (cond) {                                                                           \
         const int k = 2 - (axis);                                                           \
-        Al[sb][0][SY][SX] = -GC0(k, axis, side) * an[0];                                    \
-        for (int c = 0; c < 3; ++c) Al[sb][1 + c][SY][SX] = GC0(c, axis, side) * an[1 + c]; \
-        if ((axis) == 2) Al[sb][4][SY][SX] = -uc[0];                                        \
+        if (NODE) {                                                                         \
+          for (int e = 0; e < 5; ++e) Al[sb][e][SY][SX] = T(0);                             \
+        } else {                                                                            \
+          Al[sb][0][SY][SX] = -GC0(k, axis, side) * an[0];                                  \
+          for (int c = 0; c < 3; ++c) Al[sb][1 + c][SY][SX] = GC0(c, axis, side) * an[1 + c]; \
+          if ((axis) == 2) Al[sb][4][SY][SX] = -uc[0];                                      \
+        }                                                                                   \
       }
       NS_WALL_SLOT(wxm, 2, 0, Y, X - 1)
       NS_WALL_SLOT(wxp, 2, 1, Y, X + 1)
@@ -508,6 +547,21 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
       NS_XY_FACE(2, T(1), Y, X - 1, Al[qb][4][Y][X - 1])
       NS_XY_FACE(2, T(-1), Y, X + 1, Al[qb][4][Y][X + 1])
 #undef NS_XY_FACE
+      if (NODE) {
+        // the cell's own residuals read the boundary node across an x or y
+        // wall, whose value is imposed or the cell's own (ghost = b + c u)
+#define NS_NODE_WALL(cond, axis, side, sgn, UK)                                       \
+        if (cond) {                                                                 \
+          T fs[4] = {T(0), T(0), T(0), T(0)};                                       \
+          face_add(K, axis, (sgn) * K.i2h[axis], A1, UK, fs);                       \
+          for (int f = 0; f < 4; ++f) g[f] += GC0(f, axis, side) * fs[f];           \
+        }
+        NS_NODE_WALL(x == 0, 2, 0, T(-1), U1[0])
+        NS_NODE_WALL(x == nx - 1, 2, 1, T(1), U1[0])
+        NS_NODE_WALL(y == 0, 1, 0, T(-1), U1[1])
+        NS_NODE_WALL(y == ny - 1, 1, 1, T(1), U1[1])
+#undef NS_NODE_WALL
+      }
       T gg[5];
       for (int f = 0; f < 4; ++f) gg[f] = g[f] + Dl[qb][f][Y][X];
       gg[4] = Cq[4];
@@ -572,8 +626,15 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
 }
 
 // ------------------------------------------------------------------ host side
+// the grid the fused kernel marches over: the cells, or the interior nodes
+static void fused_grid(const modil_problem &P, int (&n)[3]) {
+  for (int a = 0; a < 3; ++a) n[a] = P.dims[a] - (P.centering == MODIL_NODE ? 1 : 0);
+}
+
 void ns3d_tiles(const modil_problem &P, int &tz, int &nzt, int &ntx, int &nty, int &ox, int &oy) {
-  const int nz = P.dims[0], ny = P.dims[1], nx = P.dims[2];
+  int n[3];
+  fused_grid(P, n);
+  const int nz = n[0], ny = n[1], nx = n[2];
   ntx = (nx + NSO_X - 1) / NSO_X;
   nty = (ny + NSO_Y - 1) / NSO_Y;
   // z-chunk: the longest of 16, 8, 4, 2 planes that still gives every compute
@@ -588,7 +649,8 @@ void ns3d_tiles(const modil_problem &P, int &tz, int &nzt, int &ntx, int &nty, i
 }
 
 bool ns3d_offsets_fit(const modil_problem &P) {
-  const unsigned long long cells = (unsigned long long)P.dims[0] * P.dims[1] * P.dims[2];
+  const unsigned long long e = P.centering == MODIL_NODE ? 1 : 0;
+  const unsigned long long cells = (P.dims[0] + e) * (P.dims[1] + e) * (P.dims[2] + e);
   const unsigned long long ts = P.dtype == MODIL_F64 ? 8 : 4;
   return 5ull * cells * ts < (1ull << 32);  // fields of level 0; level 1 is smaller
 }
@@ -600,10 +662,9 @@ static hipError_t fused_t(modil_ctx *c, const void *theta, void *g, const AdamHo
   NS3DArgs<T> A{};
   OpParams &p = A.p;
   p.ndim = 3;
-  for (int a = 0; a < 3; ++a) {
-    p.n[a] = P.dims[a];
-    p.h[a] = P.lengths[a] / P.dims[a];
-  }
+  const bool node = P.centering == MODIL_NODE;
+  fused_grid(P, p.n);
+  for (int a = 0; a < 3; ++a) p.h[a] = P.lengths[a] / P.dims[a];
   p.V = p.h[0] * p.h[1] * p.h[2];
   p.w_pde = P.w_pde; p.w_reg = P.w_reg; p.w_bc = P.w_bc;
   p.re = P.re; p.diam = P.diam; p.lam = P.lambda_; p.chi_shift = P.chi_shift;
@@ -612,7 +673,7 @@ static hipError_t fused_t(modil_ctx *c, const void *theta, void *g, const AdamHo
   // the kernel's wall slots rely on two properties of the x and y wall rules:
   // the normal velocity's ghost coefficient is minus the pressure's, and the
   // normal velocity at a y wall is mirrored (ghost -v)
-  for (int side = 0; side < 2; ++side) {
+  for (int side = 0; side < 2 && !node; ++side) {
     for (int axis = 1; axis <= 2; ++axis)
       if (ns_ghost<3>(p, 2 - axis, axis, side).c0 != -ns_ghost<3>(p, 3, axis, side).c0)
         return hipErrorInvalidValue;
@@ -636,7 +697,7 @@ static hipError_t fused_t(modil_ctx *c, const void *theta, void *g, const AdamHo
   A.th_inst = (int)c->lay.level_stride[0];
   A.theta = (const T *)theta;
   if (A.has_coarse) {
-    for (int a = 0; a < 3; ++a) A.nc[a] = P.dims[a] / 2;
+    for (int a = 0; a < 3; ++a) A.nc[a] = P.dims[a] / 2 + (node ? 1 : 0);  // cells or nodes
     A.ncz = A.nc[0];
     A.ncy = A.nc[1];
     A.ncx = A.nc[2];
@@ -666,12 +727,15 @@ static hipError_t fused_t(modil_ctx *c, const void *theta, void *g, const AdamHo
   const bool zsum = A.has_coarse && (P.flags & MODIL_FLAG_FUSED_RESTRICT) != 0;
   auto pick = [&](auto chi_tag) {
     constexpr int C = decltype(chi_tag)::value;
-    if (zsum) {
-      if (ad) forcing ? go(ns3d_fused_kernel<T, C, true, true, true>) : go(ns3d_fused_kernel<T, C, true, false, true>);
-      else forcing ? go(ns3d_fused_kernel<T, C, false, true, true>) : go(ns3d_fused_kernel<T, C, false, false, true>);
+    if (node) {
+      if (ad) forcing ? go(ns3d_fused_kernel<T, C, true, true, false, true>) : go(ns3d_fused_kernel<T, C, true, false, false, true>);
+      else forcing ? go(ns3d_fused_kernel<T, C, false, true, false, true>) : go(ns3d_fused_kernel<T, C, false, false, false, true>);
+    } else if (zsum) {
+      if (ad) forcing ? go(ns3d_fused_kernel<T, C, true, true, true, false>) : go(ns3d_fused_kernel<T, C, true, false, true, false>);
+      else forcing ? go(ns3d_fused_kernel<T, C, false, true, true, false>) : go(ns3d_fused_kernel<T, C, false, false, true, false>);
     } else {
-      if (ad) forcing ? go(ns3d_fused_kernel<T, C, true, true, false>) : go(ns3d_fused_kernel<T, C, true, false, false>);
-      else forcing ? go(ns3d_fused_kernel<T, C, false, true, false>) : go(ns3d_fused_kernel<T, C, false, false, false>);
+      if (ad) forcing ? go(ns3d_fused_kernel<T, C, true, true, false, false>) : go(ns3d_fused_kernel<T, C, true, false, false, false>);
+      else forcing ? go(ns3d_fused_kernel<T, C, false, true, false, false>) : go(ns3d_fused_kernel<T, C, false, false, false, false>);
     }
   };
   if (fixed) pick(std::integral_constant<int, 1>{});
@@ -813,6 +877,60 @@ hipError_t launch_fused_assemble(modil_ctx *c, void *g, const AdamHost *ad, cons
   if (grid.x > 65535 || grid.y > 65535 || grid.z > 65535) return hipErrorInvalidConfiguration;
   if (ad) fused_assemble_kernel<float, true><<<grid, block, 0, c->stream>>>(A);
   else fused_assemble_kernel<float, false><<<grid, block, 0, c->stream>>>(A);
+  return hipGetLastError();
+}
+
+// Boundary nodes of the finest level (node-based channel flow): they carry
+// no equation and the loss does not read their values, so their gradient is
+// zero: g = 0 there (the restriction reads it) and, with Adam, the Adam update
+// with a zero gradient (as the generic engine's Adam sweep gives them).  One thread per boundary node
+// of one field of one instance: the planes z = 0 and z = nz, then the rows
+// y = 0 and y = ny of the planes between, then the columns x = 0 and x = nx
+// of the rest (n: nodes per axis).
+template <typename T, bool ADAM>
+__global__ __launch_bounds__(256) void node_boundary_kernel(int nz, int ny, int nx, int nf, int fsize,
+                                                            int th_inst, T *g, AdamArgs<T> A) {
+  const int per = 2 * ny * nx + 2 * (nz - 2) * nx + 2 * (nz - 2) * (ny - 2);
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= per) return;
+  const int fi = blockIdx.y, f = fi % nf, inst = fi / nf;
+  int z, y, x;
+  if (e < 2 * ny * nx) {
+    const int k = e / (ny * nx), r = e - k * ny * nx;
+    z = k ? nz - 1 : 0; y = r / nx; x = r - y * nx;
+  } else if (e < 2 * ny * nx + 2 * (nz - 2) * nx) {
+    const int r = e - 2 * ny * nx, k = r / ((nz - 2) * nx), t = r - k * (nz - 2) * nx;
+    z = 1 + t / nx; y = k ? ny - 1 : 0; x = t - (z - 1) * nx;
+  } else {
+    const int r = e - 2 * ny * nx - 2 * (nz - 2) * nx, k = r / ((nz - 2) * (ny - 2));
+    const int t = r - k * (nz - 2) * (ny - 2);
+    z = 1 + t / (ny - 2); y = 1 + t - (z - 1) * (ny - 2); x = k ? nx - 1 : 0;
+  }
+  const long at = (long)inst * th_inst + (long)f * fsize + ((long)z * ny + y) * nx + x;
+  g[at] = T(0);
+  if (!ADAM) return;
+  const T mm = A.b1 * A.m[at], vv = A.b2 * A.v[at];
+  A.m[at] = mm;
+  A.v[at] = vv;
+  A.th_out[at] = adam_theta(A.th_in[at], mm, vv, A.step, A.isb2, A.eps);
+}
+
+hipError_t launch_node_boundary(modil_ctx *c, void *g, const AdamHost *ad, const void *th_in,
+                                void *th_out, void *m, void *v) {
+  const modil_problem &P = c->prob;
+  if (P.dtype != MODIL_F32 || P.centering != MODIL_NODE) return hipErrorInvalidValue;
+  const int nz = P.dims[0] + 1, ny = P.dims[1] + 1, nx = P.dims[2] + 1;
+  const int per = 2 * ny * nx + 2 * (nz - 2) * nx + 2 * (nz - 2) * (ny - 2);
+  AdamArgs<float> A{};
+  if (ad) {
+    A.th_in = (const float *)th_in; A.th_out = (float *)th_out; A.m = (float *)m; A.v = (float *)v;
+    A.b1 = float(ad->b1); A.b2 = float(ad->b2); A.step = float(ad->step);
+    A.isb2 = float(ad->isb2); A.eps = float(ad->eps);
+  }
+  const dim3 grid((unsigned)((per + 255) / 256), (unsigned)(c->lay.n_fields * P.batch));
+  const int fsize = (int)c->lay.fine_cells, th_inst = (int)c->lay.level_stride[0];
+  if (ad) node_boundary_kernel<float, true><<<grid, 256, 0, c->stream>>>(nz, ny, nx, c->lay.n_fields, fsize, th_inst, (float *)g, A);
+  else node_boundary_kernel<float, false><<<grid, 256, 0, c->stream>>>(nz, ny, nx, c->lay.n_fields, fsize, th_inst, (float *)g, A);
   return hipGetLastError();
 }
 

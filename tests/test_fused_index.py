@@ -157,3 +157,54 @@ def test_measurement_positions_in_tile():
         lx = idx % nx % NSO_X + 2
         ly = idx // nx % ny % NSO_Y + 2
         assert np.all((lx >= 2) & (lx < NST_X - 2) & (ly >= 2) & (ly < NST_Y - 2))
+
+
+NODE_CASES = [((16, 16, 24), 1, 3), ((8, 12, 20), 1, 2), ((8, 16, 24), 1, 3), ((16, 16, 32), 1, 3),
+              ((64, 64, 128), 1, 6), ((32, 32, 64), 1, 4), ((8, 8, 16), 1, 3)]
+
+
+@pytest.mark.parametrize("dims,batch,L", NODE_CASES)
+def test_fused_kernel_indices_node(dims, batch, L):
+    """Node-based values: the kernel marches over the interior nodes (cells
+    = nodes 1 .. N - 1 per axis); fields are stored with the boundary nodes
+    (N + 1 per axis); the level-1 window holds the coarse nodes of the node
+    taps (even fine node: one coarse node, odd: the two around it)."""
+    nf = 5
+    nz, ny, nx = (d - 1 for d in dims)            # interior nodes
+    tz, nzt, ntx, nty = tiles(nz, ny, nx, batch)
+    tid, X, Y, active = threads()
+    sx, sy, sz = nx + 2, ny + 2, nz + 2
+    fsize, plane = sx * sy * sz, sx * sy
+    owned = np.zeros(nzt * plane, np.int64)
+    for t in range(nzt * ntx * nty):
+        bx, by, bz = t % ntx, (t // ntx) % nty, t // (ntx * nty)
+        ox, oy = bx * NSO_X - 2, by * NSO_Y - 2
+        x, y = ox + X, oy + Y
+        z0, z1 = bz * tz, min(bz * tz + tz, nz)
+        in_xy = active & (x >= 0) & (x < nx) & (y >= 0) & (y < ny)
+        own = in_xy & (X >= 2) & (X <= NST_X - 3) & (Y >= 2) & (Y <= NST_Y - 3)
+        col = (y + 1) * sx + (x + 1)
+        np.add.at(owned, bz * plane + col[own], 1)
+        planes = [z for z in range(z0 - 2, z1 + 2) if 0 <= z < nz]
+        fo = ((nf - 1) * fsize + np.where(in_xy, col, 0)) * 4
+        assert np.all(fo + (max(planes) + 1) * plane * 4 < nf * fsize * 4)
+        if L > 1:
+            nc = tuple(d // 2 + 1 for d in dims)   # coarse nodes per axis
+            cxb, cyb = (ox >> 1) - 1, (oy >> 1) - 1
+            for v, cb, w, n in ((x[in_xy] + 1, cxb, NCT_X, nc[2]), (y[in_xy] + 1, cyb, NCT_Y, nc[1])):
+                for J in (v >> 1, (v >> 1) + (v & 1)):
+                    assert np.all((J - cb >= 0) & (J - cb < w))
+                    assert np.all((J >= 0) & (J < n))
+            zs = np.array(planes)
+            kb = np.minimum((zs + 1) >> 1, nc[0] - 2)
+            assert np.all((kb >= 0) & (kb + 1 < nc[0]))
+            # the coarse planes of each fine node plane are the resident pair
+            n = zs + 1
+            assert np.all(((n & 1) == 1) | (n // 2 == kb) | (n // 2 == kb + 1))
+            assert np.all(((n & 1) == 0) | ((n >> 1) == kb))
+    # every interior node of every chunk owned once, no boundary node owned
+    inner = np.zeros((sy, sx), bool)
+    inner[1:-1, 1:-1] = True
+    for bz in range(nzt):
+        got = owned[bz * plane:(bz + 1) * plane].reshape(sy, sx)
+        assert np.all(got[inner] == 1) and np.all(got[~inner] == 0)
