@@ -394,8 +394,6 @@ int evaluate(modil_ctx *c, const void *theta, void *grad, double *terms, const A
     {
       Timed t(c, 0);
       HIP_OR_RETURN(c, launch_ns3d_fused(c, theta, grad, adam, th_out, m, v), "fused kernel");
-      if (c->prob.centering == MODIL_NODE)
-        HIP_OR_RETURN(c, launch_node_boundary(c, grad, adam, theta, th_out, m, v), "boundary nodes");
     }
     long blocks, keys;
     fused_geometry(c->prob, blocks, keys);

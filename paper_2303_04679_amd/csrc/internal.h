@@ -351,9 +351,6 @@ hipError_t launch_reduce(modil_ctx *c, double *terms, long n_a, long off_b, long
 hipError_t launch_ns3d_fused(modil_ctx *c, const void *theta, void *g, const AdamHost *adam,
                              void *th_out, void *m, void *v);
 void ns3d_tiles(const modil_problem &P, int &tz, int &nzt, int &ntx, int &nty, int &ox, int &oy);
-// node-based channel flow: zero gradient (and Adam with it) on the finest level's boundary nodes
-hipError_t launch_node_boundary(modil_ctx *c, void *g, const AdamHost *adam, const void *th_in,
-                                void *th_out, void *m, void *v);
 // bytes of the fused kernel's level-1 gradient partials (0 where it has none)
 size_t fused_partial_bytes(const modil_problem &P);
 // level 1 of the gradient from those partials (and, with adam, Adam on level 1)

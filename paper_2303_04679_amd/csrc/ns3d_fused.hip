@@ -609,6 +609,60 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
 #undef GV
 #undef GC0
 #undef GB
+  // ---- node-based: the boundary nodes of this block's region carry no
+  // equation and get a zero gradient (and, with Adam, the Adam update with
+  // it).  The region in node coordinates: the nodes of its owned interior
+  // cells, plus the boundary nodes beyond them where the tile or chunk ends
+  // at the grid's boundary, so every boundary node belongs to one block.
+  if (NODE) {
+    const int Nx = nx + 1, Ny = ny + 1, Nz = nz + 1;  // last node index per axis
+    const int lo[3] = {bz == 0 ? 0 : z0 + 1, by == 0 ? 0 : by * NSO_Y + 1, bx == 0 ? 0 : bx * NSO_X + 1};
+    const int hi[3] = {bz == A.nzt - 1 ? Nz : z1, by == A.nty - 1 ? Ny : min(by * NSO_Y + NSO_Y, ny),
+                       bx == A.ntx - 1 ? Nx : min(bx * NSO_X + NSO_X, nx)};
+    const int last[3] = {Nz, Ny, Nx};
+    const int ext[3] = {hi[0] - lo[0] + 1, hi[1] - lo[1] + 1, hi[2] - lo[2] + 1};
+    const int base = inst * A.th_inst;
+    // faces of the region on the grid's boundary; a node on several faces is
+    // taken by the first of them (axis order z, y, x; low side first)
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int side = 0; side < 2; ++side) {
+        const int fixed = side ? last[a] : 0;
+        if ((side ? hi[a] : lo[a]) != fixed) continue;
+        const int b1 = (a + 1) % 3, b2 = (a + 2) % 3;
+        const int n = ext[b1] * ext[b2];
+        for (int e = tid; e < n; e += NS_THREADS) {
+          int c[3];
+          c[a] = fixed;
+          c[b1] = lo[b1] + e / ext[b2];
+          c[b2] = lo[b2] + e % ext[b2];
+          bool earlier = false;  // on a face handled before this one
+#pragma unroll
+          for (int a2 = 0; a2 < a; ++a2) earlier = earlier || c[a2] == 0 || c[a2] == last[a2];
+          if (earlier) continue;
+          const uint32_t off = (uint32_t)(((c[0] * (ny + 2) + c[1]) * (nx + 2)) + c[2]) * (uint32_t)sizeof(T);
+          const uint32_t fb = (uint32_t)A.fsize * (uint32_t)sizeof(T);
+          T mo[NF], vo[NF], to[NF];  // every load issued before the first use
+          if (ADAM)
+            for (int f = 0; f < NF; ++f) {
+              mo[f] = ld_at(A.adam.m + base, off + f * fb);
+              vo[f] = ld_at(A.adam.v + base, off + f * fb);
+              to[f] = ld_at(th_base, off + f * fb);
+            }
+          for (int f = 0; f < NF; ++f) {
+            const uint32_t o = off + f * fb;
+            st_at(A.g + base, o, T(0));
+            if (ADAM) {
+              const T mm = A.adam.b1 * mo[f], vv = A.adam.b2 * vo[f];
+              st_at(A.adam.m + base, o, mm);
+              st_at(A.adam.v + base, o, vv);
+              st_at(A.adam.th_out + base, o, adam_theta(to[f], mm, vv, A.adam.step, A.adam.isb2, A.adam.eps));
+            }
+          }
+        }
+      }
+  }
   // ---- block sum of the loss partials (fixed order)
   for (int k = 0; k < kTerms; ++k) {
     double v = part[k];
@@ -877,60 +931,6 @@ hipError_t launch_fused_assemble(modil_ctx *c, void *g, const AdamHost *ad, cons
   if (grid.x > 65535 || grid.y > 65535 || grid.z > 65535) return hipErrorInvalidConfiguration;
   if (ad) fused_assemble_kernel<float, true><<<grid, block, 0, c->stream>>>(A);
   else fused_assemble_kernel<float, false><<<grid, block, 0, c->stream>>>(A);
-  return hipGetLastError();
-}
-
-// Boundary nodes of the finest level (node-based channel flow): they carry
-// no equation and the loss does not read their values, so their gradient is
-// zero: g = 0 there (the restriction reads it) and, with Adam, the Adam update
-// with a zero gradient (as the generic engine's Adam sweep gives them).  One thread per boundary node
-// of one field of one instance: the planes z = 0 and z = nz, then the rows
-// y = 0 and y = ny of the planes between, then the columns x = 0 and x = nx
-// of the rest (n: nodes per axis).
-template <typename T, bool ADAM>
-__global__ __launch_bounds__(256) void node_boundary_kernel(int nz, int ny, int nx, int nf, int fsize,
-                                                            int th_inst, T *g, AdamArgs<T> A) {
-  const int per = 2 * ny * nx + 2 * (nz - 2) * nx + 2 * (nz - 2) * (ny - 2);
-  const int e = blockIdx.x * 256 + threadIdx.x;
-  if (e >= per) return;
-  const int fi = blockIdx.y, f = fi % nf, inst = fi / nf;
-  int z, y, x;
-  if (e < 2 * ny * nx) {
-    const int k = e / (ny * nx), r = e - k * ny * nx;
-    z = k ? nz - 1 : 0; y = r / nx; x = r - y * nx;
-  } else if (e < 2 * ny * nx + 2 * (nz - 2) * nx) {
-    const int r = e - 2 * ny * nx, k = r / ((nz - 2) * nx), t = r - k * (nz - 2) * nx;
-    z = 1 + t / nx; y = k ? ny - 1 : 0; x = t - (z - 1) * nx;
-  } else {
-    const int r = e - 2 * ny * nx - 2 * (nz - 2) * nx, k = r / ((nz - 2) * (ny - 2));
-    const int t = r - k * (nz - 2) * (ny - 2);
-    z = 1 + t / (ny - 2); y = 1 + t - (z - 1) * (ny - 2); x = k ? nx - 1 : 0;
-  }
-  const long at = (long)inst * th_inst + (long)f * fsize + ((long)z * ny + y) * nx + x;
-  g[at] = T(0);
-  if (!ADAM) return;
-  const T mm = A.b1 * A.m[at], vv = A.b2 * A.v[at];
-  A.m[at] = mm;
-  A.v[at] = vv;
-  A.th_out[at] = adam_theta(A.th_in[at], mm, vv, A.step, A.isb2, A.eps);
-}
-
-hipError_t launch_node_boundary(modil_ctx *c, void *g, const AdamHost *ad, const void *th_in,
-                                void *th_out, void *m, void *v) {
-  const modil_problem &P = c->prob;
-  if (P.dtype != MODIL_F32 || P.centering != MODIL_NODE) return hipErrorInvalidValue;
-  const int nz = P.dims[0] + 1, ny = P.dims[1] + 1, nx = P.dims[2] + 1;
-  const int per = 2 * ny * nx + 2 * (nz - 2) * nx + 2 * (nz - 2) * (ny - 2);
-  AdamArgs<float> A{};
-  if (ad) {
-    A.th_in = (const float *)th_in; A.th_out = (float *)th_out; A.m = (float *)m; A.v = (float *)v;
-    A.b1 = float(ad->b1); A.b2 = float(ad->b2); A.step = float(ad->step);
-    A.isb2 = float(ad->isb2); A.eps = float(ad->eps);
-  }
-  const dim3 grid((unsigned)((per + 255) / 256), (unsigned)(c->lay.n_fields * P.batch));
-  const int fsize = (int)c->lay.fine_cells, th_inst = (int)c->lay.level_stride[0];
-  if (ad) node_boundary_kernel<float, true><<<grid, 256, 0, c->stream>>>(nz, ny, nx, c->lay.n_fields, fsize, th_inst, (float *)g, A);
-  else node_boundary_kernel<float, false><<<grid, 256, 0, c->stream>>>(nz, ny, nx, c->lay.n_fields, fsize, th_inst, (float *)g, A);
   return hipGetLastError();
 }
 

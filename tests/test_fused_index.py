@@ -208,3 +208,38 @@ def test_fused_kernel_indices_node(dims, batch, L):
     for bz in range(nzt):
         got = owned[bz * plane:(bz + 1) * plane].reshape(sy, sx)
         assert np.all(got[inner] == 1) and np.all(got[~inner] == 0)
+
+
+@pytest.mark.parametrize("dims,batch,L", NODE_CASES)
+def test_node_boundary_regions(dims, batch, L):
+    """Node-based: the blocks' regions (their owned interior nodes plus the
+    boundary nodes beyond them at the grid's ends) partition the node grid,
+    and the faces each block walks (first face wins at edges and corners)
+    give every boundary node exactly once and no interior node."""
+    nz, ny, nx = (d - 1 for d in dims)
+    tz, nzt, ntx, nty = tiles(nz, ny, nx, batch)
+    last = (nz + 1, ny + 1, nx + 1)
+    count = np.zeros(tuple(v + 1 for v in last), np.int64)
+    for t in range(nzt * ntx * nty):
+        bx, by, bz = t % ntx, (t // ntx) % nty, t // (ntx * nty)
+        z0, z1 = bz * tz, min(bz * tz + tz, nz)
+        lo = (0 if bz == 0 else z0 + 1, 0 if by == 0 else by * NSO_Y + 1, 0 if bx == 0 else bx * NSO_X + 1)
+        hi = (last[0] if bz == nzt - 1 else z1, last[1] if by == nty - 1 else min(by * NSO_Y + NSO_Y, ny),
+              last[2] if bx == ntx - 1 else min(bx * NSO_X + NSO_X, nx))
+        for a in range(3):
+            for side in range(2):
+                fixed = last[a] if side else 0
+                if (hi[a] if side else lo[a]) != fixed:
+                    continue
+                b1, b2 = (a + 1) % 3, (a + 2) % 3
+                for e in range((hi[b1] - lo[b1] + 1) * (hi[b2] - lo[b2] + 1)):
+                    c = [0, 0, 0]
+                    c[a] = fixed
+                    c[b1] = lo[b1] + e // (hi[b2] - lo[b2] + 1)
+                    c[b2] = lo[b2] + e % (hi[b2] - lo[b2] + 1)
+                    if any(c[a2] in (0, last[a2]) for a2 in range(a)):
+                        continue
+                    count[tuple(c)] += 1
+    boundary = np.ones(count.shape, bool)
+    boundary[1:-1, 1:-1, 1:-1] = False
+    assert np.all(count[boundary] == 1) and np.all(count[~boundary] == 0)
