@@ -308,9 +308,10 @@ int modil_prolong_noalloc(const modil_problem *problem, const void *theta_pack, 
  * (one coarse cell per thread writing its 2^d fine cells); 0 selects the
  * per-cell kernels.  Same results up to the order of the sums.
  * MODIL_OPT_MARCH_TILE (default 0 = automatic): coarse rows and planes per
- * wave of the marching kernel as 16 * rows + planes; rows 2 or 4, planes 1, 2
- * or 4 (8 with 4 rows).  A tile that does not divide a level's grid leaves
- * that level to the gather kernel.                                        */
+ * wave of the marching kernel as 64 * rows + planes: rows 2 with planes 1,
+ * 2, 4 or 8; rows 4 with planes 1, 2, 4, 8 or 16; rows 8 with planes 4 or 8.
+ * A tile that does not divide a level's grid leaves that level to the
+ * gather kernel.                                                          */
 #define MODIL_OPT_MARCH 1
 #define MODIL_OPT_MARCH_TILE 2
 /* MODIL_OPT_TAIL (default 1): the small coarse levels of each instance (from

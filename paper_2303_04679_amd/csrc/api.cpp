@@ -919,10 +919,11 @@ int modil_set_option(modil_ctx *c, int32_t option, int64_t value) {
     return MODIL_OK;
   }
   if (option == MODIL_OPT_MARCH_TILE) {
-    const int yr = (int)(value >> 4), zr = (int)(value & 15);
-    const bool ok = value == 0 || ((yr == 2 || yr == 4) && (zr == 1 || zr == 2 || zr == 4 ||
-                                                             (yr == 4 && zr == 8)));
-    if (!ok || value < 0 || value > 255) return fail(c, MODIL_ERR_INVALID_ARG, "unsupported tile");
+    const int yr = (int)(value >> 6), zr = (int)(value & 63);
+    const bool ok = value == 0 || (yr == 2 && (zr == 1 || zr == 2 || zr == 4 || zr == 8)) ||
+                    (yr == 4 && (zr == 1 || zr == 2 || zr == 4 || zr == 8 || zr == 16)) ||
+                    (yr == 8 && (zr == 4 || zr == 8));
+    if (!ok || value < 0 || value > 1023) return fail(c, MODIL_ERR_INVALID_ARG, "unsupported tile");
     c->march_tile = (int)value;
     return MODIL_OK;
   }

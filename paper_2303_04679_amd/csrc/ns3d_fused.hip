@@ -21,6 +21,16 @@
 // two fine planes.  Blocks are mapped to tiles so that every XCD works on one
 // contiguous slab of z-chunks and neighbouring tiles share its L2.
 //
+// Node-based values (Section 2.2; NODE): the kernel marches over the
+// interior nodes as its cells, with the boundary nodes as the halo slots
+// across the walls: their values are imposed or copied from the interior
+// node next to them (the node rules of the channel), so the ghost adjoint at
+// an x or y wall is added explicitly to the cell next to it.  The boundary
+// nodes carry no equation: each block gives those beyond its region a zero
+// gradient (and Adam with it) in its epilogue.  The opt-in z-sum form (ZSUM)
+// sums the finest gradient over the fine planes of each coarse plane instead
+// of writing it; an assembly kernel finishes T^T in y and x.
+//
 // The kernel is built for FP32 fields (FP64 loss partials).  An FP64 build
 // needs more registers than the 768-thread block allows and spills heavily;
 // FP64 problems run on the generic engine.

@@ -38,40 +38,75 @@ struct MarchPlan {
   int n_tasks;    // waves with work
 };
 
-// One fine row of a plane: the lane's two cells and, with SEG, the cells
-// just outside the lane's 64-wide segment (edge lanes only; others reload
-// their own cells, which stay in the same cache line).
+// One fine row of a plane: the lane's two cells and, with SEG, the cell just
+// outside the lane's 64-wide segment (the first lane takes the one to its
+// left, the last lane the one to its right; the others reload their own
+// cell, in the same cache line).
 template <typename T, bool SEG>
 struct RowLoad {
-  T a, b, lo, hi;
+  T a, b, e;
 };
 
+// Loads address a wave-uniform base plus a 32-bit byte offset per lane.
+template <typename T>
+__device__ inline T ld_off(const T *base, uint32_t byte_off) {
+  return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+template <typename T>
+__device__ inline void st_off(T *base, uint32_t byte_off, T v) {
+  *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off) = v;
+}
+
 template <typename T, bool SEG>
-__device__ inline RowLoad<T, SEG> load_row(const T *__restrict__ r, int cx, int lo_off, int hi_off) {
+__device__ inline RowLoad<T, SEG> load_row(const T *base, uint32_t off, uint32_t eoff) {
   using P2 = typename Pair<T>::type;
   RowLoad<T, SEG> v;
-  const P2 ab = *reinterpret_cast<const P2 *>(r + 2 * cx);
+  const P2 ab = ld_off(reinterpret_cast<const P2 *>(base), off);
   v.a = ab.x;
   v.b = ab.y;
-  if (SEG) {
-    v.lo = r[lo_off];
-    v.hi = r[hi_off];
-  } else {
-    v.lo = v.hi = T(0);
-  }
+  v.e = SEG ? ld_off(base, eoff) : T(0);
   return v;
 }
 
-// Column value (T^T along x) of one row: every lane executes the shuffles.
+// The value of the lane below (wave_prev: lane i gets lane i - 1) or above
+// (wave_next: lane i gets lane i + 1) by a DPP wave shift, an operand
+// modifier of a VALU move with no LDS round trip.  The first (last) lane
+// keeps its own value; callers never use it there.  Every lane of the wave
+// must be active.
+__device__ inline uint32_t dpp_prev(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x138, 0xf, 0xf, false);  // wave_shr:1
+}
+__device__ inline uint32_t dpp_next(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x130, 0xf, 0xf, false);  // wave_shl:1
+}
+__device__ inline float wave_prev(float v) { return __uint_as_float(dpp_prev(__float_as_uint(v))); }
+__device__ inline float wave_next(float v) { return __uint_as_float(dpp_next(__float_as_uint(v))); }
+__device__ inline double wave_prev(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned long long r = (unsigned long long)dpp_prev((uint32_t)u) |
+                               ((unsigned long long)dpp_prev((uint32_t)(u >> 32)) << 32);
+  return __longlong_as_double((long long)r);
+}
+__device__ inline double wave_next(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned long long r = (unsigned long long)dpp_next((uint32_t)u) |
+                               ((unsigned long long)dpp_next((uint32_t)(u >> 32)) << 32);
+  return __longlong_as_double((long long)r);
+}
+
+// Column value (T^T along x) of one row: every lane executes the shifts.  A
+// row group of W < 64 lanes takes its neighbours from within the group: the
+// lanes whose shifted value would come from the next group (its first and
+// last lane) do not use it.
 template <typename T, bool SEG>
 __device__ inline T x_restrict(const RowLoad<T, SEG> &v, int W, int gl, int cx, int cnx) {
-  T left = __shfl_up(v.b, 1, W);    // fine 2J-1
-  T right = __shfl_down(v.a, 1, W);  // fine 2J+2
-  const T e0 = __shfl_up(v.a, 1, W);    // fine 0, for J = 1
-  const T e1 = __shfl_down(v.b, 1, W);  // fine 2n-1, for J = n-2
+  T left = wave_prev(v.b);     // fine 2J-1
+  T right = wave_next(v.a);    // fine 2J+2
+  const T e0 = wave_prev(v.a);  // fine 0, for J = 1
+  const T e1 = wave_next(v.b);  // fine 2n-1, for J = n-2
   if (SEG) {
-    if (gl == 0) left = v.lo;
-    if (gl == W - 1) right = v.hi;
+    if (gl == 0) left = v.e;
+    if (gl == W - 1) right = v.e;
   }
   T x = (cx == 0 ? T(1.25) : T(0.75)) * v.a + (cx == cnx - 1 ? T(1.25) : T(0.75)) * v.b;
   if (cx > 0) x += T(0.25) * left;
@@ -132,42 +167,55 @@ __device__ inline void y_restrict(const RowLoad<T, SEG> (&rows)[2 * YR + 2], int
   }
 }
 
+// The rows of one fine plane: pb is the field's base (wave-uniform), zoff the
+// plane's byte offset, loff the lane's pair offset within a row, eoff - loff
+// the lane's edge cell relative to its pair.
 template <typename T, int YR, bool SEG>
-__device__ inline void load_plane(const T *__restrict__ pb, int nx, int Y0, int ny, int cx,
-                                  int lo_off, int hi_off, RowLoad<T, SEG> (&rows)[2 * YR + 2]) {
+__device__ inline void load_plane(const T *pb, uint32_t zoff, uint32_t rowb, int Y0, int ny,
+                                  uint32_t loff, uint32_t edelta, RowLoad<T, SEG> (&rows)[2 * YR + 2]) {
 #pragma unroll
-  for (int k = 0; k < 2 * YR + 2; ++k)
-    rows[k] = load_row<T, SEG>(pb + (long)row_of<YR>(k, Y0, ny) * nx, cx, lo_off, hi_off);
+  for (int k = 0; k < 2 * YR + 2; ++k) {
+    const uint32_t off = zoff + (uint32_t)row_of<YR>(k, Y0, ny) * rowb + loff;
+    rows[k] = load_row<T, SEG>(pb, off, off + edelta);
+  }
 }
 
+// Coarse-level arrays of one field of one instance (wave-uniform bases).
+template <typename T>
+struct CoarseBase {
+  T *g;
+  const T *th_in;
+  T *th_out, *m, *v;
+};
+
 template <typename T, int YR, bool ADAM>
-__device__ inline void emit_rows(T *__restrict__ g, const AdamArgs<T> &A, long e0, int cnx,
+__device__ inline void emit_rows(const CoarseBase<T> &C, const AdamArgs<T> &A, uint32_t e0, uint32_t rowb,
                                  const T (&val)[YR], const T (&th)[YR], const T (&m)[YR],
                                  const T (&v)[YR]) {
 #pragma unroll
   for (int j = 0; j < YR; ++j) {
-    const long e = e0 + (long)j * cnx;
-    g[e] = val[j];
+    const uint32_t e = e0 + (uint32_t)j * rowb;
+    st_off(C.g, e, val[j]);
     if (ADAM) {
       const T mm = A.b1 * m[j] + (T(1) - A.b1) * val[j];
       const T vv = A.b2 * v[j] + (T(1) - A.b2) * val[j] * val[j];
-      A.m[e] = mm;
-      A.v[e] = vv;
-      A.th_out[e] = adam_theta(th[j], mm, vv, A.step, A.isb2, A.eps);
+      st_off(C.m, e, mm);
+      st_off(C.v, e, vv);
+      st_off(C.th_out, e, adam_theta(th[j], mm, vv, A.step, A.isb2, A.eps));
     }
   }
 }
 
 template <typename T, int YR, bool ADAM>
-__device__ inline void load_adam(const AdamArgs<T> &A, long e0, int cnx, T (&th)[YR], T (&m)[YR],
-                                 T (&v)[YR]) {
+__device__ inline void load_adam(const CoarseBase<T> &C, uint32_t e0, uint32_t rowb, T (&th)[YR],
+                                 T (&m)[YR], T (&v)[YR]) {
 #pragma unroll
   for (int j = 0; j < YR; ++j) {
     if (ADAM) {
-      const long e = e0 + (long)j * cnx;
-      th[j] = A.th_in[e];
-      m[j] = A.m[e];
-      v[j] = A.v[e];
+      const uint32_t e = e0 + (uint32_t)j * rowb;
+      th[j] = ld_off(C.th_in, e);
+      m[j] = ld_off(C.m, e);
+      v[j] = ld_off(C.v, e);
     } else {
       th[j] = m[j] = v[j] = T(0);
     }
@@ -182,7 +230,9 @@ __global__ __launch_bounds__(64 * kMarchWaves) void restrict_march_kernel(Levels
   const int B = gridDim.x, b = blockIdx.x, xcd = b & 7;
   const int q = B >> 3, r = B & 7;
   const int lb = xcd * q + (xcd < r ? xcd : r) + (b >> 3);
-  const int task = lb * kMarchWaves + (threadIdx.x >> 6);
+  // the wave's task, held in scalar registers: every base address below is
+  // wave-uniform and each lane adds a 32-bit byte offset
+  const int task = __builtin_amdgcn_readfirstlane(lb * kMarchWaves + (int)(threadIdx.x >> 6));
   if (task >= P.n_tasks) return;  // whole waves
   const int lane = threadIdx.x & 63;
   int t = task;
@@ -201,23 +251,26 @@ __global__ __launch_bounds__(64 * kMarchWaves) void restrict_march_kernel(Levels
   const int cnx = nx >> 1, cny = ny >> 1;
   const int cx = seg * 64 + gl;
   const int Y0 = (yc * P.groups + grp) * YR;
-  const int lo_off = (SEG && gl == 0 && cx > 0) ? 2 * cx - 1 : 2 * cx;
-  const int hi_off = (SEG && gl == W - 1 && cx < cnx - 1) ? 2 * cx + 2 : 2 * cx + 1;
+  // the edge lanes' cell beyond the segment, relative to the lane's pair
+  const int ed = (SEG && gl == 0 && cx > 0) ? -1 : (SEG && gl == W - 1 && cx < cnx - 1) ? 2 : 0;
+  const uint32_t edelta = (uint32_t)(ed * (int)sizeof(T));
 
   const T *fb = g + G.off[l] + (long)inst * G.stride[l] + G.foff[l][f];
   const long cbase = G.off[l + 1] + (long)inst * G.stride[l + 1] + G.foff[l + 1][f];
-  const long plane_f = (long)ny * nx;
-  const long plane_c = (long)cny * cnx;
-  const long row0 = (long)Y0 * cnx + cx;
+  const CoarseBase<T> C{g + cbase, A.th_in + cbase, A.th_out + cbase, A.m + cbase, A.v + cbase};
+  const uint32_t rowb = (uint32_t)nx * sizeof(T), crowb = (uint32_t)cnx * sizeof(T);
+  const uint32_t plane_fb = (uint32_t)ny * rowb, plane_cb = (uint32_t)cny * crowb;
+  const uint32_t loff = 2u * (uint32_t)cx * sizeof(T);
+  const uint32_t row0 = (uint32_t)Y0 * crowb + (uint32_t)cx * sizeof(T);
 
   T th[YR], m[YR], v[YR];
   if (!SPANZ) {
     RowLoad<T, SEG> rows[2 * YR + 2];
-    load_adam<T, YR, ADAM>(A, cbase + row0, cnx, th, m, v);
-    load_plane<T, YR, SEG>(fb, nx, Y0, ny, cx, lo_off, hi_off, rows);
+    load_adam<T, YR, ADAM>(C, row0, crowb, th, m, v);
+    load_plane<T, YR, SEG>(fb, 0u, rowb, Y0, ny, loff, edelta, rows);
     T Pl[YR];
     y_restrict<T, YR, SEG>(rows, W, gl, cx, cnx, Y0, ny, Pl);
-    emit_rows<T, YR, ADAM>(g, A, cbase + row0, cnx, Pl, th, m, v);
+    emit_rows<T, YR, ADAM>(C, A, row0, crowb, Pl, th, m, v);
     return;
   }
 
@@ -231,12 +284,12 @@ __global__ __launch_bounds__(64 * kMarchWaves) void restrict_march_kernel(Levels
     int iz[6];
     T wz[6];
     restrict_taps6(Z0, cnz, iz, wz);
-    const long e0 = cbase + (long)Z0 * plane_c + row0;
-    load_adam<T, YR, ADAM>(A, e0, cnx, th, m, v);
+    const uint32_t e0 = (uint32_t)Z0 * plane_cb + row0;
+    load_adam<T, YR, ADAM>(C, e0, crowb, th, m, v);
     RowLoad<T, SEG> rows[6][2 * YR + 2];
 #pragma unroll
     for (int t = 0; t < 6; ++t)
-      if (wz[t] != T(0)) load_plane<T, YR, SEG>(fb + iz[t] * plane_f, nx, Y0, ny, cx, lo_off, hi_off, rows[t]);
+      if (wz[t] != T(0)) load_plane<T, YR, SEG>(fb, (uint32_t)iz[t] * plane_fb, rowb, Y0, ny, loff, edelta, rows[t]);
     T acc[YR];
 #pragma unroll
     for (int j = 0; j < YR; ++j) acc[j] = T(0);
@@ -248,7 +301,7 @@ __global__ __launch_bounds__(64 * kMarchWaves) void restrict_march_kernel(Levels
 #pragma unroll
         for (int j = 0; j < YR; ++j) acc[j] += wz[t] * P[j];
       }
-    emit_rows<T, YR, ADAM>(g, A, e0, cnx, acc, th, m, v);
+    emit_rows<T, YR, ADAM>(C, A, e0, crowb, acc, th, m, v);
     return;
   }
   T Ap[YR], Ac[YR], An[YR];
@@ -262,10 +315,11 @@ __global__ __launch_bounds__(64 * kMarchWaves) void restrict_march_kernel(Levels
     const bool emit = J - 1 >= Z0 && J - 1 < Z0 + ZR;
     const bool needA = !(J == Z0 - 1 && za != 0);       // plane 2J feeds only J-1, J-2 there
     const bool needB = !(J == Z0 + ZR && zb != nz - 1);  // plane 2J+1 feeds only J, J+1 there
-    if (emit) load_adam<T, YR, ADAM>(A, cbase + (long)(J - 1) * plane_c + row0, cnx, th, m, v);
+    const uint32_t ec = (uint32_t)(J - 1) * plane_cb + row0;
+    if (emit) load_adam<T, YR, ADAM>(C, ec, crowb, th, m, v);
     RowLoad<T, SEG> ra[2 * YR + 2], rb[2 * YR + 2];
-    if (needA) load_plane<T, YR, SEG>(fb + za * plane_f, nx, Y0, ny, cx, lo_off, hi_off, ra);
-    if (needB) load_plane<T, YR, SEG>(fb + zb * plane_f, nx, Y0, ny, cx, lo_off, hi_off, rb);
+    if (needA) load_plane<T, YR, SEG>(fb, (uint32_t)za * plane_fb, rowb, Y0, ny, loff, edelta, ra);
+    if (needB) load_plane<T, YR, SEG>(fb, (uint32_t)zb * plane_fb, rowb, Y0, ny, loff, edelta, rb);
     if (needA) {
       T Pa[YR];
       y_restrict<T, YR, SEG>(ra, W, gl, cx, cnx, Y0, ny, Pa);
@@ -293,7 +347,7 @@ __global__ __launch_bounds__(64 * kMarchWaves) void restrict_march_kernel(Levels
           An[j] += T(0.25) * Pb[j];
       }
     }
-    if (emit) emit_rows<T, YR, ADAM>(g, A, cbase + (long)(J - 1) * plane_c + row0, cnx, Ap, th, m, v);
+    if (emit) emit_rows<T, YR, ADAM>(C, A, ec, crowb, Ap, th, m, v);
 #pragma unroll
     for (int j = 0; j < YR; ++j) {
       Ap[j] = Ac[j];
@@ -303,23 +357,38 @@ __global__ __launch_bounds__(64 * kMarchWaves) void restrict_march_kernel(Levels
   }
   // the last coarse plane is complete after the last step
   if (Jend == cnz - 1 && cnz - 1 >= Z0 && cnz - 1 < Z0 + ZR) {
-    const long e0 = cbase + (long)(cnz - 1) * plane_c + row0;
-    load_adam<T, YR, ADAM>(A, e0, cnx, th, m, v);
-    emit_rows<T, YR, ADAM>(g, A, e0, cnx, Ap, th, m, v);
+    const uint32_t e0 = (uint32_t)(cnz - 1) * plane_cb + row0;
+    load_adam<T, YR, ADAM>(C, e0, crowb, th, m, v);
+    emit_rows<T, YR, ADAM>(C, A, e0, crowb, Ap, th, m, v);
   }
 }
 
 // ------------------------------------------------------------------ host side
 // Tile choice: rows per wave YR and planes per wave ZR, 0 = automatic.
-static void choose_tile(int cnx, int cny, int cnz, bool spanz, int req, int &YR, int &ZR) {
-  YR = req ? (req >> 4) : 2;
-  ZR = req ? (req & 15) : 4;
+static void choose_tile(int cnx, int cny, int cnz, int groups, bool spanz, int req, int &YR, int &ZR) {
+  YR = req ? (req >> 6) : 2;
+  ZR = req ? (req & 63) : 4;
   if (!req && spanz) {
-    // measured on MI355X, 5 FP32 fields with Adam: 64^3 coarse cells take
-    // 18.4 us with (2, 4) against 19.2 (2, 2), 20.8 (4, 4), 23.3 (4, 2); on
-    // 32^3 and smaller levels (2, 1) is fastest (more waves in flight)
+    // measured on MI355X, 5 FP32 fields with Adam (us per launch):
+    //   128^3 coarse cells: (4, 8) 152, (4, 4) 158, (2, 8) 161, (2, 4) 167
+    //   64^3: (2, 4) 16.0, (2, 2) 16.4, (4, 2) 16.6, (4, 4) 17.5
+    //   32^3 and smaller: (2, 1) fastest (more waves in flight)
     const long cells = (long)cnx * cny * cnz;
-    if (cells <= 32L * 32 * 32) { YR = 2; ZR = 1; }
+    if (cells >= 128L * 128 * 128) {
+      YR = 4;
+      ZR = 8;
+    } else if (cells > 32L * 32 * 32) {
+      YR = 2;
+      ZR = 4;
+    } else {
+      YR = 2;
+      ZR = 1;
+    }
+    // a tile that does not divide the level falls back to one that does
+    if (cny % (groups * YR) || cnz % ZR) {
+      YR = 2;
+      ZR = 1;
+    }
   }
   if (!spanz) ZR = 1;
 }
@@ -352,9 +421,11 @@ bool restrict_march_ok(const Levels &G, int l, const void *g, size_t elem, int r
   P.wshift = 0;
   while ((1 << P.wshift) < P.W) ++P.wshift;
   P.groups = 64 / P.W;
-  choose_tile(cnx, cny, spanz ? cnz : 1, spanz, req, YR, ZR);
+  choose_tile(cnx, cny, spanz ? cnz : 1, P.groups, spanz, req, YR, ZR);
   if (cny % (P.groups * YR)) return false;
   if (spanz && cnz % ZR) return false;
+  // byte offsets within one field of a level are 32-bit
+  if ((long)nz * ny * nx * (long)elem >= (1L << 31)) return false;
   P.nyc = cny / (P.groups * YR);
   P.nzc = spanz ? cnz / ZR : 1;
   const long tasks = (long)G.batch * G.nf * P.nseg * P.nyc * P.nzc;
@@ -385,14 +456,18 @@ static void launch_march_yz(const Levels &G, int l, T *g, const AdamArgs<T> &A, 
 template <typename T, bool ADAM>
 static bool launch_march_t(const Levels &G, int l, T *g, const AdamArgs<T> &A, const MarchPlan &P,
                            int YR, int ZR, bool spanz, hipStream_t s) {
-  switch (YR * 16 + (spanz ? ZR : 1)) {
-    case 2 * 16 + 1: launch_march_yz<T, 2, 1, ADAM>(G, l, g, A, P, spanz, s); return true;
-    case 2 * 16 + 2: launch_march_yz<T, 2, 2, ADAM>(G, l, g, A, P, spanz, s); return true;
-    case 2 * 16 + 4: launch_march_yz<T, 2, 4, ADAM>(G, l, g, A, P, spanz, s); return true;
-    case 4 * 16 + 1: launch_march_yz<T, 4, 1, ADAM>(G, l, g, A, P, spanz, s); return true;
-    case 4 * 16 + 2: launch_march_yz<T, 4, 2, ADAM>(G, l, g, A, P, spanz, s); return true;
-    case 4 * 16 + 4: launch_march_yz<T, 4, 4, ADAM>(G, l, g, A, P, spanz, s); return true;
-    case 4 * 16 + 8: launch_march_yz<T, 4, 8, ADAM>(G, l, g, A, P, spanz, s); return true;
+  switch (YR * 64 + (spanz ? ZR : 1)) {
+    case 2 * 64 + 1: launch_march_yz<T, 2, 1, ADAM>(G, l, g, A, P, spanz, s); return true;
+    case 2 * 64 + 2: launch_march_yz<T, 2, 2, ADAM>(G, l, g, A, P, spanz, s); return true;
+    case 2 * 64 + 4: launch_march_yz<T, 2, 4, ADAM>(G, l, g, A, P, spanz, s); return true;
+    case 2 * 64 + 8: launch_march_yz<T, 2, 8, ADAM>(G, l, g, A, P, spanz, s); return true;
+    case 4 * 64 + 1: launch_march_yz<T, 4, 1, ADAM>(G, l, g, A, P, spanz, s); return true;
+    case 4 * 64 + 2: launch_march_yz<T, 4, 2, ADAM>(G, l, g, A, P, spanz, s); return true;
+    case 4 * 64 + 4: launch_march_yz<T, 4, 4, ADAM>(G, l, g, A, P, spanz, s); return true;
+    case 4 * 64 + 8: launch_march_yz<T, 4, 8, ADAM>(G, l, g, A, P, spanz, s); return true;
+    case 4 * 64 + 16: launch_march_yz<T, 4, 16, ADAM>(G, l, g, A, P, spanz, s); return true;
+    case 8 * 64 + 4: launch_march_yz<T, 8, 4, ADAM>(G, l, g, A, P, spanz, s); return true;
+    case 8 * 64 + 8: launch_march_yz<T, 8, 8, ADAM>(G, l, g, A, P, spanz, s); return true;
     default: return false;
   }
 }

@@ -302,7 +302,7 @@ class Context:
 
     def set_march_tile(self, rows: int = 0, planes: int = 0):
         """Coarse rows and planes per wave of the marching kernel (0, 0: automatic)."""
-        L.check(L.lib().modil_set_option(self.h, L.OPT_MARCH_TILE, 16 * rows + planes), self.h)
+        L.check(L.lib().modil_set_option(self.h, L.OPT_MARCH_TILE, 64 * rows + planes), self.h)
 
     def check(self):
         """Synchronise; raise ModilError on a non-finite loss or a HIP error."""

@@ -49,7 +49,8 @@ def test_restrict_matches_oracle_transpose(op, dims, L):
     assert rel(pk.cpu().numpy(), pk2.cpu().numpy()) <= 1e-14
 
 
-@pytest.mark.parametrize("rows,planes", [(2, 1), (2, 2), (2, 4), (4, 1), (4, 2), (4, 4), (4, 8)])
+@pytest.mark.parametrize("rows,planes", [(2, 1), (2, 2), (2, 4), (2, 8), (4, 1), (4, 2), (4, 4), (4, 8),
+                                         (4, 16), (8, 4), (8, 8)])
 def test_every_tile(rows, planes):
     need_gpu()
     spec = case("poisson", (32, 64, 128), 2, seed=23)
@@ -68,6 +69,8 @@ def test_unsupported_tile_is_rejected():
     ctx = context_of(spec, "f64")
     with pytest.raises(Exception):
         ctx.set_march_tile(3, 1)
+    with pytest.raises(Exception):
+        ctx.set_march_tile(8, 1)
 
 
 def test_batch_instances():
