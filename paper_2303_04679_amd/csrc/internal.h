@@ -296,7 +296,7 @@ hipError_t launch_restrict_chain(modil_ctx *c, void *g, int from_level, const vo
                                  bool carry = false, bool *carried = nullptr);
 // Marching restriction of level l -> l+1 with optional Adam (restrict_march.hip);
 // returns false, launching nothing, when the level's shape does not admit it.
-// tile: 16 * rows + planes per wave, 0 = automatic.
+// tile: 64 * rows + planes per wave, 0 = automatic.
 template <typename T>
 bool launch_restrict_march(const Levels &G, int l, T *g, const AdamArgs<T> &A, bool adam, int tile,
                            hipStream_t s);

@@ -189,14 +189,18 @@ __global__ __launch_bounds__(kP2Threads) void prolong2_kernel(Levels G, int l, i
   }
   const bool own = tid < (y1 - y0) * mx;
   const int Jy = own ? y0 + small_div(tid, mx, rx) : y0, Jx = own ? tid - (Jy - y0) * mx : 0;
+  using P2 = typename PPair<T>::type;
   T tf[2][2][2];
 #pragma unroll
   for (int ez = 0; ez < 2; ++ez)
 #pragma unroll
     for (int ey = 0; ey < 2; ++ey) {
       const long o = fb + ((long)(2 * Jz + ez) * ny + (2 * Jy + ey)) * nx + 2 * Jx;
-#pragma unroll
-      for (int ex = 0; ex < 2; ++ex) tf[ez][ey][ex] = own ? th_l[o + ex] : T(0);
+      P2 t2;
+      t2.x = t2.y = T(0);
+      if (own) t2 = *reinterpret_cast<const P2 *>(th_l + o);  // 2 Jx: pair-aligned
+      tf[ez][ey][0] = t2.x;
+      tf[ez][ey][1] = t2.y;
     }
 #pragma unroll
   for (int u = 0; u < kC; ++u) {
@@ -262,8 +266,10 @@ __global__ __launch_bounds__(kP2Threads) void prolong2_kernel(Levels G, int l, i
         v[e] = tf[ez][ey][e] + acc;
       }
       const long o = fb + ((long)(2 * Jz + ez) * ny + (2 * Jy + ey)) * nx + 2 * Jx;
-      dst[o] = v[0];
-      dst[o + 1] = v[1];
+      P2 out;
+      out.x = v[0];
+      out.y = v[1];
+      *reinterpret_cast<P2 *>(dst + o) = out;
     }
 }
 
@@ -277,6 +283,10 @@ template <typename T>
 bool launch_prolong2(const Levels &G, int l, const T *th_l, const T *th_m, const T *csrc, T *dst,
                      hipStream_t s) {
   if (G.node || l + 2 >= G.L) return false;
+  // level l is read and written in pairs of x-neighbours (fields and
+  // instances start at even offsets: nx is even)
+  if (reinterpret_cast<uintptr_t>(th_l) % (2 * sizeof(T)) || reinterpret_cast<uintptr_t>(dst) % (2 * sizeof(T)))
+    return false;
   for (int j = l; j <= l + 2; ++j)
     for (int f = 1; f < G.nf; ++f)
       for (int a = 0; a < 3; ++a)
