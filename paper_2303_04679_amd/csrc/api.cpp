@@ -381,13 +381,21 @@ bool use_fused(const modil_ctx *c) {
 // carry_in: w_buf already holds the Horner tail for theta (carried by the
 // previous iteration); carry_out: have the restriction tail also form the
 // Horner tail for th_out (carried reports whether it did).
+// whether launch_horner launches anything: the levels from L - 2 (or below
+// the carried tail) down to level 1 (skip_fine) or 0
+static bool horner_needed(const modil_ctx *c, bool skip_fine, bool skip_tail) {
+  const int L = c->prob.n_levels, l_end = skip_fine ? 1 : 0;
+  if (L == 1) return false;
+  return (skip_tail ? c->carry_stop - 1 : L - 2) >= l_end;
+}
+
 int evaluate(modil_ctx *c, const void *theta, void *grad, double *terms, const AdamHost *adam = nullptr,
              void *th_out = nullptr, void *m = nullptr, void *v = nullptr, bool carry_in = false,
              bool carry_out = false, bool *carried = nullptr) {
   const bool want = grad != nullptr;
   if (carried) *carried = false;
   if (use_fused(c) && want) {
-    {
+    if (horner_needed(c, true, carry_in)) {
       Timed t(c, 1);
       HIP_OR_RETURN(c, launch_horner(c, theta, nullptr, true, carry_in), "prolong");
     }
@@ -424,18 +432,20 @@ int evaluate(modil_ctx *c, const void *theta, void *grad, double *terms, const A
   const void *u = theta;
   bool summed = false;  // the data kernel summed the partials
   const bool tiled = fine_uses_tiles(c);
-  if (c->prob.n_levels > 1) {
+  if (horner_needed(c, tiled, tiled && carry_in)) {
+    // the tile kernel forms the finest level itself: Horner down to level 1
     Timed t(c, 1);
-    HIP_OR_RETURN(c, launch_horner(c, theta, nullptr, false, tiled && carry_in), "prolong");
-    u = c->w_buf;
+    HIP_OR_RETURN(c, launch_horner(c, theta, nullptr, tiled, tiled && carry_in), "prolong");
+    if (!tiled) u = c->w_buf;
   }
   if (tiled) {
-    // 2-D tiled engine: the tile kernel also forms the data terms and, with
-    // Adam, updates level 0; the restriction kernels update the coarse levels
-    // and the restriction tail sums the loss partials
+    // 2-D tiled engine: the tile kernel also forms the finest level (theta_0
+    // + T w_1 while staging its tile), the data terms and, with Adam, updates
+    // level 0; the restriction kernels update the coarse levels and the
+    // restriction tail sums the loss partials
     {
       Timed t(c, 0);
-      HIP_OR_RETURN(c, launch_fine(c, u, grad, want, adam, theta, th_out, m, v), "fine kernel");
+      HIP_OR_RETURN(c, launch_fine(c, theta, grad, want, adam, theta, th_out, m, v, true), "fine kernel");
     }
     TermSum sum;
     sum.partials = c->partials;

@@ -368,7 +368,7 @@ int modil_cnn_rasterize(modil_cnn *n, int32_t batch, const int32_t *idx, const f
 
 // trunk activation and head-map bases inside the per-image act / out arrays
 static void bases(const modil_cnn *n, long (&act_off)[3], long (&out_off)[3]) {
-  const long s1 = n->d.size / 4, s2 = n->d.size / 8, s3 = n->d.size / 16;
+  const long s1 = n->d.size / 4, s2 = n->d.size / 8;
   act_off[0] = 0;
   act_off[1] = n->d.width1 * s1 * s1;
   act_off[2] = act_off[1] + n->d.width2 * s2 * s2;

@@ -318,10 +318,13 @@ bool launch_prolong2(const Levels &G, int l, const T *th_l, const T *th_m, const
 hipError_t launch_adam(modil_ctx *c, const void *theta_in, void *theta_out, void *m, void *v,
                        const void *g, long n, const AdamHost &h);
 // generic finest-level kernel (tiled on 2-D problems); with adam given (tiled
-// engine only) also Adam on level 0 of the fields spanning the grid
+// engine only) also Adam on level 0 of the fields spanning the grid; with
+// prolong (tiled engine only) u is theta and the kernel forms the finest
+// level itself, theta_0 + T w_1, from level 1 of the prolonged levels
 hipError_t launch_fine(modil_ctx *c, const void *u, void *g, bool want_grad,
                        const AdamHost *adam = nullptr, const void *th_in = nullptr,
-                       void *th_out = nullptr, void *m = nullptr, void *v = nullptr);
+                       void *th_out = nullptr, void *m = nullptr, void *v = nullptr,
+                       bool prolong = false);
 // the 2-D engine by tiles: the problems it takes, their fine grid, tile shape
 bool fine_is_2d(const modil_problem &P);
 void fine_2d(const modil_problem &P, int &ny, int &nx);

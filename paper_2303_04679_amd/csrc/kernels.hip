@@ -26,17 +26,24 @@ namespace modil {
 // ---------------------------------------------------------------- geometry
 // 32-bit geometry of every level (pack sizes are validated to fit in int32).
 __device__ inline void locate(const Levels &G, int l, int e, int &inst, int &f, int (&i)[3]) {
-  inst = e / G.stride[l];
+  // below 2^22 the float-reciprocal division (exact there) replaces the
+  // integer divisions, which take tens of instructions each
+  const bool small = G.stride[l] * G.batch < (1 << 22);
+  inst = small ? small_div(e, G.stride[l], 1.0f / (float)G.stride[l]) : e / G.stride[l];
   int rem = e - inst * G.stride[l];
   f = 0;
   for (int k = 1; k < G.nf; ++k)
     if (rem >= G.foff[l][k]) f = k;
   int cell = rem - G.foff[l][f];
   const int nx = G.n[l][f][2], ny = G.n[l][f][1];
-  i[2] = cell % nx;
-  cell /= nx;
-  i[1] = cell % ny;
-  i[0] = cell / ny;
+  if (small) {
+    small_index(cell, ny, nx, 1.0f / (float)ny, 1.0f / (float)nx, i);
+  } else {
+    i[2] = cell % nx;
+    cell /= nx;
+    i[1] = cell % ny;
+    i[0] = cell / ny;
+  }
 }
 
 // (T w)(i) of field f at fine level l from the level-(l+1) array base cb
@@ -137,7 +144,7 @@ __device__ inline T restrict_value_at(const Levels &G, int l, int f, const int (
     for (int a = 0; a < 3; ++a)
 #pragma unroll
       for (int b = 0; b < 3; ++b) {
-        const T *r = fb + ((long)iz[a] * ny + iy[b]) * nx;
+        const T *r = fb + (iz[a] * ny + iy[b]) * nx;  // level offsets are int
         acc += wz[a] * wy[b] * (wx[0] * r[ix[0]] + wx[1] * r[ix[1]] + wx[2] * r[ix[2]]);
       }
     return acc;
@@ -598,7 +605,36 @@ struct FineArgs {
   long ncell;          // cells of the full grid
   int want_grad;
   int xonly_field;     // index of the field spanning x only, or -1
+  // prolongation fused into the 2-D tile kernel's staging: with w1 given, u
+  // holds theta (level 0 of the pack) and the kernel stages u = theta_0 +
+  // T w_1, w1 being level 1 of the prolonged levels (pack layout)
+  const T *w1;
+  long w1_inst;          // level-1 elements of one instance
+  int w1_off[kMaxF];     // field offsets on level 1
+  int w1_n[kMaxF][2];    // level-1 values along y and x of each field
+  int node;              // node-based T, else cell-based
 };
+
+// (T w_1) at fine cell (y, x) of field f of one instance (2-D tiled engine):
+// the same taps and order as the generic step on a grid without z
+template <typename T>
+__device__ inline T tile_prolong(const FineArgs<T> &A, int f, int inst, int y, int x) {
+  const T *c = A.w1 + inst * A.w1_inst + A.w1_off[f];
+  const int cnx = A.w1_n[f][1];
+  const bool sy = A.ff.stride[f][1] != 0;  // the field spans y
+  int ix[2], iy[2];
+  T wx[2], wy[2];
+  if (A.node) {
+    prolong_taps_node(x, ix, wx);
+    if (sy) prolong_taps_node(y, iy, wy);
+  } else {
+    prolong_taps(x, cnx, ix, wx);
+    if (sy) prolong_taps(y, A.w1_n[f][0], iy, wy);
+  }
+  if (!sy) return wx[0] * c[ix[0]] + wx[1] * c[ix[1]];
+  return wy[0] * (wx[0] * c[iy[0] * cnx + ix[0]] + wx[1] * c[iy[0] * cnx + ix[1]]) +
+         wy[1] * (wx[0] * c[iy[1] * cnx + ix[0]] + wx[1] * c[iy[1] * cnx + ix[1]]);
+}
 
 // ND: the grid's dimension when known at compile time (3 for the 3-D
 // kernels, whose slot indices then stay in registers), else 0 (p.ndim)
@@ -912,8 +948,14 @@ __global__ __launch_bounds__(NT) void fine_tile_kernel(FineArgs<T> A, int tiles_
   for (int k = tid; k < FT::UX * FT::UY; k += NT) {
     const int X = k % FT::UX, Y = k / FT::UX, x = x0 - 2 + X, y = y0 - 2 + Y;
     const bool in = x >= 0 && x < nx && y >= 0 && y < ny;
-    for (int f = 0; f < NF; ++f)
-      Ut[f][Y][X] = in ? ub[A.ff.off[f] + y * A.ff.stride[f][1] + x * A.ff.stride[f][2]] : T(0);
+    for (int f = 0; f < NF; ++f) {
+      T val = T(0);
+      if (in) {
+        val = ub[A.ff.off[f] + y * A.ff.stride[f][1] + x * A.ff.stride[f][2]];
+        if (A.w1) val += tile_prolong(A, f, inst, A.ff.stride[f][1] ? y : 0, x);
+      }
+      Ut[f][Y][X] = val;
+    }
   }
   __syncthreads();
   double part[kTerms] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -1431,8 +1473,21 @@ static void launch_fine_tile(modil_ctx *c, const FineArgs<T> &A, const AdamArgs<
 template <typename T>
 static hipError_t launch_fine_t(modil_ctx *c, const void *u, void *g, bool want_grad,
                                 const AdamHost *adam, const void *th_in, void *th_out, void *m,
-                                void *v) {
-  const FineArgs<T> A = fine_args<T>(c, u, g, want_grad);
+                                void *v, bool prolong) {
+  FineArgs<T> A = fine_args<T>(c, u, g, want_grad);
+  if (prolong && c->prob.n_levels > 1) {
+    // u is theta; level 1 of the prolonged levels is theta's own when L = 2
+    const T *wb = c->prob.n_levels == 2 ? (const T *)u : (const T *)c->w_buf;
+    A.w1 = wb + c->lay.level_offset[1];
+    A.w1_inst = c->lay.level_stride[1];
+    A.node = c->prob.centering == MODIL_NODE;
+    for (int f = 0; f < c->lay.n_fields; ++f) {
+      A.w1_off[f] = (int)c->lay.field_offset[1][f];
+      const FieldGeom g1 = field_geom(c->prob, 1, f);
+      A.w1_n[f][0] = g1.n[1];
+      A.w1_n[f][1] = g1.n[2];
+    }
+  }
   const AdamArgs<T> A0 = adam_args<T>(adam, th_in, th_out, m, v);
   const bool ad = adam != nullptr;
   const dim3 grid(nblk(A.ncell), c->prob.batch);
@@ -1495,10 +1550,10 @@ static hipError_t launch_fine_t(modil_ctx *c, const void *u, void *g, bool want_
 bool fine_uses_tiles(const modil_ctx *c) { return c->tile_enabled && fine_is_2d(c->prob); }
 
 hipError_t launch_fine(modil_ctx *c, const void *u, void *g, bool want_grad, const AdamHost *adam,
-                       const void *th_in, void *th_out, void *m, void *v) {
+                       const void *th_in, void *th_out, void *m, void *v, bool prolong) {
   return c->prob.dtype == MODIL_F64
-             ? launch_fine_t<double>(c, u, g, want_grad, adam, th_in, th_out, m, v)
-             : launch_fine_t<float>(c, u, g, want_grad, adam, th_in, th_out, m, v);
+             ? launch_fine_t<double>(c, u, g, want_grad, adam, th_in, th_out, m, v, prolong)
+             : launch_fine_t<float>(c, u, g, want_grad, adam, th_in, th_out, m, v, prolong);
 }
 
 hipError_t launch_colsum(modil_ctx *c, void *g_fine, const AdamHost *adam, const void *th_in,

@@ -23,7 +23,7 @@ def tiles(nz, ny, nx, batch):
     ntx = -(-nx // NSO_X)
     nty = -(-ny // NSO_Y)
     xy = ntx * nty * batch
-    tz = 16
+    tz = 32
     while tz > 2 and xy * (-(-nz // tz)) < CUS:
         tz //= 2
     return tz, -(-nz // tz), ntx, nty
@@ -58,7 +58,8 @@ def prolong_taps(i, n):
 
 CASES = [((24, 36, 60), 1, 3), ((16, 28, 24), 1, 3), ((64, 16, 32), 1, 4), ((8, 8, 8), 1, 1),
          ((16, 16, 24), 1, 3), ((8, 16, 24), 1, 3), ((16, 24, 32), 2, 3), ((40, 12, 20), 4, 3),
-         ((40, 12, 20), 26, 3), ((40, 12, 20), 52, 3), ((40, 12, 20), 86, 3), ((16, 16, 32), 1, 3),
+         ((40, 12, 20), 26, 3), ((40, 12, 20), 52, 3), ((40, 12, 20), 86, 3), ((40, 12, 20), 130, 3),
+         ((16, 16, 32), 1, 3),
          ((32, 32, 64), 1, 4), ((64, 64, 64), 1, 5), ((128, 128, 128), 1, 6),
          ((16, 128, 128), 1, 4), ((256, 256, 256), 1, 7), ((8, 8, 16), 1, 3)]
 

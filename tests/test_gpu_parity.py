@@ -260,11 +260,15 @@ def test_nonfinite_is_reported():
                                              ("burgers", (24, 40), 3, 1), ("poisson", (32, 48), 4, 1),
                                              ("poisson_node", (16, 24), 3, 1), ("cavity_node", (32, 48), 4, 1),
                                              ("cavity_node", (48, 64), 3, 12),
-                                             ("heat", (64, 96), 3, 12), ("cavity", (48, 64), 3, 16)])
+                                             ("heat", (64, 96), 3, 12), ("cavity", (48, 64), 3, 16),
+                                             ("poisson", (24, 40), 2, 1), ("burgers", (16, 24), 1, 1),
+                                             ("cavity_node", (16, 32), 2, 1), ("heat", (32, 48), 2, 1)])
 def test_tiled_engine(op, dims, L, batch, dtype):
     """The 2-D tiled engine (16 x 4 tiles; 32 x 8 when the batch fills the
-    chip) against the per-cell kernel for every instance and the oracle for
-    the first and last; ragged tiles, node-based values, an x-only field."""
+    chip), which forms the finest level theta_0 + T w_1 itself while staging,
+    against the per-cell kernel for every instance and the oracle for the
+    first and last; ragged tiles, node-based values, an x-only field, two
+    levels (w_1 is theta_1) and one (no prolongation)."""
     need_gpu()
     print(f"\n[parity] tiled {op} {dims} L={L} batch={batch} {dtype}", flush=True)
     forcing = op not in ("poisson", "poisson_node")
@@ -353,11 +357,11 @@ def test_fused_channel_kernel_fp32_only():
     assert context_of(spec, "f32").fused_active()
 
 
-@pytest.mark.parametrize("batch", [4, 26, 52, 86])
+@pytest.mark.parametrize("batch", [4, 26, 52, 86, 130])
 def test_fused_channel_zchunks(batch):
-    """z-chunk lengths 2, 4, 8 and 16: a batch of one-tile instances with 40
-    planes (the longer chunks end ragged).  The chunk is the longest that gives
-    every compute unit a block, so these batch sizes select the four lengths.
+    """z-chunk lengths 2, 4, 8, 16 and 32: a batch of one-tile instances with
+    40 planes (the longer chunks end ragged).  The chunk is the longest that
+    gives every compute unit a block, so these batch sizes select the lengths.
     Every instance matches the generic engine; the first and last the oracle
     (FP32 inputs, promoted to FP64 for the oracle)."""
     need_gpu()
