@@ -8,14 +8,16 @@
 // rows and ZR coarse planes.  Each fine value is loaded once per wave:
 //   x  a lane loads its two fine cells 2J, 2J+1 as one vector load and takes
 //      the neighbours 2J-1, 2J+2 (and the extrapolated end cells) from the
-//      adjacent lanes by shuffles;
+//      adjacent lanes by DPP wave shifts;
 //   y  the fine rows of a plane are scattered into the YR coarse rows with the
 //      weights of T (each fine row feeds two coarse rows);
 //   z  the wave marches through the fine planes two at a time; a fine plane
 //      feeds the previous, current and next coarse plane accumulators, and the
 //      previous one is complete once both planes of a step are in.
 // The loads of both planes of a step are issued before any of them is used.
-// Summation order is fixed, so results are deterministic.
+// Every address is a wave-uniform base (the wave's task is read into scalar
+// registers) plus a 32-bit byte offset per lane.  Summation order is fixed,
+// so results are deterministic.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
