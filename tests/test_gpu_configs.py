@@ -29,8 +29,28 @@ def test_workload_loss_and_gradient(name):
     theta = pack_of(ctx, [lv])
     terms, grad = ctx.loss_grad(theta)
     torch.cuda.synchronize()
+    # the timed path: Adam fused into the finest and the restriction kernels;
+    # two plain steps from zero moments, then the same two iterations in one
+    # modil_run call (the second starting from the Horner tail the first
+    # one's restriction tail carried)
+    o1, o2 = ctx.new_pack(), ctx.new_pack()
+    m, v = ctx.new_pack(), ctx.new_pack()
+    t1 = torch.empty((1, 5), dtype=torch.float64, device="cuda")
+    ctx.step(theta, o1, m, v, 1, lr=wl.lr, terms=t1)
+    m1 = m.clone()
+    ctx.step(o1, o2, m, v, 2, lr=wl.lr)
+    ra, rb = theta.clone(), ctx.new_pack()
+    rm, rv = ctx.new_pack(), ctx.new_pack()
+    out = ctx.run(ra, rb, rm, rv, 1, 2, lr=wl.lr)
+    torch.cuda.synchronize()
+    assert torch.equal(out, o2) and torch.equal(rm, m) and torch.equal(rv, v), (name, "run == steps")
     rterms, rgrad = ops.loss_and_grad(spec, lv)
     tol = TOL[wl.spec.dtype]
+    fspec = spec if wl.spec.dtype == "f32" else None
     assert_terms(terms[0].cpu().numpy(), rterms, tol, name)
-    assert_levels(levels_of(ctx, grad), rgrad, tol, name,
-                  spec=spec if wl.spec.dtype == "f32" else None)
+    assert_levels(levels_of(ctx, grad), rgrad, tol, name, spec=fspec)
+    # the first step's loss terms are those at theta; its first moment is
+    # (1 - b1) times the oracle's gradient on every level
+    assert_terms(t1[0].cpu().numpy(), rterms, tol, (name, "step"))
+    assert_levels(levels_of(ctx, m1), [[0.1 * g for g in row] for row in rgrad], tol, (name, "step m"),
+                  spec=fspec)
