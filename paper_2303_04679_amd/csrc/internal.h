@@ -300,6 +300,11 @@ hipError_t launch_restrict_chain(modil_ctx *c, void *g, int from_level, const vo
 template <typename T>
 bool launch_restrict_march(const Levels &G, int l, T *g, const AdamArgs<T> &A, bool adam, int tile,
                            hipStream_t s);
+// the same for node-based fields of one shape spanning every axis they have
+// (lanes over the flattened coarse plane); false when the level does not qualify
+template <typename T>
+bool launch_restrict_march_node(const Levels &G, int l, T *g, const AdamArgs<T> &A, bool adam,
+                                hipStream_t s);
 // Horner step of level l by coarse-cell blocks (prolong_block.hip): theta and
 // dst are level-l bases, csrc the level-(l+1) base; false (nothing launched)
 // when the level's shape does not admit it.

@@ -1292,6 +1292,8 @@ static hipError_t restrict_t(modil_ctx *c, void *g_v, int from, const void *th_i
     if (c->march_enabled &&
         launch_restrict_march<T>(G, l, g, A, ad != nullptr, c->march_tile, c->stream))
       continue;
+    if (c->march_enabled && launch_restrict_march_node<T>(G, l, g, A, ad != nullptr, c->stream))
+      continue;
     const long total = (long)G.stride[l + 1] * G.batch;
     if (ad)
       restrict_kernel<T, true><<<nblk(total), kBlock, 0, c->stream>>>(G, l, g, A);

@@ -487,6 +487,170 @@ bool launch_restrict_march(const Levels &G, int l, T *g, const AdamArgs<T> &A, b
               : launch_march_t<T, false>(G, l, g, A, P, YR, ZR, spanz, s);
 }
 
+// ------------------------------------------------- node-based values
+// Node-based T^T (Section 2.2): coarse node J gathers the fine nodes 2J - 1,
+// 2J, 2J + 1 with weights 1/2, 1, 1/2 (clipped at the ends) along every
+// spanned axis.  Node counts are 2^k + 1, which rows of 64-lane segments do
+// not tile, so a wave's 64 lanes take 64 consecutive nodes of the flattened
+// coarse plane (y, x) and the wave marches along z through ZR coarse planes:
+//   x  a lane loads fine nodes 2J and 2J + 1 of a fine row and takes 2J - 1
+//      from the previous lane (the same row when J > 0); the wave's first
+//      lane loads it itself;
+//   y  a lane gathers the three fine rows 2Y - 1, 2Y, 2Y + 1 of its coarse row;
+//   z  each fine plane is formed once per wave: an even plane 2J feeds coarse
+//      plane J, an odd plane 2J + 1 feeds J and J + 1 with 1/2 each.
+// Lanes past the plane's last node load nothing and store nothing but still
+// run the shifts.  Fine rows have an odd count, so loads are per value.
+struct NodeMarchPlan {
+  int lanes_per_plane;  // coarse nodes of one coarse plane (ncy * ncx)
+  int tasks_plane;      // waves per coarse plane chunk
+  int zr, nzc;          // coarse planes per wave, chunks along z
+  int spanz;
+  int n_tasks;
+};
+
+template <typename T, int ZR, bool ADAM>
+__global__ __launch_bounds__(64 * kMarchWaves) void restrict_march_node_kernel(Levels G, int l, T *g,
+                                                                               AdamArgs<T> A,
+                                                                               NodeMarchPlan P) {
+  const int B = gridDim.x, b = blockIdx.x, xcd = b & 7;
+  const int q8 = B >> 3, r8 = B & 7;
+  const int lb = xcd * q8 + (xcd < r8 ? xcd : r8) + (b >> 3);
+  const int task = __builtin_amdgcn_readfirstlane(lb * kMarchWaves + (int)(threadIdx.x >> 6));
+  if (task >= P.n_tasks) return;  // whole waves
+  const int lane = threadIdx.x & 63;
+  int t = task;
+  const int tp = t % P.tasks_plane;
+  t /= P.tasks_plane;
+  const int zc = t % P.nzc;
+  t /= P.nzc;
+  const int f = t % G.nf, inst = t / G.nf;
+  const int nfy = G.n[l][f][1], nfx = G.n[l][f][2], nfz = G.n[l][f][0];
+  const int ncz = G.n[l + 1][f][0], ncx = G.n[l + 1][f][2];
+  // this lane's coarse node of the plane: row Y, column J
+  const int qn = tp * 64 + lane;
+  const bool on = qn < P.lanes_per_plane;
+  const int qc = on ? qn : P.lanes_per_plane - 1;  // idle lanes mirror the last node
+  const int Y = small_div(qc, ncx, 1.0f / (float)ncx), J = qc - Y * ncx;
+  const T *fb = g + G.off[l] + (long)inst * G.stride[l] + G.foff[l][f];
+  const long cbase = G.off[l + 1] + (long)inst * G.stride[l + 1] + G.foff[l + 1][f];
+  const CoarseBase<T> C{g + cbase, A.th_in + cbase, A.th_out + cbase, A.m + cbase, A.v + cbase};
+  const uint32_t rowb = (uint32_t)nfx * sizeof(T), plane_fb = (uint32_t)nfy * rowb;
+  const uint32_t plane_cb = (uint32_t)P.lanes_per_plane * sizeof(T);
+  const uint32_t cofs = (uint32_t)qc * sizeof(T);
+  const bool has_b = 2 * J + 1 < nfx;                    // fine node 2J + 1 exists
+  const bool self_left = lane == 0 && J > 0;              // 2J - 1 not on the previous lane
+  // the three fine rows of coarse row Y (clipped rows get weight 0)
+  int rows[3];
+  T wy[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int r = 2 * Y - 1 + k;
+    rows[k] = r < 0 ? 0 : (r >= nfy ? nfy - 1 : r);
+    wy[k] = (r < 0 || r >= nfy) ? T(0) : (k == 1 ? T(1) : T(0.5));
+  }
+  // T^T along y and x of fine plane z for this lane
+  auto plane_value = [&](int z) {
+    const uint32_t zo = (uint32_t)z * plane_fb;
+    T a[3], bb[3], e[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const uint32_t o = zo + (uint32_t)rows[k] * rowb + (uint32_t)(2 * J) * sizeof(T);
+      a[k] = ld_off(fb, o);
+      bb[k] = has_b ? ld_off(fb, o + sizeof(T)) : T(0);
+      e[k] = self_left ? ld_off(fb, o - sizeof(T)) : T(0);
+    }
+    T acc = T(0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      T left = wave_prev(bb[k]);
+      if (self_left) left = e[k];
+      if (J == 0) left = T(0);
+      acc += wy[k] * (a[k] + T(0.5) * left + T(0.5) * bb[k]);
+    }
+    return acc;
+  };
+  auto finish = [&](int Jz, T val) {
+    if (!on) return;
+    const uint32_t e = (uint32_t)Jz * plane_cb + cofs;
+    T th = T(0), m = T(0), v = T(0);
+    if (ADAM) {
+      th = ld_off(C.th_in, e);
+      m = ld_off(C.m, e);
+      v = ld_off(C.v, e);
+    }
+    st_off(C.g, e, val);
+    if (ADAM) {
+      const T mm = A.b1 * m + (T(1) - A.b1) * val;
+      const T vv = A.b2 * v + (T(1) - A.b2) * val * val;
+      st_off(C.m, e, mm);
+      st_off(C.v, e, vv);
+      st_off(C.th_out, e, adam_theta(th, mm, vv, A.step, A.isb2, A.eps));
+    }
+  };
+  if (!P.spanz) {
+    finish(0, plane_value(0));
+    return;
+  }
+  const int Z0 = zc * ZR;
+  const int Z1 = Z0 + ZR < ncz ? Z0 + ZR : ncz;
+  T odd = Z0 > 0 ? plane_value(2 * Z0 - 1) : T(0);  // fine plane 2 Z0 - 1
+  for (int Jz = Z0; Jz < Z1; ++Jz) {
+    const T even = plane_value(2 * Jz);
+    const T nxt = 2 * Jz + 1 < nfz ? plane_value(2 * Jz + 1) : T(0);
+    finish(Jz, T(0.5) * odd + even + T(0.5) * nxt);
+    odd = nxt;
+  }
+}
+
+// Node-based levels of one shape spanning every axis they have (2-D: y and
+// x; 3-D: all three), node counts 2 n + 1 -> n + 1.
+static bool restrict_march_node_ok(const Levels &G, int l, size_t elem, NodeMarchPlan &P) {
+  if (!G.node || l + 1 >= G.L) return false;
+  for (int f = 1; f < G.nf; ++f)
+    for (int a = 0; a < 3; ++a)
+      if (G.n[l][f][a] != G.n[l][0][a] || G.n[l + 1][f][a] != G.n[l + 1][0][a]) return false;
+  const int nz = G.n[l][0][0], ny = G.n[l][0][1], nx = G.n[l][0][2];
+  const int cnz = G.n[l + 1][0][0], cny = G.n[l + 1][0][1], cnx = G.n[l + 1][0][2];
+  if (nx != 2 * cnx - 1 || ny != 2 * cny - 1 || cnx < 2 || cny < 2) return false;
+  const bool spanz = nz > 1;
+  if (spanz ? nz != 2 * cnz - 1 : cnz != 1) return false;
+  if ((long)nz * ny * nx * (long)elem >= (1L << 31)) return false;  // 32-bit byte offsets
+  const long plane = (long)cny * cnx;
+  if (plane >= (1L << 22)) return false;  // the float-reciprocal split of a plane index
+  P.lanes_per_plane = (int)plane;
+  P.tasks_plane = (int)((plane + 63) / 64);
+  P.spanz = spanz ? 1 : 0;
+  // two coarse planes per wave (five fine planes formed for two outputs)
+  // while that still gives 2048 waves, else one (three for one)
+  P.zr = spanz ? 2 : 1;
+  if (spanz && (long)G.batch * G.nf * ((cnz + 1) / 2) * P.tasks_plane < 2048) P.zr = 1;
+  P.nzc = spanz ? (cnz + P.zr - 1) / P.zr : 1;
+  const long tasks = (long)G.batch * G.nf * P.nzc * P.tasks_plane;
+  if (tasks > (1L << 30)) return false;
+  P.n_tasks = (int)tasks;
+  return true;
+}
+
+template <typename T>
+bool launch_restrict_march_node(const Levels &G, int l, T *g, const AdamArgs<T> &A, bool adam,
+                                hipStream_t s) {
+  NodeMarchPlan P{};
+  if (!restrict_march_node_ok(G, l, sizeof(T), P)) return false;
+  const unsigned blocks = (unsigned)((P.n_tasks + kMarchWaves - 1) / kMarchWaves);
+  auto go = [&](auto kernel) { kernel<<<blocks, 64 * kMarchWaves, 0, s>>>(G, l, g, A, P); };
+  if (P.zr == 2)
+    adam ? go(restrict_march_node_kernel<T, 2, true>) : go(restrict_march_node_kernel<T, 2, false>);
+  else
+    adam ? go(restrict_march_node_kernel<T, 1, true>) : go(restrict_march_node_kernel<T, 1, false>);
+  return true;
+}
+
+template bool launch_restrict_march_node<float>(const Levels &, int, float *, const AdamArgs<float> &,
+                                                bool, hipStream_t);
+template bool launch_restrict_march_node<double>(const Levels &, int, double *,
+                                                 const AdamArgs<double> &, bool, hipStream_t);
+
 template bool launch_restrict_march<float>(const Levels &, int, float *, const AdamArgs<float> &,
                                            bool, int, hipStream_t);
 template bool launch_restrict_march<double>(const Levels &, int, double *,

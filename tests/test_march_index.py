@@ -5,7 +5,9 @@ for the level shapes the tests and the benchmarked workloads use and every
 tile; the lane shifts as the DPP wave shifts give them (lane i gets lane
 i - 1's value, the first lane keeps its own; likewise upwards).  The values
 the walk forms follow the kernel's arithmetic step by step and are compared
-with the oracle's dense T (transposed); every coarse cell is written once."""
+with the oracle's dense T (transposed); every coarse cell is written once.
+The node-based kernel (lanes over the flattened coarse plane, a march of two
+coarse planes per wave) is walked the same way against the node-based T."""
 import numpy as np
 import pytest
 
@@ -284,3 +286,99 @@ def test_the_benchmarked_levels_take_their_tiles():
     assert (p["YR"], p["ZR"], p["W"], p["nseg"]) == (4, 8, 64, 2)
     p = plan((64,) * 3, (32,) * 3)
     assert (p["YR"], p["ZR"], p["W"], p["groups"]) == (2, 1, 32, 2)
+
+
+# ---------------------------------------------------------------- node-based
+def node_plan(fine, coarse):
+    nz, ny, nx = fine
+    cnz, cny, cnx = coarse
+    if nx != 2 * cnx - 1 or ny != 2 * cny - 1 or cnx < 2 or cny < 2:
+        return None
+    spanz = nz > 1
+    if (nz != 2 * cnz - 1) if spanz else (cnz != 1):
+        return None
+    plane = cny * cnx
+    tasks_plane = -(-plane // 64)
+    zr = 2 if spanz else 1
+    if spanz and 5 * ((cnz + 1) // 2) * tasks_plane < 2048:  # five fields, one instance
+        zr = 1
+    return dict(lanes=plane, tasks_plane=-(-plane // 64), zr=zr, nzc=-(-cnz // zr) if spanz else 1,
+                spanz=spanz)
+
+
+def node_walk(g, coarse, P):
+    """The node kernel's lanes over the flattened coarse plane, its loads,
+    shifts, z march and stores, with bounds checks."""
+    nfz, nfy, nfx = g.shape
+    ncz, ncy, ncx = coarse
+    out = np.full(coarse, np.nan)
+    writes = np.zeros(coarse, dtype=np.int64)
+    lane = np.arange(64)
+    for zc in range(P["nzc"]):
+        for tp in range(P["tasks_plane"]):
+            qn = tp * 64 + lane
+            on = qn < P["lanes"]
+            qc = np.where(on, qn, P["lanes"] - 1)
+            Y, J = qc // ncx, qc % ncx
+            has_b = 2 * J + 1 < nfx
+            self_left = (lane == 0) & (J > 0)
+            rows, wy = [], []
+            for k in range(3):
+                r = 2 * Y - 1 + k
+                rows.append(np.clip(r, 0, nfy - 1))
+                wy.append(np.where((r < 0) | (r >= nfy), 0.0, 1.0 if k == 1 else 0.5))
+
+            def plane_value(z):
+                assert 0 <= z < nfz
+                acc = np.zeros(64)
+                for k in range(3):
+                    assert np.all((rows[k] >= 0) & (rows[k] < nfy))
+                    assert np.all(2 * J < nfx)
+                    a = g[z, rows[k], 2 * J]
+                    bb = np.where(has_b, g[z, rows[k], np.minimum(2 * J + 1, nfx - 1)], 0.0)
+                    assert np.all(2 * J[self_left] - 1 >= 0)
+                    e = np.where(self_left, g[z, rows[k], np.maximum(2 * J - 1, 0)], 0.0)
+                    left = prev(bb)
+                    left = np.where(self_left, e, left)
+                    left = np.where(J == 0, 0.0, left)
+                    acc += wy[k] * (a + 0.5 * left + 0.5 * bb)
+                return acc
+
+            def finish(Jz, val):
+                assert 0 <= Jz < ncz
+                out[Jz, Y[on], J[on]] = val[on]
+                np.add.at(writes, (np.full(on.sum(), Jz), Y[on], J[on]), 1)
+
+            if not P["spanz"]:
+                finish(0, plane_value(0))
+                continue
+            Z0 = zc * P["zr"]
+            Z1 = min(Z0 + P["zr"], ncz)
+            odd = plane_value(2 * Z0 - 1) if Z0 > 0 else np.zeros(64)
+            for Jz in range(Z0, Z1):
+                even = plane_value(2 * Jz)
+                nx_ = plane_value(2 * Jz + 1) if 2 * Jz + 1 < nfz else np.zeros(64)
+                finish(Jz, 0.5 * odd + even + 0.5 * nx_)
+                odd = nx_
+    assert np.all(writes == 1)
+    return out
+
+
+NODE_CASES = [(65, 65, 129), (33, 33, 65), (17, 17, 33), (1, 65, 65), (1, 33, 33), (1, 129, 129),
+              (9, 17, 33), (5, 9, 17), (3, 5, 9)]
+
+
+@pytest.mark.parametrize("fine", NODE_CASES)
+def test_node_march_walk(fine):
+    coarse = tuple(1 if n == 1 else (n - 1) // 2 + 1 for n in fine)
+    P = node_plan(fine, coarse)
+    assert P is not None
+    g = np.random.default_rng(sum(fine)).standard_normal(fine)
+    got = node_walk(g, coarse, P)
+    want = g
+    for ax in range(3):
+        if fine[ax] == 1:
+            continue
+        T = mg.node_T_matrix(coarse[ax] - 1)
+        want = np.moveaxis(np.tensordot(T.T, np.moveaxis(want, ax, 0), axes=1), 0, ax)
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-12 * np.abs(want).max())
