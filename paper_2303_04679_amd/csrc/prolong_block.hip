@@ -374,10 +374,14 @@ __global__ __launch_bounds__(256) void prolong_node_kernel(Levels G, int l, cons
   const int nz = G.n[l][0][0], ny = G.n[l][0][1], nx = G.n[l][0][2];
   const int cny = G.n[l + 1][0][1], cnx = G.n[l + 1][0][2];
   const int cells = nz * ny * nx;
-  const int q = e / cells, r = e - q * cells;  // q = instance * fields + field
-  const int inst = q / G.nf, f = q - inst * G.nf;
-  const int zy = r / nx, x = r - zy * nx;
-  const int z = zy / ny, y = zy - z * ny;
+  // below 2^22 the float-reciprocal division (exact there) replaces the
+  // integer divisions, which take tens of instructions each
+  const bool small = total < (1 << 22);
+  const int q = small ? small_div(e, cells, 1.0f / (float)cells) : e / cells;
+  const int r = e - q * cells;  // q = instance * fields + field
+  const int inst = small ? small_div(q, G.nf, 1.0f / (float)G.nf) : q / G.nf, f = q - inst * G.nf;
+  const int zy = small ? small_div(r, nx, 1.0f / (float)nx) : r / nx, x = r - zy * nx;
+  const int z = small ? small_div(zy, ny, 1.0f / (float)ny) : zy / ny, y = zy - z * ny;
   int ix[2], iy[2], iz[2];
   T wx[2], wy[2], wz[2];
   prolong_taps_node(x, ix, wx);
