@@ -303,10 +303,11 @@ int modil_prolong_noalloc(const modil_problem *problem, const void *theta_pack, 
  * compute the same iteration.                                             */
 #define MODIL_OPT_FUSED 0
 /* MODIL_OPT_MARCH (default 1): transfer levels whose fields span every axis
- * they have with the lane-shuffle kernels -- the marching restriction (each
- * fine value loaded once per wave, Adam fused) and the block prolongation
- * (one coarse cell per thread writing its 2^d fine cells); 0 selects the
- * per-cell kernels.  Same results up to the order of the sums.
+ * they have with the lane-shift kernels -- the marching restriction (each
+ * fine value loaded once per wave, Adam fused; node-based levels with lanes
+ * over the flattened coarse plane) and the block prolongation (one coarse
+ * cell per thread writing its 2^d fine cells); 0 selects the per-cell
+ * kernels.  Same results up to the order of the sums.
  * MODIL_OPT_MARCH_TILE (default 0 = automatic): coarse rows and planes per
  * wave of the marching kernel as 64 * rows + planes: rows 2 with planes 1,
  * 2, 4 or 8; rows 4 with planes 1, 2, 4, 8 or 16; rows 8 with planes 4 or 8.
