@@ -615,25 +615,49 @@ struct FineArgs {
   int node;              // node-based T, else cell-based
 };
 
-// (T w_1) at fine cell (y, x) of field f of one instance (2-D tiled engine):
-// the same taps and order as the generic step on a grid without z
+// (T w_1) at fine cell (y, x) of field f of one instance (2-D tiled engine),
+// in two steps so that a caller can issue the loads of many cells before it
+// uses any: tile_prolong_load fetches the (up to) four coarse values, and
+// tile_prolong_sum forms the same taps in the same order as the generic step
+// on a grid without z.
 template <typename T>
-__device__ inline T tile_prolong(const FineArgs<T> &A, int f, int inst, int y, int x) {
-  const T *c = A.w1 + inst * A.w1_inst + A.w1_off[f];
-  const int cnx = A.w1_n[f][1];
+__device__ inline void tile_prolong_taps(const FineArgs<T> &A, int f, int y, int x, int (&ix)[2],
+                                         int (&iy)[2], T (&wx)[2], T (&wy)[2]) {
   const bool sy = A.ff.stride[f][1] != 0;  // the field spans y
-  int ix[2], iy[2];
-  T wx[2], wy[2];
+  iy[0] = iy[1] = 0;
+  wy[0] = wy[1] = T(0);
   if (A.node) {
     prolong_taps_node(x, ix, wx);
     if (sy) prolong_taps_node(y, iy, wy);
   } else {
-    prolong_taps(x, cnx, ix, wx);
+    prolong_taps(x, A.w1_n[f][1], ix, wx);
     if (sy) prolong_taps(y, A.w1_n[f][0], iy, wy);
   }
-  if (!sy) return wx[0] * c[ix[0]] + wx[1] * c[ix[1]];
-  return wy[0] * (wx[0] * c[iy[0] * cnx + ix[0]] + wx[1] * c[iy[0] * cnx + ix[1]]) +
-         wy[1] * (wx[0] * c[iy[1] * cnx + ix[0]] + wx[1] * c[iy[1] * cnx + ix[1]]);
+}
+
+template <typename T>
+__device__ inline void tile_prolong_load(const FineArgs<T> &A, int f, int inst, int y, int x,
+                                         T (&cv)[4]) {
+  const T *c = A.w1 + inst * A.w1_inst + A.w1_off[f];
+  const int cnx = A.w1_n[f][1];
+  int ix[2], iy[2];
+  T wx[2], wy[2];
+  tile_prolong_taps(A, f, y, x, ix, iy, wx, wy);
+  cv[0] = c[iy[0] * cnx + ix[0]];
+  cv[1] = c[iy[0] * cnx + ix[1]];
+  if (A.ff.stride[f][1] != 0) {
+    cv[2] = c[iy[1] * cnx + ix[0]];
+    cv[3] = c[iy[1] * cnx + ix[1]];
+  }
+}
+
+template <typename T>
+__device__ inline T tile_prolong_sum(const FineArgs<T> &A, int f, int y, int x, const T (&cv)[4]) {
+  int ix[2], iy[2];
+  T wx[2], wy[2];
+  tile_prolong_taps(A, f, y, x, ix, iy, wx, wy);
+  if (A.ff.stride[f][1] == 0) return wx[0] * cv[0] + wx[1] * cv[1];
+  return wy[0] * (wx[0] * cv[0] + wx[1] * cv[1]) + wy[1] * (wx[0] * cv[2] + wx[1] * cv[3]);
 }
 
 // ND: the grid's dimension when known at compile time (3 for the 3-D
@@ -945,14 +969,34 @@ __global__ __launch_bounds__(NT) void fine_tile_kernel(FineArgs<T> A, int tiles_
       av[f] = A0.v[k];
     }
   }
-  for (int k = tid; k < FT::UX * FT::UY; k += NT) {
+  // Staging: the thread's staged values (and their level-1 taps) are all
+  // loaded before any is used, from coordinates clamped into the grid so
+  // that every load is in bounds; cells outside the grid then stage zero.
+  constexpr int KS = (FT::UX * FT::UY + NT - 1) / NT;
+  T sv[KS][NF], cv[KS][NF][4];
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    const int k = tid + s * NT;
+    const int xc = min(max(x0 - 2 + k % FT::UX, 0), nx - 1);
+    const int yc = min(max(y0 - 2 + k / FT::UX, 0), ny - 1);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      sv[s][f] = ub[A.ff.off[f] + yc * A.ff.stride[f][1] + xc * A.ff.stride[f][2]];
+      if (A.w1) tile_prolong_load(A, f, inst, A.ff.stride[f][1] ? yc : 0, xc, cv[s][f]);
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    const int k = tid + s * NT;
+    if (KS * NT > FT::UX * FT::UY && k >= FT::UX * FT::UY) break;
     const int X = k % FT::UX, Y = k / FT::UX, x = x0 - 2 + X, y = y0 - 2 + Y;
     const bool in = x >= 0 && x < nx && y >= 0 && y < ny;
+#pragma unroll
     for (int f = 0; f < NF; ++f) {
       T val = T(0);
       if (in) {
-        val = ub[A.ff.off[f] + y * A.ff.stride[f][1] + x * A.ff.stride[f][2]];
-        if (A.w1) val += tile_prolong(A, f, inst, A.ff.stride[f][1] ? y : 0, x);
+        val = sv[s][f];
+        if (A.w1) val += tile_prolong_sum(A, f, A.ff.stride[f][1] ? y : 0, x, cv[s][f]);
       }
       Ut[f][Y][X] = val;
     }

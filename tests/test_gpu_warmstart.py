@@ -6,7 +6,7 @@ A network trained on 96 cold-start solutions (its own forward and backward
 kernels, Adam on the GPU) starts 16 held-out instances from predicted coarse
 levels; the same iteration from zero is the baseline.  Both runs use the same
 step schedule; the metric is the first checked iteration with residual
-r <= 1e-5.  The fallback (cold-start mODIL as the judge) keeps a prediction
+r <= 1e-5.  The fallback (cold-start mODIL as the arbiter) keeps a prediction
 only where it lowers the starting residual and, at a checkpoint, only where
 the warm run's residual is below the cold run's.
 """
