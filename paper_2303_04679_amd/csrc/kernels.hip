@@ -238,22 +238,32 @@ __device__ inline void field_index(const Levels &G, int l, int f, int e, int (&i
   small_index(e, ny, nx, 1.0f / (float)ny, 1.0f / (float)nx, i);
 }
 
-// dst[e] = src[e] for e < n, global -> LDS, eight values in flight per thread
+// dst[e] = src[e] for lo <= e < hi, global -> LDS, up to eight values in
+// flight per thread.  A round takes K = 1, 2, 4 or 8 slots, chosen per wave
+// (enough for its first lane, whose elements are the wave's smallest), and a
+// lane past hi loads and stores element hi - 1 (the same value to the same
+// place): each round is straight-line code whose K loads are all issued
+// before the first is waited for.
+template <int K, typename T>
+__device__ inline void tail_copy_round(T *dst, const T *__restrict__ src, int e0, int bd, int hi) {
+  T v[K];
+#pragma unroll
+  for (int u = 0; u < K; ++u) v[u] = src[min(e0 + u * bd, hi - 1)];
+#pragma unroll
+  for (int u = 0; u < K; ++u) dst[min(e0 + u * bd, hi - 1)] = v[u];
+}
+
 template <typename T>
 __device__ inline void tail_copy_in(T *dst, const T *__restrict__ src, int lo, int hi) {
-  constexpr int kU = 8;
-  for (int e0 = lo + (int)threadIdx.x; e0 < hi; e0 += kU * (int)blockDim.x) {
-    T v[kU];
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int e = e0 + u * (int)blockDim.x;
-      v[u] = e < hi ? src[e] : T(0);
-    }
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int e = e0 + u * (int)blockDim.x;
-      if (e < hi) dst[e] = v[u];
-    }
+  const int bd = (int)blockDim.x;
+  const int lane0 = __builtin_amdgcn_readfirstlane((int)threadIdx.x);  // the wave's first lane
+  for (int r = 0; lo + lane0 + r < hi; r += 8 * bd) {
+    const int e0 = lo + (int)threadIdx.x + r;
+    const int need = (hi - (lo + lane0 + r) + bd - 1) / bd;  // slots of the first lane
+    if (need > 4) tail_copy_round<8>(dst, src, e0, bd, hi);
+    else if (need > 2) tail_copy_round<4>(dst, src, e0, bd, hi);
+    else if (need > 1) tail_copy_round<2>(dst, src, e0, bd, hi);
+    else tail_copy_round<1>(dst, src, e0, bd, hi);
   }
 }
 
@@ -284,17 +294,20 @@ __global__ __launch_bounds__(1024) void horner_tail_kernel(Levels G, int l_stop,
     const int e = h_lo + tid + u * bd;
     pth[u] = e < h_hi ? theta[bstop + e] : T(0);
   }
-  T *hb[2] = {sm, sm + field_cells(G, l_stop + 1, f)};
+  // the two LDS buffers, chosen by a select (not an indexed array) so that
+  // the compiler keeps their accesses as LDS instructions; a generic (flat)
+  // access would wait on global stores as well
+  T *const hb0 = sm, *const hb1 = sm + field_cells(G, l_stop + 1, f);
   {
     const int l = G.L - 1;
     const T *src = theta + G.off[l] + inst * G.stride[l] + G.foff[l][f];
-    tail_copy_in(hb[(l - l_stop - 1) & 1], src, 0, field_cells(G, l, f));
+    tail_copy_in(((l - l_stop - 1) & 1) ? hb1 : hb0, src, 0, field_cells(G, l, f));
   }
   lds_barrier();
   for (int l = G.L - 2; l >= l_stop; --l) {
     const bool last = l == l_stop;
-    T *dst = hb[(l - l_stop - 1) & 1];
-    const T *cs = hb[(l - l_stop) & 1];
+    T *dst = ((l - l_stop - 1) & 1) ? hb1 : hb0;
+    const T *cs = ((l - l_stop) & 1) ? hb1 : hb0;
     const int base = G.off[l] + inst * G.stride[l] + G.foff[l][f];
     const int n1 = G.n[l][f][1], n2 = G.n[l][f][2];
     const float r1 = 1.0f / (float)n1, r2 = 1.0f / (float)n2;
@@ -352,14 +365,20 @@ __global__ __launch_bounds__(kBlock) void restrict_kernel(Levels G, int l, T *g,
 // in LDS: src has dims n (z, y, x), dst the same dims with n[a] replaced by
 // the coarse extent c.  T^T gathers fine 2J-1 .. 2J+2 with 1/4, 3/4, 3/4,
 // 1/4 and the end rows' 5/4, -1/4.  Applied once per spanned axis it is the
-// tensor-product T^T of one level.
+// tensor-product T^T of one level.  All six slots are read at once, at
+// indices clamped into the row, and a slot that does not apply adds zero
+// times its value: the sum takes the same terms in the same order as the
+// conditional form, with one LDS wait instead of up to five.  The index
+// split uses the hardware reciprocal (within one ulp, which small_index
+// allows).
 template <typename T>
 __device__ inline void tail_restrict_pass(const T *__restrict__ src, T *__restrict__ dst,
                                           const int (&n)[3], int a, int c) {
   int m[3] = {n[0], n[1], n[2]};
   m[a] = c;
   const int total = m[0] * m[1] * m[2];
-  const float r1 = 1.0f / (float)m[1], r2 = 1.0f / (float)m[2];
+  if ((int)threadIdx.x >= total) return;
+  const float r1 = __builtin_amdgcn_rcpf((float)m[1]), r2 = __builtin_amdgcn_rcpf((float)m[2]);
   const int sa = a == 2 ? 1 : (a == 1 ? n[2] : n[1] * n[2]);  // stride of axis a in src
   const int nf = n[a];
   for (int e = threadIdx.x; e < total; e += blockDim.x) {
@@ -368,12 +387,14 @@ __device__ inline void tail_restrict_pass(const T *__restrict__ src, T *__restri
     const int J = i[a];
     i[a] = 0;
     const T *s = src + (i[0] * n[1] + i[1]) * n[2] + i[2];
-    T acc = (J == 0 ? T(1.25) : T(0.75)) * s[2 * J * sa] +
-            (J == c - 1 ? T(1.25) : T(0.75)) * s[(2 * J + 1) * sa];
-    if (J >= 1) acc += T(0.25) * s[(2 * J - 1) * sa];
-    if (J <= c - 2) acc += T(0.25) * s[(2 * J + 2) * sa];
-    if (J == 1) acc -= T(0.25) * s[0];
-    if (J == c - 2) acc -= T(0.25) * s[(nf - 1) * sa];
+    const T x0 = s[2 * J * sa], x1 = s[(2 * J + 1) * sa];
+    const T xm = s[max(2 * J - 1, 0) * sa], xp = s[min(2 * J + 2, nf - 1) * sa];
+    const T xa = s[0], xb = s[(nf - 1) * sa];
+    T acc = (J == 0 ? T(1.25) : T(0.75)) * x0 + (J == c - 1 ? T(1.25) : T(0.75)) * x1;
+    acc += (J >= 1 ? T(0.25) : T(0)) * xm;
+    acc += (J <= c - 2 ? T(0.25) : T(0)) * xp;
+    acc += (J == 1 ? T(-0.25) : T(0)) * xa;
+    acc += (J == c - 2 ? T(-0.25) : T(0)) * xb;
     dst[e] = acc;
   }
 }
@@ -393,9 +414,9 @@ __device__ inline void tail_restrict_pass(const T *__restrict__ src, T *__restri
 // updated theta is kept in LDS at element H.toff: the part's slice of level
 // l_stop, then the levels above it in turn; the levels this block produces
 // are stored there by their Adam update, the others (final before the
-// launch) are loaded there at the start.  Reads of global memory are issued
-// early: level l_lo of g and the carried theta at the start, each level's
-// Adam state before its passes.
+// launch) are loaded there at the start.  Every read of global memory is
+// issued at the start: level l_lo of g, the carried theta and the Adam state
+// of every level produced.
 template <typename T>
 struct CarryTail {
   T *w = nullptr;
@@ -435,22 +456,29 @@ __global__ __launch_bounds__(kTailThreads) void restrict_tail_kernel(Levels G, i
   const int h_lo = (int)((long)n_stop * part / H.parts);
   const int h_hi = (int)((long)n_stop * (part + 1) / H.parts);
 
-  // Adam state of the first level produced
+  // The levels produced, l_lo+1 .. L-1, hold at most kTailR * blockDim.x
+  // values together (the host's choice of l_lo); a thread owns the values
+  // tid + u * blockDim.x of their concatenation, and the Adam state of all of
+  // them is loaded here, before the block stores anything: a wait for a load
+  // issued after a store would also wait for the store.
   T th[kTailR], mo[kTailR], vo[kTailR];
-  auto adam_load = [&](int l) {
-    const int base = field_base(G, l, inst, f), n = field_cells(G, l, f);
 #pragma unroll
-    for (int u = 0; u < kTailR; ++u) {
-      const int e = tid + u * bd;
-      th[u] = mo[u] = vo[u] = T(0);
-      if (ADAM && e < n) {
-        th[u] = A.th_in[base + e];
-        mo[u] = A.m[base + e];
-        vo[u] = A.v[base + e];
+  for (int u = 0; u < kTailR; ++u) {
+    th[u] = mo[u] = vo[u] = T(0);
+    if (!ADAM) continue;
+    int e = tid + u * bd;
+    for (int j = l_lo + 1; j < G.L; ++j) {
+      const int n = field_cells(G, j, f);
+      if (e < n) {
+        const int k = field_base(G, j, inst, f) + e;
+        th[u] = A.th_in[k];
+        mo[u] = A.m[k];
+        vo[u] = A.v[k];
+        break;
       }
+      e -= n;
     }
-  };
-  adam_load(l_lo + 1);
+  }
   // level l_lo of g, and the theta of the carried levels l_stop .. l_lo
   tail_copy_in(sm, g + field_base(G, l_lo, inst, f), 0, field_cells(G, l_lo, f));
   const int slice = h_hi - h_lo;
@@ -468,9 +496,12 @@ __global__ __launch_bounds__(kTailThreads) void restrict_tail_kernel(Levels G, i
       }
     }
   lds_barrier();
+  // every load above has returned (vmcnt 0; the other counters left at their
+  // maximum), so no wait inside the level loop includes the stores it issues
+  __builtin_amdgcn_s_waitcnt(0x0F70);
   T *cur = sm, *oth = sm + cap0;
+  int cat = 0;  // offset of level l + 1 in the concatenation
   for (int l = l_lo; l + 1 < G.L; ++l) {
-    if (l > l_lo) adam_load(l + 1);
     if (!G.node) {
       // cell-based: T^T one axis at a time (4-6 taps per output and pass)
       int n[3] = {G.n[l][f][0], G.n[l][f][1], G.n[l][f][2]};
@@ -506,8 +537,8 @@ __global__ __launch_bounds__(kTailThreads) void restrict_tail_kernel(Levels G, i
     const bool keep = carry && l + 1 > H.l_stop, keep_slice = carry && l + 1 == H.l_stop;
 #pragma unroll
     for (int u = 0; u < kTailR; ++u) {
-      const int e = tid + u * bd;
-      if (e >= nl) continue;
+      const int e = tid + u * bd - cat;
+      if (e < 0 || e >= nl) continue;
       const T val = cur[e];
       if (lead) g[base + e] = val;
       if (ADAM) {
@@ -523,6 +554,7 @@ __global__ __launch_bounds__(kTailThreads) void restrict_tail_kernel(Levels G, i
         if (keep_slice && e >= h_lo && e < h_hi) tl[e - h_lo] = tn;
       }
     }
+    cat += nl;
     if (keep) toff += nl;
     if (keep_slice) toff = slice;
     // the next level's first pass writes oth, which no thread reads any more
@@ -531,13 +563,13 @@ __global__ __launch_bounds__(kTailThreads) void restrict_tail_kernel(Levels G, i
   lds_barrier();
   // Horner tail; level l > l_stop sits in LDS buffer (l - l_stop - 1) & 1 at
   // the start of the LDS, the restriction's regions being free
-  T *hb[2] = {sm, sm + field_cells(G, H.l_stop + 1, f)};
+  T *const hb0 = sm, *const hb1 = sm + field_cells(G, H.l_stop + 1, f);
   for (int l = G.L - 1; l >= H.l_stop; --l) {
     const bool last = l == H.l_stop;
     const int n = field_cells(G, l, f);
     if (!last) toff -= n;  // now the offset of level l in tl
-    T *dst = hb[(l - H.l_stop - 1) & 1];
-    const T *cs = hb[(l - H.l_stop) & 1];
+    T *dst = ((l - H.l_stop - 1) & 1) ? hb1 : hb0;  // selects keep them LDS accesses
+    const T *cs = ((l - H.l_stop) & 1) ? hb1 : hb0;
     const int base = field_base(G, l, inst, f);
     const bool top = l == G.L - 1;
     const int n1 = G.n[l][f][1], n2 = G.n[l][f][2];
