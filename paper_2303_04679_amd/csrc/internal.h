@@ -75,6 +75,16 @@ __device__ inline float adam_theta<float>(float th, float m, float v, float step
 // The memory clobber keeps the compiler from moving memory accesses across it.
 __device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
+// Makes a loaded value count as used at this point: its load is issued
+// before here and waited for here.  Keeps the compiler from sinking a load
+// past a barrier to its first real use, where the wait for it (one counter
+// tracks loads and stores in issue order) would also cover later loads and
+// stores.
+template <typename T>
+__device__ inline void settle(const T &v) {
+  asm volatile("" ::"v"(v));
+}
+
 // e / m for 0 <= e < 2^22 and m >= 1 with rcp = 1 / m (rounded): e is exact
 // in float and the product is within 2^-23 relative of e / m, i.e. less than
 // 1/2 from it, so the truncated quotient is off by at most one, which one

@@ -70,6 +70,19 @@ __global__ __launch_bounds__(256) void prolong_block_kernel(Levels G, int l, con
   const int lo = (SEG && gl == 0 && cx > 0) ? cx - 1 : cx;
   const int hi = (SEG && gl == W - 1 && cx < cnx - 1) ? cx + 1 : cx;
 
+  // theta of the fine cells written, loaded with the coarse rows (an
+  // inactive lane reads row 0's, which exist) and taken before the shuffles:
+  // all loads go out in one round, and none is waited for after a store
+  constexpr int NEZ = SPANZ ? 2 : 1;
+  P2 th[NEZ][2];
+#pragma unroll
+  for (int ez = 0; ez < NEZ; ++ez)
+#pragma unroll
+    for (int ey = 0; ey < 2; ++ey) {
+      const int z = SPANZ ? 2 * cz + ez : cz, y = 2 * cy + ey;
+      th[ez][ey] = *reinterpret_cast<const P2 *>(theta + fbase + ((long)z * ny + y) * nx + 2 * cx);
+    }
+
   // x-interpolated coarse rows: X[dz][dy][e] for the fine x cells 2cx + e
   constexpr int NZ = SPANZ ? 3 : 1;
   T c[NZ][3], el[NZ][3], eh[NZ][3];
@@ -81,6 +94,13 @@ __global__ __launch_bounds__(256) void prolong_block_kernel(Levels G, int l, con
       c[a][b] = r[cx];
       el[a][b] = SEG ? r[lo] : T(0);
       eh[a][b] = SEG ? r[hi] : T(0);
+    }
+#pragma unroll
+  for (int ez = 0; ez < NEZ; ++ez)
+#pragma unroll
+    for (int ey = 0; ey < 2; ++ey) {
+      settle(th[ez][ey].x);
+      settle(th[ez][ey].y);
     }
   T X[NZ][3][2];
 #pragma unroll
@@ -99,7 +119,7 @@ __global__ __launch_bounds__(256) void prolong_block_kernel(Levels G, int l, con
     }
   if (!active) return;
 #pragma unroll
-  for (int ez = 0; ez < (SPANZ ? 2 : 1); ++ez)
+  for (int ez = 0; ez < NEZ; ++ez)
 #pragma unroll
     for (int ey = 0; ey < 2; ++ey) {
       T v[2];
@@ -115,10 +135,9 @@ __global__ __launch_bounds__(256) void prolong_block_kernel(Levels G, int l, con
       }
       const int z = SPANZ ? 2 * cz + ez : cz, y = 2 * cy + ey;
       const long o = fbase + ((long)z * ny + y) * nx + 2 * cx;
-      const P2 th = *reinterpret_cast<const P2 *>(theta + o);
       P2 out;
-      out.x = th.x + v[0];
-      out.y = th.y + v[1];
+      out.x = th[ez][ey].x + v[0];
+      out.y = th[ez][ey].y + v[1];
       *reinterpret_cast<P2 *>(dst + o) = out;
     }
   (void)nz;
@@ -202,12 +221,21 @@ __global__ __launch_bounds__(kP2Threads) void prolong2_kernel(Levels G, int l, i
       tf[ez][ey][0] = t2.x;
       tf[ez][ey][1] = t2.y;
     }
+  // every load above is issued before the first is waited for: the level-l
+  // values are taken here, with the coarse planes, in one round trip
+#pragma unroll
+  for (int ez = 0; ez < 2; ++ez)
+#pragma unroll
+    for (int ey = 0; ey < 2; ++ey) {
+      settle(tf[ez][ey][0]);
+      settle(tf[ez][ey][1]);
+    }
 #pragma unroll
   for (int u = 0; u < kC; ++u) {
     const int e = tid + u * kP2Threads;
     if (e < ncs) Cs[e] = cv[u];
   }
-  lds_barrier();  // the theta loads stay in flight
+  lds_barrier();
   // level-(l+1) slab: theta_{l+1} + T w_{l+2}
 #pragma unroll
   for (int u = 0; u < kM; ++u) {
