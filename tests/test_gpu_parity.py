@@ -121,9 +121,12 @@ def test_adam(dtype):
 @pytest.mark.parametrize("op,dims,L", [("burgers", (32, 32), 4), ("heat", (32, 32), 4),
                                        ("ns3d", (8, 8, 16), 3), ("cavity", (32, 32), 4),
                                        ("poisson_node", (32, 32), 4), ("cavity_node", (32, 32), 4),
-                                       ("ns3d_node", (8, 8, 16), 3)])
+                                       ("ns3d_node", (8, 8, 16), 3), ("ns3d", (32, 32, 64), 4)])
 def test_step_sequence_f64(op, dims, L):
-    """Three modil_step calls (ping-pong theta) follow the oracle's loss, gradient and Adam."""
+    """Three modil_step calls (ping-pong theta) follow the oracle's loss, gradient and Adam.
+    The 32 x 32 x 64 channel starts its restriction tail at a level of 8192
+    cells (copied into LDS in rounds of eight loads per thread) and updates
+    three levels there."""
     need_gpu()
     spec = case(op, dims, L, seed=3)
     lv = _levels(spec, 4)
