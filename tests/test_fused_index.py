@@ -66,8 +66,14 @@ CASES = [((24, 36, 60), 1, 3), ((16, 28, 24), 1, 3), ((64, 16, 32), 1, 4), ((8, 
 
 @pytest.mark.parametrize("dims,batch,L", CASES)
 @pytest.mark.parametrize("nf", [5, 4])
-def test_fused_kernel_indices(dims, batch, L, nf):
+@pytest.mark.parametrize("elem", [4, 8])
+def test_fused_kernel_indices(dims, batch, L, nf, elem):
+    """Element size 8 is the FP64 build of the same source (switched off in
+    the library): its byte offsets stay in bounds too at the sizes where it
+    was tested, so no out-of-range access explains its wrong results."""
     nz, ny, nx = dims
+    if elem == 8 and nf * nz * ny * nx * elem >= 2 ** 32:
+        pytest.skip("beyond the 32-bit offsets an FP64 field set would need")
     tz, nzt, ntx, nty = tiles(nz, ny, nx, batch)
     ntiles = nzt * ntx * nty
     tpx = -(-ntiles // NS_XCD)
@@ -86,7 +92,7 @@ def test_fused_kernel_indices(dims, batch, L, nf):
     assert np.array_equal(np.sort(pos), np.arange(NST_X * NST_Y))
     fsize = nz * ny * nx
     plane = nx * ny
-    assert nf * fsize * 4 < 2 ** 32            # the host's 32-bit offset condition
+    assert nf * fsize * elem < 2 ** 32         # the host's 32-bit offset condition
     owned = np.zeros(batch * nzt * ny * nx, np.int64)
     for t in range(ntiles):
         bx, by, bz = t % ntx, (t // ntx) % nty, t // (ntx * nty)
@@ -110,10 +116,10 @@ def test_fused_kernel_indices(dims, batch, L, nf):
         owned_idx = bz * plane + col[own]
         np.add.at(owned, owned_idx, 1)  # instance 0's tiles; the others are the same
         # global byte offsets: column in the last field plus the farthest plane
-        fo = ((nf - 1) * fsize + np.where(in_xy, col, 0)) * 4
+        fo = ((nf - 1) * fsize + np.where(in_xy, col, 0)) * elem
         planes = [z for z in range(z0 - 2, z1 + 2) if 0 <= z < nz]
-        assert np.all(fo + max(planes) * plane * 4 < nf * fsize * 4)
-        assert np.all(fo + max(planes) * plane * 4 < 2 ** 32)
+        assert np.all(fo + max(planes) * plane * elem < nf * fsize * elem)
+        assert np.all(fo + max(planes) * plane * elem < 2 ** 32)
         if L > 1:
             nc = (nz // 2, ny // 2, nx // 2)
             cxb, cyb = (ox >> 1) - 1, (oy >> 1) - 1
@@ -137,16 +143,16 @@ def test_fused_kernel_indices(dims, batch, L, nf):
             cy, cx = cyb + rem // NCT_X, cxb + rem % NCT_X
             cin = (cy >= 0) & (cy < nc[1]) & (cx >= 0) & (cx < nc[2])
             csize = nc[0] * nc[1] * nc[2]
-            co = (f[cin] * csize + cy[cin] * nc[2] + cx[cin]) * 4
-            assert np.all(co + (nc[0] - 1) * nc[1] * nc[2] * 4 < nf * csize * 4)
+            co = (f[cin] * csize + cy[cin] * nc[2] + cx[cin]) * elem
+            assert np.all(co + (nc[0] - 1) * nc[1] * nc[2] * elem < nf * csize * elem)
             # z sums of the gradient (optional path): slots and offsets
             hz, kz0 = tz // 2, z0 // 2 - 1
             nkz = hz + 2
             for q in range(z0, z1):
                 for K in prolong_taps(np.array([q]), nc[0]):
                     assert 0 <= int(K[0]) - kz0 < nkz
-            zmax = ((nkz - 1) * plane + (nf - 1) * nkz * plane + col[own]) * 4
-            assert np.all(zmax < nf * nkz * plane * 4) and np.all(zmax < 2 ** 32)
+            zmax = ((nkz - 1) * plane + (nf - 1) * nkz * plane + col[own]) * elem
+            assert np.all(zmax < nf * nkz * plane * elem) and np.all(zmax < 2 ** 32)
     # every cell of every chunk owned exactly once
     assert np.all(owned[:nzt * plane] == 1)
 
