@@ -451,6 +451,14 @@ __global__ __launch_bounds__(kTailThreads) void restrict_tail_kernel(Levels G, i
   const int bd = blockDim.x, tid = threadIdx.x;
   const bool carry = ADAM && H.w != nullptr;
   T *const tl = sm + H.toff;  // updated theta of levels l_stop .. L-1 (carry)
+  // this field's extents (z, y, x), cell count and pack offset on every level,
+  // read once into LDS: the level loops index them by a run-time level, which
+  // from the kernel arguments takes a chain of scalar loads per level
+  __shared__ int geo[kMaxL][5];
+  if (tid < G.L * 5) {
+    const int gl = tid / 5, gk = tid - 5 * gl;
+    geo[gl][gk] = gk < 3 ? G.n[gl][f][gk] : (gk == 3 ? field_cells(G, gl, f) : field_base(G, gl, inst, f));
+  }
   // this part's slice of the largest Horner level
   const int n_stop = carry ? field_cells(G, H.l_stop, f) : 0;
   const int h_lo = (int)((long)n_stop * part / H.parts);
@@ -504,9 +512,9 @@ __global__ __launch_bounds__(kTailThreads) void restrict_tail_kernel(Levels G, i
   for (int l = l_lo; l + 1 < G.L; ++l) {
     if (!G.node) {
       // cell-based: T^T one axis at a time (4-6 taps per output and pass)
-      int n[3] = {G.n[l][f][0], G.n[l][f][1], G.n[l][f][2]};
+      int n[3] = {geo[l][0], geo[l][1], geo[l][2]};
       for (int a = 2; a >= 0; --a) {
-        const int c = G.n[l + 1][f][a];
+        const int c = geo[l + 1][a];
         if (c == n[a]) continue;  // the field does not span this axis
         tail_restrict_pass(cur, oth, n, a, c);
         n[a] = c;
@@ -533,7 +541,7 @@ __global__ __launch_bounds__(kTailThreads) void restrict_tail_kernel(Levels G, i
       lds_barrier();
     }
     // cur holds g_{l+1}
-    const int base = field_base(G, l + 1, inst, f), nl = field_cells(G, l + 1, f);
+    const int base = geo[l + 1][4], nl = geo[l + 1][3];
     const bool keep = carry && l + 1 > H.l_stop, keep_slice = carry && l + 1 == H.l_stop;
 #pragma unroll
     for (int u = 0; u < kTailR; ++u) {
@@ -566,13 +574,13 @@ __global__ __launch_bounds__(kTailThreads) void restrict_tail_kernel(Levels G, i
   T *const hb0 = sm, *const hb1 = sm + field_cells(G, H.l_stop + 1, f);
   for (int l = G.L - 1; l >= H.l_stop; --l) {
     const bool last = l == H.l_stop;
-    const int n = field_cells(G, l, f);
+    const int n = geo[l][3];
     if (!last) toff -= n;  // now the offset of level l in tl
     T *dst = ((l - H.l_stop - 1) & 1) ? hb1 : hb0;  // selects keep them LDS accesses
     const T *cs = ((l - H.l_stop) & 1) ? hb1 : hb0;
-    const int base = field_base(G, l, inst, f);
+    const int base = geo[l][4];
     const bool top = l == G.L - 1;
-    const int n1 = G.n[l][f][1], n2 = G.n[l][f][2];
+    const int n1 = geo[l][1], n2 = geo[l][2];
     const float r1 = 1.0f / (float)n1, r2 = 1.0f / (float)n2;
     for (int e = tid + (last ? h_lo : 0); e < (last ? h_hi : n); e += bd) {
       T val = last ? tl[e - h_lo] : tl[toff + e];
