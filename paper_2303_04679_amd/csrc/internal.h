@@ -105,9 +105,38 @@ __device__ inline void small_index(int e, int n1, int n2, float r1, float r2, in
   i[1] = q - i[0] * n1;
 }
 
+// x of the lane that DPP control CTRL names, on the rows and banks (groups of
+// four lanes) that ROW and BANK enable; 0 elsewhere.  A double moves as its two
+// 32-bit halves under the same control.
+template <int CTRL, int ROW, int BANK>
+__device__ inline double dpp_take(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROW, BANK, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW, BANK, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Sum of x over the 64 lanes of a wave, in a fixed order, left in lane 63
+// (other lanes hold partial sums).  Within each row of 16 lanes: every lane
+// adds the three before it (row shifts 1, 2, 3 of x), then the partial four
+// (shift 4, upper three banks) and eight (shift 8, upper two banks) before
+// it, so lane 15 of the row holds the row's sum; then lane 15 of rows 0 and 2
+// is added across to rows 1 and 3, and lane 31 to rows 2 and 3.  Each step is
+// one DPP move per 32-bit half and one add, with no LDS round trip.
+__device__ inline double wave_sum(double x) {
+  double s = x + dpp_take<0x111, 0xf, 0xf>(x);  // row_shr:1
+  s += dpp_take<0x112, 0xf, 0xf>(x);           // row_shr:2
+  s += dpp_take<0x113, 0xf, 0xf>(x);           // row_shr:3
+  s += dpp_take<0x114, 0xf, 0xe>(s);           // row_shr:4, banks 1-3
+  s += dpp_take<0x118, 0xf, 0xc>(s);           // row_shr:8, banks 2-3
+  s += dpp_take<0x142, 0xa, 0xf>(s);           // row_bcast:15 into rows 1 and 3
+  s += dpp_take<0x143, 0xc, 0xf>(s);           // row_bcast:31 into rows 2 and 3
+  return s;
+}
+
 // Fixed-order final sum of one instance's FP64 loss partials: slots [0, n_a)
 // and [off_b, off_b + n_b) of src.  The first kBlock threads of the calling
-// block add kBlock-strided slots, then each wave's lanes by shuffles, then the
+// block add kBlock-strided slots, then each wave's lanes (wave_sum), then the
 // waves in order, so every caller sums in the same order.  Writes the kTerms
 // sums to terms and raises flag on a non-finite one.  Every thread of the
 // block calls it (it holds a barrier); the block has at least kBlock threads.
@@ -122,9 +151,8 @@ __device__ inline void final_terms(const double *src, long n_a, long off_b, long
       const long slot = b < n_a ? b : off_b + (b - n_a);
       for (int k = 0; k < kTerms; ++k) t[k] += src[slot * kTerms + k];
     }
-  for (int k = 0; k < kTerms; ++k)
-    for (int off = 32; off >= 1; off >>= 1) t[k] += __shfl_down(t[k], off, 64);
-  if (tid < kBlock && (tid & 63) == 0)
+  for (int k = 0; k < kTerms; ++k) t[k] = wave_sum(t[k]);
+  if (tid < kBlock && (tid & 63) == 63)
     for (int k = 0; k < kTerms; ++k) sh[tid >> 6][k] = t[k];
   __syncthreads();
   if (tid < kTerms) {

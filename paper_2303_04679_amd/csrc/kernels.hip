@@ -614,13 +614,9 @@ __global__ __launch_bounds__(kBlock) void adam_kernel(const T *__restrict__ th_i
 // ------------------------------------------------------- block-sum of terms
 __device__ inline void block_terms(double (&t)[kTerms], double *out) {
   __shared__ double sh[kBlock / 64][kTerms];
-  for (int k = 0; k < kTerms; ++k) {
-    double x = t[k];
-    for (int off = 32; off >= 1; off >>= 1) x += __shfl_down(x, off, 64);
-    t[k] = x;
-  }
+  for (int k = 0; k < kTerms; ++k) t[k] = wave_sum(t[k]);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0)
+  if (lane == 63)
     for (int k = 0; k < kTerms; ++k) sh[wave][k] = t[k];
   __syncthreads();
   if (threadIdx.x < kTerms) {
@@ -927,9 +923,8 @@ template <int NT>
 __device__ inline void block_terms_n(double (&t)[kTerms], double *out) {
   static_assert(NT % 64 == 0 && NT <= 1024, "whole waves");
   __shared__ double sh[NT / 64][kTerms];
-  for (int k = 0; k < kTerms; ++k)
-    for (int off = 32; off >= 1; off >>= 1) t[k] += __shfl_down(t[k], off, 64);
-  if ((threadIdx.x & 63) == 0)
+  for (int k = 0; k < kTerms; ++k) t[k] = wave_sum(t[k]);
+  if ((threadIdx.x & 63) == 63)
     for (int k = 0; k < kTerms; ++k) sh[threadIdx.x >> 6][k] = t[k];
   __syncthreads();
   if (threadIdx.x < kTerms) {
