@@ -110,9 +110,8 @@ __global__ __launch_bounds__(kLbBlock) void multidot_kernel(MultiDotArgs<T> A) {
   for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int k = 0; k < kLbChunk; ++k) {
-      double v = acc[r][k];
-      for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-      if (lane == 0) sh[wave][r][k] = v;
+      const double v = wave_sum(acc[r][k]);  // fixed order, in lane 63
+      if (lane == 63) sh[wave][r][k] = v;
     }
   __syncthreads();
   if (threadIdx.x < 2 * kLbChunk) {
@@ -132,8 +131,8 @@ __global__ __launch_bounds__(256) void dot_reduce_kernel(const double *__restric
   for (int b = threadIdx.x; b < blocks; b += 256)
     v += partials[(((long)chunk * blocks + b) * 2 + r) * kLbChunk + k];
   __shared__ double sh[4];
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  v = wave_sum(v);  // fixed order, in lane 63
+  if ((threadIdx.x & 63) == 63) sh[threadIdx.x >> 6] = v;
   __syncthreads();
   if (threadIdx.x == 0) out[r * kLbMaxLeft + l] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
 }

@@ -673,13 +673,10 @@ __global__ __launch_bounds__(NS_THREADS, NS_WAVES_PER_EU) void ns3d_fused_kernel
         }
       }
   }
-  // ---- block sum of the loss partials (fixed order)
-  for (int k = 0; k < kTerms; ++k) {
-    double v = part[k];
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_down(v, off, 64);
-    part[k] = v;
-  }
-  if ((tid & 63) == 0)
+  // ---- block sum of the loss partials (fixed order: each wave's by
+  // wave_sum, left in its lane 63, then the waves in order)
+  for (int k = 0; k < kTerms; ++k) part[k] = wave_sum(part[k]);
+  if ((tid & 63) == 63)
     for (int k = 0; k < kTerms; ++k) red[tid >> 6][k] = part[k];
   __syncthreads();
   if (tid < kTerms) {
