@@ -69,8 +69,12 @@ def test_loss_grad(op, dims, L, dtype):
 
 @pytest.mark.parametrize("op,dims,L", [("poisson", (48, 32), 4), ("heat", (32, 64), 4),
                                        ("ns3d", (8, 16, 8), 3), ("poisson_node", (48, 32), 4),
-                                       ("poisson_node", (16, 8, 16), 3)])
+                                       ("poisson_node", (16, 8, 16), 3),
+                                       ("poisson", (16, 512), 3), ("poisson", (4, 8, 256), 2)])
 def test_prolong_and_restrict(op, dims, L):
+    """Horner prolongation and M_L^T against the oracle.  The last two shapes
+    have coarse rows of 128 and 256 cells, which the block prolongation and
+    the marching restriction take in several 64-lane segments."""
     need_gpu()
     spec = case(op, dims, L, seed=1)
     lv = _levels(spec, 2)
