@@ -144,3 +144,29 @@ def test_residual_metric_averages_over_equations():
     r = ops.residual_metric(spec, _levels(spec, [z + 1.0, z, z, z]))
     V = math.prod(L / n for L, n in zip(lengths, dims))
     assert r == pytest.approx(V * math.sqrt(sum(x * x for x in f) / 4.0), rel=1e-13)
+
+
+@pytest.mark.parametrize("op,dims", [("cavity", (8, 12)), ("ns3d", (4, 8, 6)), ("heat", (8, 6)),
+                                     ("cavity_node", (8, 6))])
+def test_data_only_loss_on_one_level(op, dims):
+    """With every weight but the data weight at zero and one level (M is the
+    identity), the loss is the weighted sum of squared misfits at the
+    measured points and its gradient 2 w (u - y) there, zero elsewhere:
+    brute force over the measurement list."""
+    from tests.oracle_cases import case, random_levels
+    spec = case(op, dims, 1, seed=3)
+    spec.weights = {t: 0.0 for t in spec.weights}
+    spec.weights["data"] = 1.0
+    spec.meas = [m for m in spec.meas if m[1] == "data"]
+    lv = random_levels(spec, 4)
+    terms, grad = ops.loss_and_grad(spec, lv)
+    loss = 0.0
+    want = [np.zeros_like(np.asarray(x)) for x in lv[0]]
+    for fi, _, idx, vals, wt in spec.meas:
+        u = np.asarray(lv[0][fi]).reshape(-1)[np.asarray(idx)]
+        loss += wt * float(((u - vals) ** 2).sum())
+        want[fi].reshape(-1)[np.asarray(idx)] += 2.0 * wt * (u - vals)
+    assert terms["pde"] == 0.0 and terms["reg"] == 0.0 and terms["bc"] == 0.0
+    assert terms["data"] == pytest.approx(loss, rel=1e-14)
+    for g, w in zip(grad[0], want):
+        np.testing.assert_allclose(g, w, rtol=0, atol=1e-14)
