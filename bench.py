@@ -232,7 +232,7 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs the mODIL iteration on one GPU only; "
+        print("bench.py: the mODIL iteration runs on one GPU only; "
               "multi-GPU domain decomposition is not implemented.", file=sys.stderr)
         sys.exit(2)
     import torch
