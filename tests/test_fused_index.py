@@ -61,7 +61,8 @@ CASES = [((24, 36, 60), 1, 3), ((16, 28, 24), 1, 3), ((64, 16, 32), 1, 4), ((8, 
          ((40, 12, 20), 26, 3), ((40, 12, 20), 52, 3), ((40, 12, 20), 86, 3), ((40, 12, 20), 130, 3),
          ((16, 16, 32), 1, 3),
          ((32, 32, 64), 1, 4), ((64, 64, 64), 1, 5), ((128, 128, 128), 1, 6),
-         ((16, 128, 128), 1, 4), ((256, 256, 256), 1, 7), ((8, 8, 16), 1, 3)]
+         ((16, 128, 128), 1, 4), ((256, 256, 256), 1, 7), ((8, 8, 16), 1, 3),
+         ((4, 4, 4), 1, 1), ((4, 4, 4), 1, 2), ((4, 8, 12), 1, 2)]
 
 
 @pytest.mark.parametrize("dims,batch,L", CASES)
