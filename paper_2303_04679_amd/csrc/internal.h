@@ -338,6 +338,8 @@ hipError_t launch_restrict_chain(modil_ctx *c, void *g, int from_level, const vo
 template <typename T>
 bool launch_restrict_march(const Levels &G, int l, T *g, const AdamArgs<T> &A, bool adam, int tile,
                            hipStream_t s);
+// whether launch_restrict_march would launch for this level (host only)
+bool restrict_march_applies(const Levels &G, int l, const void *g, size_t elem, int tile);
 // the same for node-based fields of one shape spanning every axis they have
 // (lanes over the flattened coarse plane); false when the level does not qualify
 template <typename T>

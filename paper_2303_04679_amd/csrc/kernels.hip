@@ -416,7 +416,10 @@ __device__ inline void tail_restrict_pass(const T *__restrict__ src, T *__restri
 // are stored there by their Adam update, the others (final before the
 // launch) are loaded there at the start.  Every read of global memory is
 // issued at the start: level l_lo of g, the carried theta and the Adam state
-// of every level produced.
+// of every level produced.  l_lo is l_big for fields f < nf_big and l_small
+// <= l_big for the others: small fields beside larger ones (the heat
+// problem's 1-D q beside its 2-D u) can start here at a finer level while
+// the marching kernel restricts the larger fields alone.
 template <typename T>
 struct CarryTail {
   T *w = nullptr;
@@ -431,7 +434,8 @@ __device__ inline int field_base(const Levels &G, int l, int inst, int f) {
 }
 
 template <typename T, bool ADAM>
-__global__ __launch_bounds__(kTailThreads) void restrict_tail_kernel(Levels G, int l_lo, int cap0, T *g,
+__global__ __launch_bounds__(kTailThreads) void restrict_tail_kernel(Levels G, int l_big, int l_small,
+                                                                     int nf_big, int cap0, T *g,
                                                                      AdamArgs<T> A, TermSum S,
                                                                      CarryTail<T> H) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -447,6 +451,7 @@ __global__ __launch_bounds__(kTailThreads) void restrict_tail_kernel(Levels G, i
   }
   const int part = blockIdx.x % H.parts, fi = blockIdx.x / H.parts;
   const int inst = fi / G.nf, f = fi % G.nf;
+  const int l_lo = f < nf_big ? l_big : l_small;
   const bool lead = part == 0;  // writes what the parts share
   const int bd = blockDim.x, tid = threadIdx.x;
   const bool carry = ADAM && H.w != nullptr;
@@ -1362,12 +1367,47 @@ static hipError_t restrict_t(modil_ctx *c, void *g_v, int from, const void *th_i
   int lt = c->tail_enabled
                ? tail_level(G, from, sizeof(T), c->lds_budget - 1024, kTailCapRestrict)
                : G.L - 1;
-  const int cap0 = lt + 1 < G.L ? (int)max_field(G, lt) : 0;
+  int cap0 = lt + 1 < G.L ? (int)max_field(G, lt) : 0;
+  // Fields past a leading group of one shape that are small enough to start
+  // the tail at level `from` (the heat problem's 1-D q beside its 2-D u):
+  // the marching kernel then restricts the leading group alone, levels
+  // from .. lt-1, where mixed shapes would take the per-cell kernel.  Taken
+  // only when the marching kernel applies at every one of those levels.
+  int nf_big = G.nf;
+  Levels Gb = G;
+  if (c->march_enabled && lt > from && lt + 1 < G.L) {
+    int k = 1;
+    while (k < G.nf && G.n[from][k][0] == G.n[from][0][0] && G.n[from][k][1] == G.n[from][0][1] &&
+           G.n[from][k][2] == G.n[from][0][2])
+      ++k;
+    bool ok = k < G.nf;
+    long cap_small = 0;
+    for (int f = k; ok && f < G.nf; ++f) {
+      long work = 0;
+      for (int j = from + 1; j < G.L; ++j) work += field_size(G, j, f);
+      cap_small = std::max(cap_small, field_size(G, from, f));
+      ok = work <= kTailCapRestrict;
+    }
+    Gb.nf = k;
+    for (int l = from; ok && l < lt; ++l) ok = restrict_march_applies(Gb, l, g, sizeof(T), c->march_tile);
+    if (ok) {
+      nf_big = k;
+      cap0 = (int)std::max<long>(cap0, cap_small);
+    }
+  }
   const size_t bytes = (size_t)2 * cap0 * sizeof(T);
   if (lt + 1 < G.L && !(ad ? lds_ready(restrict_tail_kernel<T, true>, bytes)
-                          : lds_ready(restrict_tail_kernel<T, false>, bytes)))
+                          : lds_ready(restrict_tail_kernel<T, false>, bytes))) {
     lt = G.L - 1;
+    nf_big = G.nf;
+  }
+  const int l_small = nf_big < G.nf ? from : lt;
   for (int l = from; l + 1 < G.L && l < lt; ++l) {
+    if (nf_big < G.nf) {
+      // checked above: applies at every level of the range
+      launch_restrict_march<T>(Gb, l, g, A, ad != nullptr, c->march_tile, c->stream);
+      continue;
+    }
     if (c->march_enabled &&
         launch_restrict_march<T>(G, l, g, A, ad != nullptr, c->march_tile, c->stream))
       continue;
@@ -1402,9 +1442,11 @@ static hipError_t restrict_t(modil_ctx *c, void *g_v, int from, const void *th_i
     }
     const int blocks = G.batch * G.nf * H.parts + (sum ? G.batch : 0);
     if (ad)
-      restrict_tail_kernel<T, true><<<blocks, kTailThreads, lds, c->stream>>>(G, lt, cap0, g, A, S, H);
+      restrict_tail_kernel<T, true><<<blocks, kTailThreads, lds, c->stream>>>(G, lt, l_small, nf_big, cap0,
+                                                                             g, A, S, H);
     else
-      restrict_tail_kernel<T, false><<<blocks, kTailThreads, lds, c->stream>>>(G, lt, cap0, g, A, S, H);
+      restrict_tail_kernel<T, false><<<blocks, kTailThreads, lds, c->stream>>>(G, lt, l_small, nf_big, cap0,
+                                                                              g, A, S, H);
     if (summed) *summed = sum != nullptr;
   }
   return hipGetLastError();

@@ -436,6 +436,13 @@ bool restrict_march_ok(const Levels &G, int l, const void *g, size_t elem, int r
   return true;
 }
 
+bool restrict_march_applies(const Levels &G, int l, const void *g, size_t elem, int tile) {
+  int YR, ZR;
+  bool spanz;
+  MarchPlan P{};
+  return restrict_march_ok(G, l, g, elem, tile, YR, ZR, spanz, P);
+}
+
 template <typename T, int YR, int ZR, bool ADAM>
 static void launch_march_yz(const Levels &G, int l, T *g, const AdamArgs<T> &A, const MarchPlan &P,
                             bool spanz, hipStream_t s) {
