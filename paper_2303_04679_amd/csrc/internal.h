@@ -215,6 +215,7 @@ struct modil_ctx {
   void *w_buf = nullptr;     // Horner intermediates, levels 0..L-2 (level 0 = fine u)
   void *g_buf = nullptr;     // gradient pack used by modil_step
   void *gq_buf = nullptr;    // per-cell contributions of 1-D fields (heat q)
+  int gq_rows = 0;           // rows in gq_buf: grid rows, or rows of tiles (their sums)
   void *sens_buf = nullptr;  // 3-D adjoint: face-slot sensitivities [6][nnb][batch][cells]
   void *cpart = nullptr;     // fused channel flow: level-1 gradient partials of every tile
   void *fine_tmp = nullptr;  // one fine-field array (scratch)

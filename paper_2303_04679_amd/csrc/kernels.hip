@@ -1113,12 +1113,24 @@ __global__ __launch_bounds__(NT) void fine_tile_kernel(FineArgs<T> A, int tiles_
       for (int f = 0; f < NF; ++f) {
         const T gf = gacc[f] + Dt[f][cy][cx];
         if (f == A.xonly_field) {
-          A.gq[(long)inst * A.ncell + c] = gf;
+          Dt[f][cy][cx] = gf;  // the cell's own slot, summed over the tile's rows below
         } else {
           const long k = (long)inst * A.ff.inst_stride + A.ff.off[f] + c;
           A.g[k] = gf;
           if (ADAM) adam_elem_loaded(A0, (int)k, gf, ath[f], am[f], av[f]);
         }
+      }
+    }
+    if (A.xonly_field >= 0) {
+      // the x-only field's contributions summed over the tile's rows in row
+      // order (rows past the grid hold zero): one row of gq per row of tiles,
+      // which the column-sum kernel adds up
+      __syncthreads();
+      if (tid < TX && x0 + tid < nx) {
+        T s = T(0);
+        for (int r = 0; r < TY; ++r) s += Dt[A.xonly_field][r][tid];
+        const int trow = blockIdx.x / tiles_x, trows = gridDim.x / tiles_x;
+        A.gq[((long)inst * trows + trow) * nx + x0 + tid] = s;
       }
     }
   }
@@ -1139,6 +1151,14 @@ __global__ __launch_bounds__(kColX * kColY) void colsum_kernel(const T *__restri
   __shared__ T sh[kColY][kColX];
   const int inst = blockIdx.y;
   const int ix = blockIdx.x * kColX + threadIdx.x;
+  const long e = (long)inst * inst_stride + foff + ix;
+  // the Adam state is loaded with the columns, so both latencies overlap
+  T th = T(0), m = T(0), v = T(0);
+  if (ADAM && threadIdx.y == 0 && ix < nx) {
+    th = A0.th_in[e];
+    m = A0.m[e];
+    v = A0.v[e];
+  }
   T acc = T(0);
   if (ix < nx) {
     const T *src = gq + (long)inst * nt * nx + ix;
@@ -1150,9 +1170,8 @@ __global__ __launch_bounds__(kColX * kColY) void colsum_kernel(const T *__restri
   if (threadIdx.y == 0 && ix < nx) {
     T s = T(0);
     for (int k = 0; k < kColY; ++k) s += sh[k][threadIdx.x];
-    const long e = (long)inst * inst_stride + foff + ix;
     g[e] = s;
-    if (ADAM) adam_elem(A0, (int)e, s);  // level 0 of the x-only field
+    if (ADAM) adam_elem_loaded(A0, (int)e, s, th, m, v);  // level 0 of the x-only field
   }
 }
 
@@ -1580,6 +1599,7 @@ static void launch_fine_tile(modil_ctx *c, const FineArgs<T> &A, const AdamArgs<
   int tx, ty, nbx, nby;
   fine_tile_shape(c->prob, tx, ty, nbx, nby);
   c->fine_slots = (long)nbx * nby;
+  c->gq_rows = nby;  // the x-only field's contributions come summed per row of tiles
   const TileMeas M{c->tm_ptr, c->tm_rec};
   const dim3 grid(nbx * nby, c->prob.batch);
   // residuals are formed on the tile plus a one-cell ring (34 x 10, 18 x 6
@@ -1616,6 +1636,7 @@ static hipError_t launch_fine_t(modil_ctx *c, const void *u, void *g, bool want_
   const dim3 grid(nblk(A.ncell), c->prob.batch);
   const modil_problem &P = c->prob;
   c->fine_slots = nblk(A.ncell);
+  c->gq_rows = P.dims[0];  // per-cell contributions (the tile launcher sets its own)
   if (fine_uses_tiles(c)) {
     switch (P.op) {
       case MODIL_OP_POISSON:
@@ -1685,7 +1706,7 @@ hipError_t launch_colsum(modil_ctx *c, void *g_fine, const AdamHost *adam, const
   for (int f = 0; f < c->lay.n_fields; ++f)
     if (field_is_x_only(c->prob, f)) xf = f;
   if (xf < 0) return hipSuccess;
-  const int nt = c->prob.dims[0], nx = c->prob.dims[1];
+  const int nt = c->gq_rows, nx = c->prob.dims[1];
   const dim3 grid((nx + kColX - 1) / kColX, c->prob.batch), block(kColX, kColY);
   const long st = c->lay.level_stride[0], fo = c->lay.field_offset[0][xf];
   if (c->prob.dtype == MODIL_F64) {
