@@ -456,13 +456,9 @@ int evaluate(modil_ctx *c, const void *theta, void *grad, double *terms, const A
     if (want) {
       bool xonly = false;
       for (int f = 0; f < c->lay.n_fields; ++f) xonly |= field_is_x_only(c->prob, f);
-      if (xonly) {
-        Timed t(c, 4);
-        HIP_OR_RETURN(c, launch_colsum(c, grad, adam, theta, th_out, m, v), "column sum");
-      }
       Timed t(c, 2);
       HIP_OR_RETURN(c, launch_restrict_chain(c, grad, 0, theta, th_out, m, v, adam, &sum, &summed,
-                                             carry_out, carried),
+                                             carry_out, carried, xonly),
                     "restrict");
     }
     if (!summed) {

@@ -328,11 +328,14 @@ struct TermSum {
 };
 // Restriction of the gradient from level from_level down, with Adam on every
 // level produced when adam is given.  With sum given, the chain's last kernel
-// also does that sum when it can (summed tells whether it did).
+// also does that sum when it can (summed tells whether it did).  With colsum,
+// the x-only field's column sums of the tile kernel's contributions (and its
+// level-0 Adam) come first: in the restriction tail where it can, else by
+// launch_colsum.
 hipError_t launch_restrict_chain(modil_ctx *c, void *g, int from_level, const void *th_in,
                                  void *th_out, void *m, void *v, const AdamHost *adam,
                                  const TermSum *sum = nullptr, bool *summed = nullptr,
-                                 bool carry = false, bool *carried = nullptr);
+                                 bool carry = false, bool *carried = nullptr, bool colsum = false);
 // Marching restriction of level l -> l+1 with optional Adam (restrict_march.hip);
 // returns false, launching nothing, when the level's shape does not admit it.
 // tile: 64 * rows + planes per wave, 0 = automatic.

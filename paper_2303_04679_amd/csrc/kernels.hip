@@ -420,6 +420,17 @@ __device__ inline void tail_restrict_pass(const T *__restrict__ src, T *__restri
 // <= l_big for the others: small fields beside larger ones (the heat
 // problem's 1-D q beside its 2-D u) can start here at a finer level while
 // the marching kernel restricts the larger fields alone.
+// With gq set, the block of field f (which starts at level 0) first forms
+// that field's level-0 gradient from gq, the tile rows' sums of its per-cell
+// contributions (rows x cells per instance), adding the rows in order, and
+// applies Adam to level 0 (the x-only field of the heat problem, whose
+// column sums would otherwise take a launch of their own).
+template <typename T>
+struct ColFold {
+  const T *gq = nullptr;
+  int rows = 0, f = -1;
+};
+
 template <typename T>
 struct CarryTail {
   T *w = nullptr;
@@ -437,7 +448,7 @@ template <typename T, bool ADAM>
 __global__ __launch_bounds__(kTailThreads) void restrict_tail_kernel(Levels G, int l_big, int l_small,
                                                                      int nf_big, int cap0, T *g,
                                                                      AdamArgs<T> A, TermSum S,
-                                                                     CarryTail<T> H) {
+                                                                     CarryTail<T> H, ColFold<T> Q) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *const sm = reinterpret_cast<T *>(smem_raw);
   // blocks past the (instance, field) ones sum the loss partials of an
@@ -492,8 +503,26 @@ __global__ __launch_bounds__(kTailThreads) void restrict_tail_kernel(Levels G, i
       e -= n;
     }
   }
-  // level l_lo of g, and the theta of the carried levels l_stop .. l_lo
-  tail_copy_in(sm, g + field_base(G, l_lo, inst, f), 0, field_cells(G, l_lo, f));
+  // level l_lo of g (or its column sums), and the theta of the carried
+  // levels l_stop .. l_lo
+  const bool fold = Q.gq != nullptr && f == Q.f;
+  const int n0 = fold ? field_cells(G, 0, f) : 0, base0 = field_base(G, 0, inst, f);
+  T s0 = T(0), th0 = T(0), m0 = T(0), v0 = T(0);
+  if (fold) {
+    if (tid < n0) {
+      if (ADAM) {
+        th0 = A.th_in[base0 + tid];
+        m0 = A.m[base0 + tid];
+        v0 = A.v[base0 + tid];
+      }
+      const T *src = Q.gq + (long)inst * Q.rows * n0 + tid;
+#pragma unroll 8
+      for (int r = 0; r < Q.rows; ++r) s0 += src[(long)r * n0];
+      sm[tid] = s0;
+    }
+  } else {
+    tail_copy_in(sm, g + field_base(G, l_lo, inst, f), 0, field_cells(G, l_lo, f));
+  }
   const int slice = h_hi - h_lo;
   int toff = 0;  // offset in tl of the next level
   if (carry)
@@ -512,6 +541,10 @@ __global__ __launch_bounds__(kTailThreads) void restrict_tail_kernel(Levels G, i
   // every load above has returned (vmcnt 0; the other counters left at their
   // maximum), so no wait inside the level loop includes the stores it issues
   __builtin_amdgcn_s_waitcnt(0x0F70);
+  if (fold && lead && tid < n0) {
+    g[base0 + tid] = s0;
+    if (ADAM) adam_elem_loaded(A, base0 + tid, s0, th0, m0, v0);
+  }
   T *cur = sm, *oth = sm + cap0;
   int cat = 0;  // offset of level l + 1 in the concatenation
   for (int l = l_lo; l + 1 < G.L; ++l) {
@@ -1371,7 +1404,7 @@ hipError_t launch_horner(modil_ctx *c, const void *theta, void *fine_dst, bool s
 template <typename T>
 static hipError_t restrict_t(modil_ctx *c, void *g_v, int from, const void *th_in, void *th_out,
                              void *m, void *v, const AdamHost *ad, const TermSum *sum,
-                             bool *summed, bool carry, bool *carried) {
+                             bool *summed, bool carry, bool *carried, bool colsum) {
   if (summed) *summed = false;
   if (carried) *carried = false;
   const Levels G = levels_of(c);
@@ -1421,6 +1454,24 @@ static hipError_t restrict_t(modil_ctx *c, void *g_v, int from, const void *th_i
     nf_big = G.nf;
   }
   const int l_small = nf_big < G.nf ? from : lt;
+  // the x-only field's column sums (and its level-0 Adam): in the tail when
+  // that field starts there at level 0, else by their own launch first
+  ColFold<T> Q;
+  if (colsum) {
+    int xf = -1;
+    for (int f = 0; f < G.nf; ++f)
+      if (field_is_x_only(c->prob, f)) xf = f;
+    const int start = xf >= nf_big ? l_small : lt;
+    if (xf >= 0 && from == 0 && start == 0 && lt + 1 < G.L && field_size(G, 0, xf) <= kTailThreads &&
+        field_size(G, 0, xf) <= cap0) {
+      Q.gq = (const T *)c->gq_buf;
+      Q.rows = c->gq_rows;
+      Q.f = xf;
+    } else {
+      const hipError_t e = launch_colsum(c, g_v, ad, th_in, th_out, m, v);
+      if (e != hipSuccess) return e;
+    }
+  }
   for (int l = from; l + 1 < G.L && l < lt; ++l) {
     if (nf_big < G.nf) {
       // checked above: applies at every level of the range
@@ -1462,10 +1513,10 @@ static hipError_t restrict_t(modil_ctx *c, void *g_v, int from, const void *th_i
     const int blocks = G.batch * G.nf * H.parts + (sum ? G.batch : 0);
     if (ad)
       restrict_tail_kernel<T, true><<<blocks, kTailThreads, lds, c->stream>>>(G, lt, l_small, nf_big, cap0,
-                                                                             g, A, S, H);
+                                                                             g, A, S, H, Q);
     else
       restrict_tail_kernel<T, false><<<blocks, kTailThreads, lds, c->stream>>>(G, lt, l_small, nf_big, cap0,
-                                                                              g, A, S, H);
+                                                                              g, A, S, H, Q);
     if (summed) *summed = sum != nullptr;
   }
   return hipGetLastError();
@@ -1473,10 +1524,10 @@ static hipError_t restrict_t(modil_ctx *c, void *g_v, int from, const void *th_i
 
 hipError_t launch_restrict_chain(modil_ctx *c, void *g, int from, const void *th_in, void *th_out,
                                  void *m, void *v, const AdamHost *adam, const TermSum *sum,
-                                 bool *summed, bool carry, bool *carried) {
+                                 bool *summed, bool carry, bool *carried, bool colsum) {
   return c->prob.dtype == MODIL_F64
-             ? restrict_t<double>(c, g, from, th_in, th_out, m, v, adam, sum, summed, carry, carried)
-             : restrict_t<float>(c, g, from, th_in, th_out, m, v, adam, sum, summed, carry, carried);
+             ? restrict_t<double>(c, g, from, th_in, th_out, m, v, adam, sum, summed, carry, carried, colsum)
+             : restrict_t<float>(c, g, from, th_in, th_out, m, v, adam, sum, summed, carry, carried, colsum);
 }
 
 hipError_t launch_adam(modil_ctx *c, const void *th_in, void *th_out, void *m, void *v,

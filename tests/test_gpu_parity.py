@@ -29,6 +29,7 @@ CASES = [
     ("heat", (64, 32), 4),
     ("heat", (40, 72), 3),
     ("heat", (128, 64), 4),
+    ("heat", (96, 96), 3),
     ("ns3d", (16, 16, 24), 3),
     ("ns3d_fixed", (8, 16, 24), 3),
     ("cavity", (32, 48), 4),
@@ -127,14 +128,15 @@ def test_adam(dtype):
                                        ("ns3d", (8, 8, 16), 3), ("cavity", (32, 32), 4),
                                        ("poisson_node", (32, 32), 4), ("cavity_node", (32, 32), 4),
                                        ("ns3d_node", (8, 8, 16), 3), ("ns3d", (32, 32, 64), 4),
-                                       ("heat", (128, 64), 4)])
+                                       ("heat", (128, 64), 4), ("heat", (96, 96), 3)])
 def test_step_sequence_f64(op, dims, L):
     """Three modil_step calls (ping-pong theta) follow the oracle's loss, gradient and Adam.
     The 32 x 32 x 64 channel starts its restriction tail at a level of 8192
     cells (copied into LDS in rounds of eight loads per thread) and updates
     three levels there.  On the 128 x 64 heat grid the marching kernel
     restricts u alone from the finest level while the tail takes the 1-D q
-    from the finest level on."""
+    from the finest level on, its column sums included; on the 96 x 96 grid
+    the tail starts at level 1 and the column sums take their own launch."""
     need_gpu()
     spec = case(op, dims, L, seed=3)
     lv = _levels(spec, 4)
