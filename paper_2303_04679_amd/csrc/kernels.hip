@@ -6,7 +6,7 @@
 //                   g(c) = sum_o s_o(c - o) of every equation whose stencil
 //                   touches c (Section 2.1 loss, adjoint by hand)
 //   data_kernel     measurement misfits and their adjoint
-//   colsum_kernel   sums the per-cell contributions of a field that spans x only
+//   colsum_kernel   column sums of the contributions of a field that spans x only
 //   reduce_kernel   fixed-order reduction of the FP64 partials per instance
 //   adam_kernel     elementwise Adam over a pack
 //
@@ -1157,7 +1157,7 @@ __global__ __launch_bounds__(NT) void fine_tile_kernel(FineArgs<T> A, int tiles_
     if (A.xonly_field >= 0) {
       // the x-only field's contributions summed over the tile's rows in row
       // order (rows past the grid hold zero): one row of gq per row of tiles,
-      // which the column-sum kernel adds up
+      // which the restriction tail (or the column-sum kernel) adds up
       __syncthreads();
       if (tid < TX && x0 + tid < nx) {
         T s = T(0);
@@ -1170,8 +1170,8 @@ __global__ __launch_bounds__(NT) void fine_tile_kernel(FineArgs<T> A, int tiles_
   block_terms_n<NT>(part, A.partials + ((long)inst * A.n_part_blocks + blockIdx.x) * kTerms);
 }
 
-// column sums of the x-only field's per-cell contributions (rows = t)
-// Column sums of the per-cell contributions of the x-only field: a block
+// Column sums of the x-only field's contributions, nt rows of nx (the grid's
+// rows of cells, or the tile kernel's sums over each row of tiles): a block
 // takes 64 columns of one instance; 16 row groups sum every 16th row, then the
 // group sums are added in group order (fixed order: deterministic).
 constexpr int kColX = 64, kColY = 16;
